@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""FP64 randUTV throughput on one MI355X.
+
+One step = one full randUTV factorization A = U T V^T (U and V built) of the
+12000 x 12000 matrix A = P diag(0.99^i) Q^T (P, Q Haar), block size b = 256,
+q = 2 power steps, sketch seed 0 -- every block step of the method (sketch,
+power iteration, QR of the sketch, right transform of all rows and of V, panel
+QR, left transform, U update, b x b SVDs and their applications) runs inside
+the timed region; A, U, T, V are resident in HBM before it starts.
+
+value = F_std / t in TFLOP/s, with the leading-order count
+F_std = (1+2q)(m n^2 - n^3/3) + 2 m n^2 + 4/3 n^3 + 4 m^2 n  (1.843e13 here).
+The roofline entry is the dominant kernel class (most device time), its
+achieved FP64 rate from HIP events recorded on its launching stream during the
+timed steps, against the FP64 matrix-core peak (78.6 TFLOP/s).  cpu_baseline
+times the FP64 CPU oracle on the first block steps of the same problem.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m", type=int, default=12000)
+    ap.add_argument("--n", type=int, default=12000)
+    ap.add_argument("--b", type=int, default=256)
+    ap.add_argument("--q", type=int, default=2)
+    ap.add_argument("--spectrum", default="exp")
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="block steps of the same problem timed for the CPU oracle baseline (0: skip)")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    return ap.parse_args()
+
+
+def traffic_entry(kernel: str):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary, if one exists for the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        import hashlib
+
+        with open(path) as f:
+            rec = json.load(f)
+        src = os.path.join(ROOT, "paper_2002_06960_amd", "csrc", rec["source"])
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if digest != rec["sha256"] or rec.get("kernel") != kernel:
+            return None
+        return rec["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
+                                   "not part of this build (--gpus 1)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2002_06960_amd as pkg
+    from randutv_inputs import make_matrix_device
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    pkg.load()  # fails loudly without the HIP library
+    m, n, b, q = args.m, args.n, args.b, args.q
+    dev = "cuda:0"
+    A = make_matrix_device(args.spectrum, m, n, seed=0, device=dev)
+    U = pkg.colmajor_empty(m, m, dev)
+    T = pkg.colmajor_empty(m, n, dev)
+    V = pkg.colmajor_empty(n, n, dev)
+    torch.cuda.synchronize()
+    print(f"# workload randutv fp64 {m}x{n} b={b} q={q} spectrum={args.spectrum}", file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        pkg.randutv_factor(A, b, q, 0, U=U, T=T, V=V)
+        torch.cuda.synchronize()
+        print(f"# warmup {w}: {time.perf_counter() - t0:.3f} s", file=sys.stderr, flush=True)
+
+    timing = not args.no_kernel_timing
+    pkg.randutv_set_timing(timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        pkg.randutv_factor(A, b, q, 0, U=U, T=T, V=V)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = pkg.randutv_kernel_stats() if timing else {}
+    pkg.randutv_set_timing(False)
+    ms_step = 1e3 * elapsed / max(args.steps, 1)
+    print(f"# timed {args.steps} steps: {ms_step:.2f} ms/step", file=sys.stderr, flush=True)
+
+    F = pkg.flops_std(m, n, q)
+    value = F / (ms_step * 1e-3) / 1e12
+
+    # correctness of the timed output
+    nA = torch.linalg.norm(A)
+    res = (torch.linalg.norm(A - U @ T @ V.T) / nA).item()
+    eye_m = torch.eye(m, dtype=torch.float64, device=dev)
+    orth_u = (U.T @ U - eye_m).abs().max().item()
+    del eye_m
+    eye_n = torch.eye(n, dtype=torch.float64, device=dev)
+    orth_v = (V.T @ V - eye_n).abs().max().item()
+    del eye_n
+
+    roofline = None
+    kern = {}
+    if stats:
+        for name, (launches, ms, fl) in stats.items():
+            if launches:
+                kern[name] = {"launches": launches // max(args.steps, 1), "ms_per_step": ms / args.steps,
+                              "tflops": (fl / (ms * 1e-3) / 1e12) if ms > 0 and fl > 0 else None}
+        dom = max((k for k in stats if stats[k][0]), key=lambda k: stats[k][1])
+        launches, ms, fl = stats[dom]
+        achieved = fl / (ms * 1e-3) / 1e12
+        tb = traffic_entry(dom)
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
+                    "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                    "traffic": tb, "avg_launch_ms": ms / launches, "launches": launches}
+        print("# kernel classes (ms/step, launches/step, TFLOP/s):", file=sys.stderr)
+        for name, kv in sorted(kern.items(), key=lambda x: -x[1]["ms_per_step"]):
+            print(f"#   {name:20s} {kv['ms_per_step']:9.3f} {kv['launches']:6d} {kv['tflops']}",
+                  file=sys.stderr)
+
+    cpu = None
+    if args.cpu_steps > 0:
+        from oracle import randutv_oracle as ro
+
+        Ah = A.cpu().numpy()
+        threads = os.cpu_count()
+        t0 = time.perf_counter()
+        ro.randutv(Ah, b, q, 0, max_steps=args.cpu_steps)
+        tc = time.perf_counter() - t0
+        fe = ro.flops_exact(m, n, b, q, max_steps=args.cpu_steps)
+        scale = F / ro.flops_exact(m, n, b, q)  # express in F_std units
+        cpu = {"value": round(fe * scale / tc / 1e12, 5), "unit": "TFLOP/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"first {args.cpu_steps} of {-(-n // b)} block steps of the same "
+                         f"{m}x{n} b={b} q={q} factorization (U, V built), {tc:.1f} s"}
+        print(f"# cpu oracle: {tc:.1f} s for {args.cpu_steps} steps", file=sys.stderr)
+
+    out = {
+        "metric": "randUTV TFLOP/s (FP64, standard flop count) at n=12000",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"randutv_fp64_{m}x{n}_b{b}_q{q}_{args.spectrum}",
+                   "m": m, "n": n, "b": b, "q": q, "spectrum": args.spectrum, "build_uv": True,
+                   "parallelism": "single-gpu"},
+        "frac_of_fp64_peak": round(value / PEAK_FP64_TFLOPS, 4),
+        "residual": res,
+        "orth_u": orth_u,
+        "orth_v": orth_v,
+        "flops_std": F,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kern,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,145 @@
+/*
+ * randutv.h -- C ABI of the MI355X (gfx950) randUTV library.
+ *
+ * Rank-revealing UTV factorization A = U T V^T (Heavner, Martinsson &
+ * Quintana-Orti, arXiv 2002.06960, Section 1.1 eq. (1) and Section 3.1):
+ * U (m x m) and V (n x n) orthogonal, T (m x n) upper triangular, computed by
+ * the blocked randomized algorithm of Section 3.1 / Figure 2 (sketch with
+ * power iteration, Householder QR of the sketch, right transform of all rows,
+ * panel Householder QR, left transform, SVD of each diagonal b x b block).
+ *
+ * Conventions shared by every entry point:
+ *   - real FP64, column-major storage;
+ *   - every matrix/vector pointer is a DEVICE (HBM) pointer owned by the
+ *     caller, unless the comment says "host";
+ *   - calls run on the library's own HIP streams on the current device and
+ *     return after the device work has finished (synchronous), unless noted;
+ *   - return value: 0 on success; -k when the k-th argument is invalid
+ *     (LAPACK style); RANDUTV_ERR_* (> 0) for run-time failures.  Outputs are
+ *     undefined on a non-zero return.
+ */
+#ifndef RANDUTV_H
+#define RANDUTV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RANDUTV_OK 0
+#define RANDUTV_ERR_HIP 1          /* HIP runtime error or no usable device */
+#define RANDUTV_ERR_NOMEM 2        /* device workspace allocation failed */
+#define RANDUTV_ERR_NONFINITE 3    /* A holds NaN or Inf */
+#define RANDUTV_ERR_NOCONV 4       /* a b x b Jacobi SVD exceeded its sweep cap */
+#define RANDUTV_ERR_SYNC 5         /* a multi-workgroup kernel's bounded wait expired */
+#define RANDUTV_ERR_TOO_LARGE 6    /* a dimension exceeds a documented kernel limit */
+
+/*
+ * randutv_factor -- A = U T V^T (Section 3.1, Figure 2).
+ *   m, n    : rows and columns, m >= n >= 0 (the paper assumes m >= n).
+ *   A, lda  : input m x n, lda >= max(1, m).  Read only, unless T == A.
+ *   b       : block size, b >= 1 (clamped to n).  Kernel limit b <= 256.
+ *   q       : power-iteration count, q >= 0 (Y = (B^T B)^q B^T G per step).
+ *   seed    : key of the sketch stream: step i draws G(i), (m - i b) x b_i,
+ *             i.i.d. N(0,1) from Philox4x64-10 keyed (seed, i), block k at
+ *             counter (k, 0, 0, 0), four normals per block by Box-Muller,
+ *             column-major fill (see randutv_sketch).
+ *   U       : m x m output, ld = m; or NULL to skip building U.
+ *   T       : m x n output, ld = m; may alias A when lda == m.
+ *   V       : n x n output, ld = n; or NULL to skip building V.
+ * Each diagonal b x b block of T is diagonal with non-negative, descending
+ * entries (the singular values of that block's triangular factor).
+ * m == 0 or n == 0 returns 0 without touching memory.
+ * Errors: -1 m, -2 n (n < 0 or n > m), -3 A NULL, -4 lda, -5 b, -6 q,
+ * -8 U aliases T or V, -9 T NULL (or T == A with lda != m), -10 V aliases T,
+ * RANDUTV_ERR_TOO_LARGE for min(b, n) > 256, RANDUTV_ERR_* at run time.
+ */
+int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda,
+                   int64_t b, int32_t q, uint64_t seed,
+                   double* U, double* T, double* V);
+
+/*
+ * randutv_truncate -- rank-k truncation A_k = U(:, 0:k) T(0:k, :) V^T
+ * (Section 1.1).  U m x m (ld m), T m x n (ld m), V n x n (ld n), Ak m x n
+ * (ld m), all device pointers from a previous randutv_factor.
+ * 0 <= k <= n; k == 0 writes zeros.  Errors: -1 m, -2 n, -3 k, -4 U, -5 T,
+ * -6 V, -7 Ak.
+ */
+int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U,
+                     const double* T, const double* V, double* Ak);
+
+/*
+ * randutv_sketch -- write the sketch G(step) (rows x cols, ld = ldg) that
+ * randutv_factor draws at that step (Section 3.1, "draw a random matrix with
+ * i.i.d. standard normal entries"; generator as described at randutv_factor).
+ * Element (r, c) is normal number r + c*rows of the (seed, step) stream.
+ * Errors: -3 rows, -4 cols, -5 G, -6 ldg.
+ */
+int randutv_sketch(uint64_t seed, uint64_t step, int64_t rows, int64_t cols,
+                   double* G, int64_t ldg);
+
+/*
+ * Building blocks of the step loop, exported for per-kernel checks.
+ */
+
+/* C = alpha op(A) op(B) + beta C with op(X) = X (trans 'N') or X^T ('T');
+ * op(A) M x K, op(B) K x N, C M x N.  FP64 MFMA kernels.  C must not overlap
+ * A or B.  Errors: -1 transa, -2 transb, -3 M, -4 N, -5 K, -8 lda, -10 ldb,
+ * -13 ldc. */
+int randutv_dgemm(char transa, char transb, int64_t M, int64_t N, int64_t K,
+                  double alpha, const double* A, int64_t lda, const double* B,
+                  int64_t ldb, double beta, double* C, int64_t ldc);
+
+/* Householder QR of the m x k matrix A (m >= k, k <= 256) in place, LAPACK
+ * dgeqr2 conventions (Figure 2's "unpivoted QR"): on return R is in the upper
+ * triangle, reflector vectors (v(0) = 1 implied) below it, tau (k) holds the
+ * scalars: A_in = H_0 ... H_{k-1} [R; 0], H_j = I - tau_j v_j v_j^T.
+ * Errors: -1 m, -2 k, -3 A, -4 lda, -5 tau. */
+int randutv_geqrf(int64_t m, int64_t k, double* A, int64_t lda, double* tau);
+
+/* Forward column-wise compact-WY factor (LAPACK dlarft): from the reflectors
+ * stored below the diagonal of W (m x k, ld ldw; diagonal and upper part are
+ * ignored and read as 1 and 0) and tau, write the k x k upper triangular Tf
+ * (ld ldt) with H_0 ... H_{k-1} = I - W Tf W^T (Figure 2's T_V, T_U).
+ * Errors: -1 m, -2 k, -3 W, -4 ldw, -5 tau, -6 Tf, -7 ldt. */
+int randutv_larft(int64_t m, int64_t k, const double* W, int64_t ldw,
+                  const double* tau, double* Tf, int64_t ldt);
+
+/* SVD of the k x k matrix R (k <= 256, ld ldr) by one-sided Jacobi
+ * (Figure 2's "SVD(A_11)"): R = Us diag(d) Vs^T, d >= 0 descending (ties keep
+ * column order), Us/Vs k x k (ld k); each (u_j, v_j) is signed so that the
+ * largest-magnitude entry of v_j (lowest index on ties) is positive; u_j is
+ * completed by Gram-Schmidt over e_1, e_2, ... where d_j == 0.  *sweeps
+ * (host pointer, may be NULL) receives the sweep count.  Errors: -1 k, -2 R,
+ * -3 ldr, -4 d, -5 Us, -6 Vs, RANDUTV_ERR_NOCONV after 30 sweeps. */
+int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d,
+                  double* Us, double* Vs, int32_t* sweeps);
+
+/* Per-kernel timing.  randutv_set_timing(1) clears the counters and makes
+ * every later randutv_factor call record a HIP event pair around each kernel
+ * launch on the stream it is launched on; randutv_set_timing(0) stops it.
+ * randutv_kernel_stats writes, per kernel class, the number of launches, the
+ * summed device time in ms and the algorithmic FP64 flops accumulated since
+ * timing was enabled.  Returns the number of classes written (at most cap);
+ * names: host array of cap pointers to static strings. */
+int randutv_set_timing(int32_t enable);
+int randutv_kernel_stats(int32_t cap, const char** names, int64_t* launches,
+                         double* ms, double* flops);
+
+/* Jacobi sweep counts of each step of the last randutv_factor call (host
+ * array of cap entries); returns the number of steps. */
+int randutv_last_sweeps(int32_t cap, int32_t* sweeps);
+
+/* Text of the last HIP runtime error met by the calling thread inside the
+ * library ("" if none), for diagnosing RANDUTV_ERR_HIP / RANDUTV_ERR_NOMEM. */
+const char* randutv_last_hip_error(void);
+
+/* Human-readable text for a return code (static storage). */
+const char* randutv_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RANDUTV_H */

@@ -252,12 +252,14 @@ def jacobi_svd(R: np.ndarray, max_sweeps: int = JACOBI_MAX_SWEEPS):
 # randUTV (Section 3.1; Figure 2 with readings R1-R10)
 # ----------------------------------------------------------------------------
 def randutv(A: np.ndarray, b: int, q: int, seed: int = 0, build_u: bool = True,
-            build_v: bool = True, return_info: bool = False):
+            build_v: bool = True, return_info: bool = False, max_steps: int | None = None):
     """Blocked randUTV: A = U T V^T with U, V orthogonal and T upper triangular.
 
     A: m x n FP64 with m >= n; b: block size (clamped to n); q: power steps.
     Returns (U, T, V) (U or V None when not built) and optionally an info dict
-    with per-step Jacobi sweep counts.
+    with per-step Jacobi sweep counts.  max_steps stops after that many block
+    steps (a partial factorization, still A = U T V^T; used to time a bounded
+    sample of a large problem).
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
@@ -270,7 +272,7 @@ def randutv(A: np.ndarray, b: int, q: int, seed: int = 0, build_u: bool = True,
     V = np.eye(n, order="F") if build_v else None
     sweeps = []
     s, i = 0, 0
-    while s < n:
+    while s < n and (max_steps is None or i < max_steps):
         bi = min(b, n - s)
         e = s + bi
         # --- right transform: V^ from the powered sketch (Section 3.1)
@@ -333,13 +335,16 @@ def flops_std(m: int, n: int, q: int, build_u: bool = True, build_v: bool = True
     return f
 
 
-def flops_exact(m: int, n: int, b: int, q: int, build_u: bool = True, build_v: bool = True) -> float:
+def flops_exact(m: int, n: int, b: int, q: int, build_u: bool = True, build_v: bool = True,
+                max_steps: int | None = None) -> float:
     """Exact product count of the step list as computed here (GEMM-shaped work
     2*M*N*K per product, Householder QR 2 r c^2 - 2 c^3/3, T factor r c^2,
     small SVD applies).  Jacobi rotations are not counted."""
     f = 0.0
     s = 0
-    while s < n:
+    steps = 0
+    while s < n and (max_steps is None or steps < max_steps):
+        steps += 1
         bi = min(b, n - s)
         mi, ni = m - s, n - s
         f += 2.0 * mi * ni * bi * (1 + 2 * q)          # sketch + power products

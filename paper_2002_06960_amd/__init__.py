@@ -1,0 +1,35 @@
+"""randUTV (A = U T V^T) for one AMD Instinct MI355X (gfx950).
+
+The factorization runs in hand-written HIP kernels behind a C ABI
+(include/randutv.h, librandutv.so); this package is the thin Python binding.
+"""
+from .randutv import (  # noqa: F401
+    RandUTVError,
+    as_colmajor,
+    colmajor_empty,
+    load,
+    randutv_dgemm,
+    randutv_factor,
+    randutv_geqrf,
+    randutv_gesvj,
+    randutv_kernel_stats,
+    randutv_larft,
+    randutv_last_sweeps,
+    randutv_set_timing,
+    randutv_sketch,
+    randutv_strerror,
+    randutv_truncate,
+)
+
+
+def flops_std(m: int, n: int, q: int, build_u: bool = True, build_v: bool = True) -> float:
+    """Leading-order flop count of randUTV used to express throughput:
+    (1+2q)(m n^2 - n^3/3) + 2 m n^2 + (2 m n^2 - 2n^3/3) [+ 2 n^3 for V]
+    [+ 4 m^2 n - 2 m n^2 for U]."""
+    m, n = float(m), float(n)
+    f = (1 + 2 * q) * (m * n * n - n ** 3 / 3.0) + 4 * m * n * n - 2 * n ** 3 / 3.0
+    if build_v:
+        f += 2 * n ** 3
+    if build_u:
+        f += 4 * m * m * n - 2 * m * n * n
+    return f

@@ -1,0 +1,272 @@
+// FP64 GEMM on the CDNA4 matrix cores: C = alpha op(A) op(B) + beta C.
+//
+// Every product of the randUTV step loop (sketch, power iteration, the X = A W
+// products of the compact-WY updates and the rank-b updates A -= X Z^T) goes
+// through this kernel.  Tiles of BM x BN are staged through LDS in BK-deep
+// slices (double buffered, next slice prefetched into registers while the
+// current one feeds the matrix cores).  Four waves per workgroup each own a
+// (BM/2) x (BN/2) sub-tile built from 16x16 blocks of v_mfma_f64_16x16x4.
+//
+// The MFMA is issued with the operands swapped (op(B)^T block as the 16x4
+// operand, op(A)^T block as the 4x16 operand) so that the 16 lanes of a lane
+// group hold 16 consecutive rows of one C column; a store instruction then
+// covers 4 columns x 16 consecutive rows, i.e. full 128-byte segments of
+// column-major C.
+//
+// Skinny products (an n x b output with K in the thousands) split K over
+// blockIdx.y; each split writes alpha * partial to a buffer and a second
+// kernel sums the splits in a fixed order (deterministic).
+#include "kernels.hpp"
+
+namespace rutv {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGemmThreads = 256;
+
+template <bool TA, bool TB, int BM, int BN, int BK>
+__global__ __launch_bounds__(kGemmThreads, 2) void dgemm_mfma_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, i64 lda,
+    const double* __restrict__ B, i64 ldb, double beta, double* __restrict__ C, i64 ldc,
+    int kchunk, double* __restrict__ part, int tilesM, int ntiles) {
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int MI = WM / 16, NJ = WN / 16;
+  constexpr int LDAS = BM + 1, LDBS = BN + 1;  // +1 double: conflict-free transposing stores
+  constexpr int AE = BM * BK / kGemmThreads, BE = BN * BK / kGemmThreads;
+  static_assert(AE * kGemmThreads == BM * BK && BE * kGemmThreads == BN * BK, "tile/threads");
+  __shared__ double As[2][BK * LDAS];
+  __shared__ double Bs[2][BK * LDBS];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave & 1) * WM, wn0 = (wave >> 1) * WN;
+
+  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+  // give each XCD a contiguous run of tiles (column-major over the tile grid,
+  // neighbours share the op(B) panel) when the count divides evenly.
+  int bid = blockIdx.x;
+  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  const int m0 = (bid % tilesM) * BM, n0 = (bid / tilesM) * BN;
+  const int kz = blockIdx.y;
+  const int kbeg = kz * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+
+  double ra[AE], rb[BE];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < AE; ++r) {
+      const int e = tid + kGemmThreads * r;
+      const int mm = TA ? e / BK : e % BM;
+      const int kk = TA ? e % BK : e / BM;
+      const int gm = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gm < M && gk < kend) v = TA ? A[(i64)gk + (i64)gm * lda] : A[(i64)gm + (i64)gk * lda];
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < BE; ++r) {
+      const int e = tid + kGemmThreads * r;
+      const int nn = TB ? e % BN : e / BK;
+      const int kk = TB ? e / BN : e % BK;
+      const int gn = n0 + nn, gk = k0 + kk;
+      double v = 0.0;
+      if (gn < N && gk < kend) v = TB ? B[(i64)gn + (i64)gk * ldb] : B[(i64)gk + (i64)gn * ldb];
+      rb[r] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < AE; ++r) {
+      const int e = tid + kGemmThreads * r;
+      const int mm = TA ? e / BK : e % BM;
+      const int kk = TA ? e % BK : e / BM;
+      As[buf][kk * LDAS + mm] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < BE; ++r) {
+      const int e = tid + kGemmThreads * r;
+      const int nn = TB ? e % BN : e / BK;
+      const int kk = TB ? e / BN : e % BK;
+      Bs[buf][kk * LDBS + nn] = rb[r];
+    }
+  };
+
+  dbl4 acc[MI][NJ];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+      const int cur = t & 1;
+      if (t + 1 < nk) gload(kbeg + (t + 1) * BK);
+      const double* as = As[cur];
+      const double* bs = Bs[cur];
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + (lane >> 4), cl = lane & 15;
+        double af[MI], bf[NJ];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) af[i] = as[kr * LDAS + wm0 + 16 * i + cl];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) bf[j] = bs[kr * LDBS + wn0 + 16 * j + cl];
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);
+      }
+      if (t + 1 < nk) sstore(cur ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // v_mfma_f64_16x16x4 leaves D(4r + lane/16, lane%16) in register r; with the
+  // swapped operands D is the transposed C block, so the lane holds
+  // C[m0+wm0+16i+(lane&15)][n0+wn0+16j+4r+(lane>>4)], r = 0..3
+  const int cm = lane & 15, cn = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+    const int gm = m0 + wm0 + 16 * i + cm;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gn = n0 + wn0 + 16 * j + 4 * r + cn;
+        if (gn >= N) continue;
+        double v = alpha * acc[i][j][r];
+        if (part) {
+          part[(i64)kz * M * N + gm + (i64)gn * M] = v;
+        } else {
+          double* c = C + gm + (i64)gn * ldc;
+          if (beta != 0.0) v += beta * *c;
+          *c = v;
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(int M, int N, int S,
+                                                            const double* __restrict__ part,
+                                                            double beta, double* __restrict__ C,
+                                                            i64 ldc) {
+  const i64 MN = (i64)M * N;
+  for (i64 idx = (i64)blockIdx.x * 256 + threadIdx.x; idx < MN; idx += (i64)gridDim.x * 256) {
+    const int m = (int)(idx % M);
+    const i64 n = idx / M;
+    double s = 0.0;
+    for (int z = 0; z < S; ++z) s += part[(i64)z * MN + idx];
+    double* c = C + m + n * ldc;
+    if (beta != 0.0) s += beta * *c;
+    *c = s;
+  }
+}
+
+namespace {
+
+struct Plan {
+  int bm;      // square tile edge: 64 or 128
+  int splits;  // K splits
+  int kchunk;  // K per split (multiple of 16)
+};
+
+constexpr int kBK = 16;
+constexpr i64 kTargetWG = 1024;  // about four workgroups per CU
+
+Plan choose_plan(i64 M, i64 N, i64 K) {
+  const i64 t128 = cdiv(M, 128) * cdiv(N, 128);
+  const i64 t64 = cdiv(M, 64) * cdiv(N, 64);
+  Plan p{128, 1, (int)std::max<i64>(K, 1)};
+  if (K <= 512) {  // rank-b updates and small products: no split
+    p.bm = t128 >= 256 ? 128 : 64;
+    return p;
+  }
+  if (t128 >= kTargetWG) return p;
+  p.bm = 64;
+  if (t64 >= kTargetWG) return p;
+  // skinny output with long K: split K over blockIdx.y
+  i64 s = cdiv(kTargetWG, t64);
+  const i64 max_s = std::max<i64>(1, K / 256);  // keep at least 256 of K per split
+  if (s > max_s) s = max_s;
+  const i64 chunk = cdiv(cdiv(K, s), kBK) * kBK;
+  p.splits = (int)cdiv(K, chunk);
+  p.kchunk = (int)chunk;
+  return p;
+}
+
+template <bool TA, bool TB>
+void launch_tile(hipStream_t st, int bm, dim3 grid, int M, int N, int K, double alpha,
+                 const double* A, i64 lda, const double* B, i64 ldb, double beta, double* C,
+                 i64 ldc, int kchunk, double* part, int tilesM, int ntiles) {
+  if (bm == 128)
+    dgemm_mfma_kernel<TA, TB, 128, 128, kBK><<<grid, kGemmThreads, 0, st>>>(
+        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, ntiles);
+  else
+    dgemm_mfma_kernel<TA, TB, 64, 64, kBK><<<grid, kGemmThreads, 0, st>>>(
+        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, ntiles);
+}
+
+}  // namespace
+
+i64 dgemm_work_elems(i64 M, i64 N, i64 K) {
+  const Plan p = choose_plan(M, N, K);
+  return p.splits > 1 ? (i64)p.splits * M * N : 0;
+}
+
+int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha, const double* A,
+          i64 lda, const double* B, i64 ldb, double beta, double* C, i64 ldc, double* work,
+          i64 work_elems) {
+  if (M <= 0 || N <= 0) return RANDUTV_OK;
+  if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return RANDUTV_ERR_TOO_LARGE;
+  Plan p = choose_plan(M, N, K);
+  if (p.splits > 1 && (work == nullptr || (i64)p.splits * M * N > work_elems)) {
+    // not enough partial space: fall back to as many splits as fit
+    i64 s = work ? work_elems / (M * N) : 0;
+    if (s <= 1) {
+      p.splits = 1;
+      p.kchunk = (int)std::max<i64>(K, 1);
+    } else {
+      i64 chunk = cdiv(cdiv(K, s), kBK) * kBK;
+      p.splits = (int)cdiv(K, chunk);
+      p.kchunk = (int)chunk;
+    }
+  }
+  const int tilesM = (int)cdiv(M, p.bm), tilesN = (int)cdiv(N, p.bm);
+  const int ntiles = tilesM * tilesN;
+  dim3 grid(ntiles, p.splits);
+  double* part = p.splits > 1 ? work : nullptr;
+  const int cls = ta ? (tb ? K_GEMM_TT : K_GEMM_TN) : (tb ? K_GEMM_NT : K_GEMM_NN);
+  LaunchTimer* tm = launch_timer();
+  if (tm) tm->begin(st, cls);
+  if (!ta && !tb)
+    launch_tile<false, false>(st, p.bm, grid, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb,
+                              beta, C, ldc, p.kchunk, part, tilesM, ntiles);
+  else if (ta && !tb)
+    launch_tile<true, false>(st, p.bm, grid, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb,
+                             beta, C, ldc, p.kchunk, part, tilesM, ntiles);
+  else if (!ta && tb)
+    launch_tile<false, true>(st, p.bm, grid, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb,
+                             beta, C, ldc, p.kchunk, part, tilesM, ntiles);
+  else
+    launch_tile<true, true>(st, p.bm, grid, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb,
+                            beta, C, ldc, p.kchunk, part, tilesM, ntiles);
+  RUTV_TRY(hipGetLastError());
+  if (tm) tm->end(st, cls, 2.0 * (double)M * (double)N * (double)K);
+  if (part) {
+    const i64 MN = M * N;
+    const int blocks = (int)std::min<i64>(cdiv(MN, 256), 4096);
+    if (tm) tm->begin(st, K_SPLITK);
+    splitk_reduce_kernel<<<blocks, 256, 0, st>>>((int)M, (int)N, p.splits, part, beta, C, ldc);
+    RUTV_TRY(hipGetLastError());
+    if (tm) tm->end(st, K_SPLITK, 0.0);
+  }
+  return RANDUTV_OK;
+}
+
+}  // namespace rutv

@@ -1,0 +1,75 @@
+// Host-side launchers of the gfx950 kernels (all enqueue on the given stream).
+#pragma once
+
+#include "common.hpp"
+
+namespace rutv {
+
+// Per-launch accounting hook (kernel timing); implemented by the driver.
+struct LaunchTimer {
+  virtual void begin(hipStream_t st, int cls) = 0;
+  virtual void end(hipStream_t st, int cls, double flops) = 0;
+  virtual ~LaunchTimer() = default;
+};
+void set_launch_timer(LaunchTimer* t);
+LaunchTimer* launch_timer();
+
+enum KernelClass : int {
+  K_GEMM_NN = 0, K_GEMM_TN, K_GEMM_NT, K_GEMM_TT, K_SPLITK, K_PANEL, K_LARFT,
+  K_JACOBI, K_SKETCH, K_EXTRACT, K_UTIL, K_APPLY_US, K_NUM_CLASSES
+};
+const char* kernel_class_name(int cls);
+
+// ---- GEMM (gemm.hip) ------------------------------------------------------
+// C = alpha op(A) op(B) + beta C.  'work' (work_elems doubles) holds split-K
+// partial tiles; the launcher picks fewer splits when it is too small.
+int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha,
+          const double* A, i64 lda, const double* B, i64 ldb, double beta,
+          double* C, i64 ldc, double* work, i64 work_elems);
+// split-K partial buffer size (doubles) that lets dgemm use its preferred plan
+i64 dgemm_work_elems(i64 M, i64 N, i64 K);
+
+// ---- Householder panel QR and compact-WY factor (householder.hip) ----------
+constexpr int kPanelMaxCols = 256;
+struct PanelWork {
+  double* part = nullptr;   // per-workgroup partial sums
+  double* tot = nullptr;    // reduced sums
+  unsigned* bar = nullptr;  // grid barrier counter
+  int* err = nullptr;       // device status word
+};
+i64 panel_work_elems(i64 m);
+int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau,
+             const PanelWork& w);
+// W (m x k, ld ldw) := explicit unit lower trapezoidal part of the factored
+// panel P; R (k x k, ld ldr, may be null) := its upper triangle; if zero_panel
+// the panel is overwritten with zeros afterwards.
+int extract_reflectors(hipStream_t st, i64 m, i64 k, double* P, i64 ldp, double* W,
+                       i64 ldw, double* R, i64 ldr, bool zero_panel);
+// Tf (k x k, ld ldt) from the Gram matrix G = W^T W (k x k, ld ldg) and tau.
+int larft_from_gram(hipStream_t st, i64 k, const double* G, i64 ldg,
+                    const double* tau, double* Tf, i64 ldt);
+
+// ---- Jacobi SVD (jacobi.hip) ------------------------------------------------
+constexpr int kJacobiMaxN = 256;
+constexpr int kJacobiMaxSweeps = 30;
+i64 jacobi_work_elems(i64 k);
+// status[0] = sweeps, status[1] = converged flag (device ints)
+int jacobi_svd(hipStream_t st, i64 k, const double* R, i64 ldr, double* d, double* Us,
+               double* Vs, double* work, int* status);
+
+// ---- sketch and utilities (util.hip) ----------------------------------------
+int sketch(hipStream_t st, uint64_t seed, uint64_t step, i64 rows, i64 cols, double* G,
+           i64 ldg);
+int set_identity(hipStream_t st, i64 n, double* X, i64 ldx);
+// B := A (m x n) and flag[0] |= 1 if A holds a non-finite value (flag may be null)
+int copy_check(hipStream_t st, i64 m, i64 n, const double* A, i64 lda, double* B, i64 ldb,
+               int* flag);
+int check_finite(hipStream_t st, i64 m, i64 n, const double* A, i64 lda, int* flag);
+int fill_zero_u32(hipStream_t st, unsigned* p, i64 n);
+// write diag(d) into the k x k block D (ld ldd) (off-diagonal entries := 0)
+int set_diag_block(hipStream_t st, i64 k, const double* d, double* D, i64 ldd);
+// X (rows x cols, ld ldx) := Y (same shape, ld ldy)
+int copy_matrix(hipStream_t st, i64 rows, i64 cols, const double* Y, i64 ldy, double* X,
+                i64 ldx);
+
+}  // namespace rutv

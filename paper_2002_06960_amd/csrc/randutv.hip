@@ -1,0 +1,622 @@
+// randUTV driver and C ABI (see include/randutv.h).
+//
+// Step loop (Section 3.1, Figure 2; 0-based step i, s = i b, b_i = min(b, n-s)):
+//   G     <- sketch(seed, i)                      (m-s) x b_i
+//   Y     <- B^T G, then q times Y <- B^T (B Y)   B = T(s:m, s:n)
+//   (W_V, tau_V) <- QR(Y);  T_V <- larft;  Z_V <- W_V T_V^T
+//   T(:, s:n) -= (T(:, s:n) W_V) Z_V^T            all m rows
+//   V(:, s:n) -= (V(:, s:n) W_V) Z_V^T
+//   (W_U, tau_U, R) <- QR(T(s:m, s:s+b_i));  T_U;  Z_U <- W_U T_U^T
+//   T(s:m, s+b_i:n) -= Z_U (W_U^T T(s:m, s+b_i:n))  (= H_U^T C)
+//   U(:, s:m) -= (U(:, s:m) W_U) Z_U^T
+//   T(s:m, s:s+b_i) <- 0;  R = U_S diag(d) V_S^T;  T(s:s+b_i, s:s+b_i) <- diag(d)
+//   T(0:s, s:s+b_i) <- T(0:s, s:s+b_i) V_S;  V(:, s:s+b_i) <- V(:, s:s+b_i) V_S
+//   U(:, s:s+b_i) <- U(:, s:s+b_i) U_S
+// The left factors U_S^T of the rows T(s:s+b_i, s+b_i:n) are applied after
+// the loop: later steps only multiply those rows from the right, and left and
+// right factors commute, so the result is the same while the SVD stays off
+// the path that feeds the next step.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace rutv {
+
+// ---------------------------------------------------------------------------
+// kernel timing (HIP events on the launching stream)
+// ---------------------------------------------------------------------------
+static thread_local char g_hip_error[256] = "";
+void note_hip_error(hipError_t e) {
+  snprintf(g_hip_error, sizeof(g_hip_error), "%s (%d): %s", hipGetErrorName(e), (int)e,
+           hipGetErrorString(e));
+}
+
+static LaunchTimer* g_timer = nullptr;
+void set_launch_timer(LaunchTimer* t) { g_timer = t; }
+LaunchTimer* launch_timer() { return g_timer; }
+
+static const char* kClassNames[K_NUM_CLASSES] = {
+    "dgemm_nn", "dgemm_tn", "dgemm_nt", "dgemm_tt", "splitk_reduce", "panel_qr",
+    "larft", "jacobi_svd", "sketch", "extract_reflectors", "util", "apply_us"};
+const char* kernel_class_name(int cls) {
+  return (cls >= 0 && cls < K_NUM_CLASSES) ? kClassNames[cls] : "?";
+}
+
+struct EventTimer final : LaunchTimer {
+  struct Rec {
+    hipEvent_t a, b;
+    int cls;
+    double flops;
+  };
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> open;  // begin events awaiting their end (one per class nesting level)
+  int64_t launches[K_NUM_CLASSES] = {};
+  double ms[K_NUM_CLASSES] = {};
+  double flops[K_NUM_CLASSES] = {};
+
+  hipEvent_t take() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void start_call() {
+    used = 0;
+    recs.clear();
+    open.clear();
+  }
+  void clear_counts() {
+    for (int c = 0; c < K_NUM_CLASSES; ++c) launches[c] = 0, ms[c] = 0.0, flops[c] = 0.0;
+  }
+  void begin(hipStream_t st, int) override {
+    hipEvent_t e = take();
+    if (e) (void)hipEventRecord(e, st);
+    open.push_back(e);
+  }
+  void end(hipStream_t st, int cls, double f) override {
+    hipEvent_t a = open.empty() ? nullptr : open.back();
+    if (!open.empty()) open.pop_back();
+    hipEvent_t b = take();
+    if (a && b) {
+      (void)hipEventRecord(b, st);
+      recs.push_back({a, b, cls, f});
+    }
+  }
+  void collect() {
+    for (auto& r : recs) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.cls] += t;
+        launches[r.cls] += 1;
+        flops[r.cls] += r.flops;
+      }
+    }
+    recs.clear();
+    used = 0;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// per-process library state: stream, workspace, timing
+// ---------------------------------------------------------------------------
+struct Context {
+  std::mutex mu;
+  int device = -1;
+  hipStream_t st = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool timing = false;
+  EventTimer timer;
+  std::vector<int> sweeps;
+
+  int init() {
+    int dev = 0;
+    RUTV_TRY(hipGetDevice(&dev));
+    if (st && dev == device) return RANDUTV_OK;
+    if (st) {
+      (void)hipStreamDestroy(st);
+      st = nullptr;
+      if (ws) (void)hipFree(ws);
+      ws = nullptr;
+      ws_bytes = 0;
+    }
+    device = dev;
+    RUTV_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    return RANDUTV_OK;
+  }
+  int reserve(size_t bytes) {
+    if (bytes <= ws_bytes) return RANDUTV_OK;
+    if (ws) {
+      RUTV_TRY(hipStreamSynchronize(st));
+      (void)hipFree(ws);
+      ws = nullptr;
+      ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc((void**)&ws, bytes);
+    if (e != hipSuccess) {
+      ws = nullptr;
+      (void)hipGetLastError();
+      return RANDUTV_ERR_NOMEM;
+    }
+    ws_bytes = bytes;
+    return RANDUTV_OK;
+  }
+};
+
+static Context& ctx() {
+  static Context c;
+  return c;
+}
+
+// carve aligned regions out of one allocation
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <class T>
+  T* take(i64 count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (size_t)std::max<i64>(count, 1);
+    return p;
+  }
+};
+
+struct FactorWS {
+  double *G, *Y, *Zp, *WV, *ZV, *TV, *tauV, *Gram, *X, *WU, *ZU, *TU, *tauU, *X3, *Rb;
+  double *dall, *Usall, *Vsall, *jwork, *splitk, *panel;
+  int* status;  // [0] finite flag, [1] panel sync error, [2 + 2i] sweeps, [3 + 2i] converged
+  unsigned* bar;
+  i64 splitk_elems;
+};
+
+static i64 splitk_need(i64 m, i64 n, i64 b, int q, bool wantU, bool wantV) {
+  i64 need = 0;
+  auto upd = [&](i64 M, i64 N, i64 K) { need = std::max(need, dgemm_work_elems(M, N, K)); };
+  for (i64 s = 0; s < n; s += b) {
+    const i64 bi = std::min(b, n - s), mi = m - s, ni = n - s;
+    upd(ni, bi, mi);
+    if (q > 0) upd(mi, bi, ni);
+    upd(bi, bi, ni);
+    upd(ni, bi, bi);
+    upd(m, bi, ni);
+    upd(m, ni, bi);
+    if (wantV) {
+      upd(n, bi, ni);
+      upd(n, ni, bi);
+    }
+    upd(bi, bi, mi);
+    upd(mi, bi, bi);
+    if (ni > bi) {
+      upd(bi, ni - bi, mi);
+      upd(mi, ni - bi, bi);
+      upd(bi, ni - bi, bi);
+    }
+    if (wantU) {
+      upd(m, bi, mi);
+      upd(m, mi, bi);
+      upd(m, bi, bi);
+    }
+    if (s > 0) upd(s, bi, bi);
+  }
+  return need;
+}
+
+static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wantU, bool wantV) {
+  const i64 nsteps = cdiv(n, b);
+  const i64 mx = std::max(m, n);
+  w.G = c.take<double>(m * b);
+  w.Y = c.take<double>(n * b);
+  w.Zp = c.take<double>(m * b);
+  w.WV = c.take<double>(n * b);
+  w.ZV = c.take<double>(n * b);
+  w.TV = c.take<double>(b * b);
+  w.tauV = c.take<double>(b);
+  w.Gram = c.take<double>(b * b);
+  w.X = c.take<double>(mx * b);
+  w.WU = c.take<double>(m * b);
+  w.ZU = c.take<double>(m * b);
+  w.TU = c.take<double>(b * b);
+  w.tauU = c.take<double>(b);
+  w.X3 = c.take<double>(b * n);
+  w.Rb = c.take<double>(b * b);
+  w.dall = c.take<double>(nsteps * b);
+  w.Usall = c.take<double>(nsteps * b * b);
+  w.Vsall = c.take<double>(nsteps * b * b);
+  w.jwork = c.take<double>(jacobi_work_elems(b));
+  w.splitk_elems = splitk_need(m, n, b, q, wantU, wantV);
+  w.splitk = c.take<double>(w.splitk_elems);
+  w.panel = c.take<double>(panel_work_elems(mx));
+  w.status = c.take<int>(2 + 2 * nsteps);
+  w.bar = c.take<unsigned>(64);
+  return c.off;
+}
+
+static int gemm(hipStream_t st, const FactorWS& w, bool ta, bool tb, i64 M, i64 N, i64 K,
+                double alpha, const double* A, i64 lda, const double* B, i64 ldb, double beta,
+                double* C, i64 ldc) {
+  return dgemm(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, w.splitk,
+               w.splitk_elems);
+}
+
+// compact-WY factor of the reflectors in P (rows x k, ld ldp): W explicit,
+// T from the Gram matrix, Z = W T^T
+static int wy_factor(hipStream_t st, const FactorWS& w, i64 rows, i64 k, double* P, i64 ldp,
+                     const double* tau, double* W, double* Tf, double* Z, double* R,
+                     bool zero_panel) {
+  RUTV_CHECK(extract_reflectors(st, rows, k, P, ldp, W, rows, R, k, zero_panel));
+  RUTV_CHECK(gemm(st, w, true, false, k, k, rows, 1.0, W, rows, W, rows, 0.0, w.Gram, k));
+  RUTV_CHECK(larft_from_gram(st, k, w.Gram, k, tau, Tf, k));
+  RUTV_CHECK(gemm(st, w, false, true, rows, k, k, 1.0, W, rows, Tf, k, 0.0, Z, rows));
+  return RANDUTV_OK;
+}
+
+// C(rows x cols, ld ldc) <- C (I - W T W^T) = C - (C W) Z^T, X scratch (rows x k)
+static int right_apply(hipStream_t st, const FactorWS& w, i64 rows, i64 cols, i64 k, double* C,
+                       i64 ldc, const double* W, const double* Z, double* X) {
+  RUTV_CHECK(gemm(st, w, false, false, rows, k, cols, 1.0, C, ldc, W, cols, 0.0, X, rows));
+  RUTV_CHECK(gemm(st, w, false, true, rows, cols, k, -1.0, X, rows, Z, cols, 1.0, C, ldc));
+  return RANDUTV_OK;
+}
+
+static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uint64_t seed,
+                       double* U, double* T, double* V) {
+  Context& cx = ctx();
+  RUTV_CHECK(cx.init());
+  hipStream_t st = cx.st;
+  const bool wantU = U != nullptr, wantV = V != nullptr;
+  const i64 ldt = m, ldu = m, ldv = n;
+  if (b > n) b = n;
+  const i64 nsteps = cdiv(n, b);
+
+  FactorWS w{};
+  Carver probe;
+  const size_t bytes = layout(probe, w, m, n, b, q, wantU, wantV);
+  RUTV_CHECK(cx.reserve(bytes));
+  Carver real;
+  real.base = cx.ws;
+  layout(real, w, m, n, b, q, wantU, wantV);
+
+  cx.timer.start_call();
+  set_launch_timer(cx.timing ? &cx.timer : nullptr);
+  struct Reset {
+    ~Reset() { set_launch_timer(nullptr); }
+  } reset_timer;
+
+  RUTV_TRY(hipMemsetAsync(w.status, 0, sizeof(int) * (2 + 2 * nsteps), st));
+  // T := A (checking finiteness on the way)
+  if (T != A)
+    RUTV_CHECK(copy_check(st, m, n, A, lda, T, ldt, &w.status[0]));
+  else
+    RUTV_CHECK(check_finite(st, m, n, T, ldt, &w.status[0]));
+  if (wantU) RUTV_CHECK(set_identity(st, m, U, ldu));
+  if (wantV) RUTV_CHECK(set_identity(st, n, V, ldv));
+
+  PanelWork pw;
+  pw.part = w.panel;
+  pw.bar = w.bar;
+  pw.err = &w.status[1];
+
+  i64 s = 0;
+  for (i64 i = 0; s < n; ++i) {
+    const i64 bi = std::min(b, n - s), e = s + bi, mi = m - s, ni = n - s;
+    double* Bm = T + s + s * ldt;
+    // ---- right transform: sketch, power iteration, QR(Y), T(:, s:n) and V updates
+    RUTV_CHECK(sketch(st, seed, (uint64_t)i, mi, bi, w.G, mi));
+    RUTV_CHECK(gemm(st, w, true, false, ni, bi, mi, 1.0, Bm, ldt, w.G, mi, 0.0, w.Y, ni));
+    for (int it = 0; it < q; ++it) {
+      RUTV_CHECK(gemm(st, w, false, false, mi, bi, ni, 1.0, Bm, ldt, w.Y, ni, 0.0, w.Zp, mi));
+      RUTV_CHECK(gemm(st, w, true, false, ni, bi, mi, 1.0, Bm, ldt, w.Zp, mi, 0.0, w.Y, ni));
+    }
+    RUTV_CHECK(panel_qr(st, ni, bi, w.Y, ni, w.tauV, pw));
+    RUTV_CHECK(wy_factor(st, w, ni, bi, w.Y, ni, w.tauV, w.WV, w.TV, w.ZV, nullptr, false));
+    RUTV_CHECK(right_apply(st, w, m, ni, bi, T + s * ldt, ldt, w.WV, w.ZV, w.X));
+    if (wantV) RUTV_CHECK(right_apply(st, w, n, ni, bi, V + s * ldv, ldv, w.WV, w.ZV, w.X));
+    // ---- left transform: QR of the column block, rest of the rows, U update
+    RUTV_CHECK(panel_qr(st, mi, bi, Bm, ldt, w.tauU, pw));
+    RUTV_CHECK(wy_factor(st, w, mi, bi, Bm, ldt, w.tauU, w.WU, w.TU, w.ZU, w.Rb, true));
+    if (e < n) {
+      double* C = T + s + e * ldt;
+      RUTV_CHECK(gemm(st, w, true, false, bi, ni - bi, mi, 1.0, w.WU, mi, C, ldt, 0.0, w.X3, bi));
+      RUTV_CHECK(gemm(st, w, false, false, mi, ni - bi, bi, -1.0, w.ZU, mi, w.X3, bi, 1.0, C, ldt));
+    }
+    if (wantU) RUTV_CHECK(right_apply(st, w, m, mi, bi, U + s * ldu, ldu, w.WU, w.ZU, w.X));
+    // ---- SVD of the b_i x b_i triangular factor
+    double* d = w.dall + i * b;
+    double* Us = w.Usall + i * b * b;
+    double* Vs = w.Vsall + i * b * b;
+    RUTV_CHECK(jacobi_svd(st, bi, w.Rb, bi, d, Us, Vs, w.jwork, &w.status[2 + 2 * i]));
+    RUTV_CHECK(set_diag_block(st, bi, d, Bm, ldt));
+    if (s > 0) {
+      RUTV_CHECK(gemm(st, w, false, false, s, bi, bi, 1.0, T + s * ldt, ldt, Vs, bi, 0.0, w.X, s));
+      RUTV_CHECK(copy_matrix(st, s, bi, w.X, s, T + s * ldt, ldt));
+    }
+    if (wantV) {
+      RUTV_CHECK(gemm(st, w, false, false, n, bi, bi, 1.0, V + s * ldv, ldv, Vs, bi, 0.0, w.X, n));
+      RUTV_CHECK(copy_matrix(st, n, bi, w.X, n, V + s * ldv, ldv));
+    }
+    if (wantU) {
+      RUTV_CHECK(gemm(st, w, false, false, m, bi, bi, 1.0, U + s * ldu, ldu, Us, bi, 0.0, w.X, m));
+      RUTV_CHECK(copy_matrix(st, m, bi, w.X, m, U + s * ldu, ldu));
+    }
+    s = e;
+  }
+  // ---- deferred left factors of the SVDs: T(s:e, e:n) <- U_S^T T(s:e, e:n)
+  s = 0;
+  for (i64 i = 0; s < n; ++i) {
+    const i64 bi = std::min(b, n - s), e = s + bi;
+    if (e < n) {
+      const double* Us = w.Usall + i * b * b;
+      double* C = T + s + e * ldt;
+      RUTV_CHECK(gemm(st, w, true, false, bi, n - e, bi, 1.0, Us, bi, C, ldt, 0.0, w.X3, bi));
+      RUTV_CHECK(copy_matrix(st, bi, n - e, w.X3, bi, C, ldt));
+    }
+    s = e;
+  }
+  RUTV_TRY(hipStreamSynchronize(st));
+  if (cx.timing) cx.timer.collect();
+  std::vector<int> stat(2 + 2 * nsteps);
+  RUTV_TRY(hipMemcpy(stat.data(), w.status, sizeof(int) * stat.size(), hipMemcpyDeviceToHost));
+  cx.sweeps.assign(nsteps, 0);
+  for (i64 i = 0; i < nsteps; ++i) cx.sweeps[i] = stat[2 + 2 * i];
+  if (stat[0]) return RANDUTV_ERR_NONFINITE;
+  if (stat[1]) return RANDUTV_ERR_SYNC;
+  for (i64 i = 0; i < nsteps; ++i)
+    if (!stat[3 + 2 * i]) return RANDUTV_ERR_NOCONV;
+  return RANDUTV_OK;
+}
+
+}  // namespace rutv
+
+using namespace rutv;
+
+extern "C" {
+
+int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                   uint64_t seed, double* U, double* T, double* V) {
+  if (m < 0) return -1;
+  if (n < 0 || n > m) return -2;
+  if (m == 0 || n == 0) return RANDUTV_OK;
+  if (!A) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (b < 1) return -5;
+  if (q < 0) return -6;
+  if (!T) return -9;
+  if (T == A && lda != m) return -9;
+  if (U && (U == T || U == V)) return -8;
+  if (V && V == T) return -10;
+  if (std::min(b, n) > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  return factor_impl(m, n, A, lda, b, q, seed, U, T, V);
+}
+
+int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const double* T,
+                     const double* V, double* Ak) {
+  if (m < 0) return -1;
+  if (n < 0 || n > m) return -2;
+  if (k < 0 || k > n) return -3;
+  if (m == 0 || n == 0) return RANDUTV_OK;
+  if (!U) return -4;
+  if (!T) return -5;
+  if (!V) return -6;
+  if (!Ak) return -7;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  RUTV_CHECK(cx.init());
+  hipStream_t st = cx.st;
+  if (k == 0) {
+    RUTV_TRY(hipMemsetAsync(Ak, 0, sizeof(double) * m * n, st));
+    RUTV_TRY(hipStreamSynchronize(st));
+    return RANDUTV_OK;
+  }
+  // M1 = T(0:k, :) V^T  (k x n), then Ak = U(:, 0:k) M1
+  const i64 sk1 = dgemm_work_elems(k, n, n), sk2 = dgemm_work_elems(m, n, k);
+  const i64 sk = std::max(sk1, sk2);
+  Carver c;
+  c.take<double>(k * n);
+  c.take<double>(sk);
+  RUTV_CHECK(cx.reserve(c.off));
+  Carver r;
+  r.base = cx.ws;
+  double* M1 = r.take<double>(k * n);
+  double* wk = r.take<double>(sk);
+  set_launch_timer(nullptr);
+  RUTV_CHECK(dgemm(st, false, true, k, n, n, 1.0, T, m, V, n, 0.0, M1, k, wk, sk));
+  RUTV_CHECK(dgemm(st, false, false, m, n, k, 1.0, U, m, M1, k, 0.0, Ak, m, wk, sk));
+  RUTV_TRY(hipStreamSynchronize(st));
+  return RANDUTV_OK;
+}
+
+int randutv_sketch(uint64_t seed, uint64_t step, int64_t rows, int64_t cols, double* G,
+                   int64_t ldg) {
+  if (rows < 0) return -3;
+  if (cols < 0) return -4;
+  if (rows == 0 || cols == 0) return RANDUTV_OK;
+  if (!G) return -5;
+  if (ldg < std::max<int64_t>(1, rows)) return -6;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  RUTV_CHECK(cx.init());
+  set_launch_timer(nullptr);
+  RUTV_CHECK(sketch(cx.st, seed, step, rows, cols, G, ldg));
+  RUTV_TRY(hipStreamSynchronize(cx.st));
+  return RANDUTV_OK;
+}
+
+int randutv_dgemm(char transa, char transb, int64_t M, int64_t N, int64_t K, double alpha,
+                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                  double* C, int64_t ldc) {
+  const bool ta = transa == 'T' || transa == 't', tb = transb == 'T' || transb == 't';
+  if (!ta && transa != 'N' && transa != 'n') return -1;
+  if (!tb && transb != 'N' && transb != 'n') return -2;
+  if (M < 0) return -3;
+  if (N < 0) return -4;
+  if (K < 0) return -5;
+  if (M == 0 || N == 0) return RANDUTV_OK;
+  if (K > 0 && !A) return -7;
+  if (lda < std::max<int64_t>(1, ta ? K : M)) return -8;
+  if (K > 0 && !B) return -9;
+  if (ldb < std::max<int64_t>(1, tb ? N : K)) return -10;
+  if (!C) return -12;
+  if (ldc < std::max<int64_t>(1, M)) return -13;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  RUTV_CHECK(cx.init());
+  const i64 sk = dgemm_work_elems(M, N, K);
+  RUTV_CHECK(cx.reserve(sizeof(double) * std::max<i64>(sk, 1)));
+  set_launch_timer(nullptr);
+  RUTV_CHECK(dgemm(cx.st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                   reinterpret_cast<double*>(cx.ws), sk));
+  RUTV_TRY(hipStreamSynchronize(cx.st));
+  return RANDUTV_OK;
+}
+
+int randutv_geqrf(int64_t m, int64_t k, double* A, int64_t lda, double* tau) {
+  if (m < 0) return -1;
+  if (k < 0 || k > m) return -2;
+  if (m == 0 || k == 0) return RANDUTV_OK;
+  if (!A) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (!tau) return -5;
+  if (k > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  RUTV_CHECK(cx.init());
+  Carver c;
+  c.take<double>(panel_work_elems(m));
+  c.take<unsigned>(64);
+  c.take<int>(4);
+  RUTV_CHECK(cx.reserve(c.off));
+  Carver r;
+  r.base = cx.ws;
+  PanelWork pw;
+  pw.part = r.take<double>(panel_work_elems(m));
+  pw.bar = r.take<unsigned>(64);
+  pw.err = r.take<int>(4);
+  set_launch_timer(nullptr);
+  RUTV_TRY(hipMemsetAsync(pw.err, 0, sizeof(int), cx.st));
+  RUTV_CHECK(panel_qr(cx.st, m, k, A, lda, tau, pw));
+  int err = 0;
+  RUTV_TRY(hipMemcpyAsync(&err, pw.err, sizeof(int), hipMemcpyDeviceToHost, cx.st));
+  RUTV_TRY(hipStreamSynchronize(cx.st));
+  return err ? RANDUTV_ERR_SYNC : RANDUTV_OK;
+}
+
+int randutv_larft(int64_t m, int64_t k, const double* W, int64_t ldw, const double* tau,
+                  double* Tf, int64_t ldt) {
+  if (m < 0) return -1;
+  if (k < 0 || k > m) return -2;
+  if (k == 0) return RANDUTV_OK;
+  if (!W) return -3;
+  if (ldw < std::max<int64_t>(1, m)) return -4;
+  if (!tau) return -5;
+  if (!Tf) return -6;
+  if (ldt < k) return -7;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  RUTV_CHECK(cx.init());
+  const i64 sk = dgemm_work_elems(k, k, m);
+  Carver c;
+  c.take<double>(m * k);
+  c.take<double>(k * k);
+  c.take<double>(sk);
+  RUTV_CHECK(cx.reserve(c.off));
+  Carver r;
+  r.base = cx.ws;
+  double* We = r.take<double>(m * k);
+  double* G = r.take<double>(k * k);
+  double* wk = r.take<double>(sk);
+  set_launch_timer(nullptr);
+  RUTV_CHECK(extract_reflectors(cx.st, m, k, const_cast<double*>(W), ldw, We, m, nullptr, 0, false));
+  RUTV_CHECK(dgemm(cx.st, true, false, k, k, m, 1.0, We, m, We, m, 0.0, G, k, wk, sk));
+  RUTV_CHECK(larft_from_gram(cx.st, k, G, k, tau, Tf, ldt));
+  RUTV_TRY(hipStreamSynchronize(cx.st));
+  return RANDUTV_OK;
+}
+
+int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d, double* Us, double* Vs,
+                  int32_t* sweeps) {
+  if (k < 0) return -1;
+  if (k == 0) return RANDUTV_OK;
+  if (!R) return -2;
+  if (ldr < k) return -3;
+  if (!d) return -4;
+  if (!Us) return -5;
+  if (!Vs) return -6;
+  if (k > kJacobiMaxN) return RANDUTV_ERR_TOO_LARGE;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  RUTV_CHECK(cx.init());
+  Carver c;
+  c.take<double>(jacobi_work_elems(k));
+  c.take<int>(4);
+  RUTV_CHECK(cx.reserve(c.off));
+  Carver r;
+  r.base = cx.ws;
+  double* wk = r.take<double>(jacobi_work_elems(k));
+  int* status = r.take<int>(4);
+  set_launch_timer(nullptr);
+  RUTV_CHECK(jacobi_svd(cx.st, k, R, ldr, d, Us, Vs, wk, status));
+  int hs[2] = {0, 0};
+  RUTV_TRY(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, cx.st));
+  RUTV_TRY(hipStreamSynchronize(cx.st));
+  if (sweeps) *sweeps = hs[0];
+  return hs[1] ? RANDUTV_OK : RANDUTV_ERR_NOCONV;
+}
+
+int randutv_set_timing(int32_t enable) {
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  cx.timing = enable != 0;
+  cx.timer.clear_counts();
+  return RANDUTV_OK;
+}
+
+int randutv_kernel_stats(int32_t cap, const char** names, int64_t* launches, double* ms,
+                         double* flops) {
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  int nout = 0;
+  for (int c = 0; c < K_NUM_CLASSES && nout < cap; ++c) {
+    if (names) names[nout] = kernel_class_name(c);
+    if (launches) launches[nout] = cx.timer.launches[c];
+    if (ms) ms[nout] = cx.timer.ms[c];
+    if (flops) flops[nout] = cx.timer.flops[c];
+    ++nout;
+  }
+  return nout;
+}
+
+int randutv_last_sweeps(int32_t cap, int32_t* sweeps) {
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  const int n = (int)cx.sweeps.size();
+  for (int i = 0; i < n && i < cap; ++i) sweeps[i] = cx.sweeps[i];
+  return n;
+}
+
+const char* randutv_last_hip_error(void) { return g_hip_error; }
+
+const char* randutv_strerror(int code) {
+  switch (code) {
+    case RANDUTV_OK: return "success";
+    case RANDUTV_ERR_HIP: return "HIP runtime error or no usable device";
+    case RANDUTV_ERR_NOMEM: return "device workspace allocation failed";
+    case RANDUTV_ERR_NONFINITE: return "input holds NaN or Inf";
+    case RANDUTV_ERR_NOCONV: return "Jacobi SVD did not converge within 30 sweeps";
+    case RANDUTV_ERR_SYNC: return "multi-workgroup kernel wait expired";
+    case RANDUTV_ERR_TOO_LARGE: return "dimension exceeds a kernel limit";
+    default: return code < 0 ? "invalid argument" : "unknown error";
+  }
+}
+
+}  // extern "C"

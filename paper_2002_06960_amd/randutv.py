@@ -1,0 +1,257 @@
+"""Python binding of the gfx950 randUTV library (ctypes over include/randutv.h).
+
+Argument marshalling only: every step of the factorization runs in the HIP
+kernels of librandutv.so.  Torch is used for device memory: matrices are
+float64 CUDA (HIP) tensors in column-major layout (stride (1, ld)); inputs in
+another layout are copied to column-major first.  Calls are synchronous: the
+current torch stream is synchronised before the library runs, and outputs are
+ready on return.  A missing or unloadable library raises RuntimeError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librandutv.so")
+
+RANDUTV_OK = 0
+ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONV, ERR_SYNC, ERR_TOO_LARGE = 1, 2, 3, 4, 5, 6
+
+# name -> (restype, argtypes)
+_I64, _I32, _U64, _D, _P, _C = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double,
+                                ctypes.c_void_p, ctypes.c_char)
+SIGNATURES = {
+    "randutv_factor": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P]),
+    "randutv_truncate": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _P]),
+    "randutv_sketch": (ctypes.c_int, [_U64, _U64, _I64, _I64, _P, _I64]),
+    "randutv_dgemm": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
+    "randutv_geqrf": (ctypes.c_int, [_I64, _I64, _P, _I64, _P]),
+    "randutv_larft": (ctypes.c_int, [_I64, _I64, _P, _I64, _P, _P, _I64]),
+    "randutv_gesvj": (ctypes.c_int, [_I64, _P, _I64, _P, _P, _P, ctypes.POINTER(_I32)]),
+    "randutv_set_timing": (ctypes.c_int, [_I32]),
+    "randutv_kernel_stats": (ctypes.c_int, [_I32, ctypes.POINTER(ctypes.c_char_p),
+                                            ctypes.POINTER(_I64), ctypes.POINTER(_D),
+                                            ctypes.POINTER(_D)]),
+    "randutv_last_sweeps": (ctypes.c_int, [_I32, ctypes.POINTER(_I32)]),
+    "randutv_last_hip_error": (ctypes.c_char_p, []),
+    "randutv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+_lib = None
+
+
+class RandUTVError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        self.code = code
+        lib = load()
+        msg = lib.randutv_strerror(code).decode() if code > 0 else f"argument {-code} is invalid"
+        if code in (ERR_HIP, ERR_NOMEM):
+            msg += f" [{lib.randutv_last_hip_error().decode()}]"
+        super().__init__(f"{fn} returned {code}: {msg}")
+
+
+def load(path: Optional[str] = None):
+    """Load librandutv.so (built in-tree by paper_2002_06960_amd/build.py)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    # Bind the library to the HIP runtime that torch has already loaded (same
+    # SONAME): loading it first would bring in a second HIP runtime, and two
+    # runtimes in one process do not share devices or memory.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with paper_2002_06960_amd/build.py "
+                           "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(fn: str, code: int):
+    if code != RANDUTV_OK:
+        raise RandUTVError(fn, code)
+
+
+# --------------------------------------------------------------------------- tensors
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor_empty(rows: int, cols: int, device=None):
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=torch.float64, device=device or "cuda").t()
+
+
+def as_colmajor(x):
+    """Return (tensor, ld): x as a float64 CUDA tensor with stride (1, ld)."""
+    torch = _torch()
+    if x.dtype != torch.float64 or not x.is_cuda:
+        raise TypeError("expected a float64 CUDA tensor")
+    if x.dim() == 1:
+        x = x.reshape(-1, 1)
+    m, n = x.shape
+    if x.stride(0) == 1 and (n <= 1 or x.stride(1) >= max(1, m)):
+        return x, max(1, x.stride(1) if n > 1 else m)
+    y = x.t().contiguous().t()
+    return y, max(1, m)
+
+
+def _ptr(x) -> int:
+    return 0 if x is None else x.data_ptr()
+
+
+def _sync():
+    torch = _torch()
+    torch.cuda.current_stream().synchronize()
+
+
+# --------------------------------------------------------------------------- API
+def _out(x, rows, cols, device):
+    if x is None:
+        return colmajor_empty(rows, cols, device)
+    if (tuple(x.shape) != (rows, cols) or x.stride(0) != 1 or (cols > 1 and x.stride(1) != rows)
+            or x.dtype.itemsize != 8 or not x.is_cuda):
+        raise ValueError(f"output must be a column-major float64 CUDA tensor of shape {(rows, cols)}")
+    return x
+
+
+def randutv_factor(A, b: int, q: int, seed: int = 0, build_u: bool = True,
+                   build_v: bool = True, in_place: bool = False, U=None, T=None, V=None) -> Tuple:
+    """A = U T V^T.  Returns (U, T, V) column-major tensors (U/V None if not built).
+
+    U, T, V may be given as preallocated column-major outputs."""
+    lib = load()
+    A, lda = as_colmajor(A)
+    m, n = A.shape
+    if in_place and lda == m:
+        T = A
+    else:
+        T = _out(T, m, n, A.device)
+    U = _out(U, m, m, A.device) if build_u else None
+    V = _out(V, n, n, A.device) if build_v else None
+    _sync()
+    _check("randutv_factor", lib.randutv_factor(m, n, _ptr(A), lda, b, q, seed & (2**64 - 1),
+                                                _ptr(U), _ptr(T), _ptr(V)))
+    return U, T, V
+
+
+def randutv_truncate(U, T, V, k: int):
+    """A_k = U(:, :k) T(:k, :) V^T."""
+    lib = load()
+    m, n = T.shape
+    for x, ld in ((U, m), (T, m), (V, n)):
+        if x.stride(0) != 1 or (x.shape[1] > 1 and x.stride(1) != ld):
+            raise ValueError("randutv_truncate expects the column-major outputs of randutv_factor")
+    Ak = colmajor_empty(m, n, T.device)
+    _sync()
+    _check("randutv_truncate", lib.randutv_truncate(m, n, k, _ptr(U), _ptr(T), _ptr(V), _ptr(Ak)))
+    return Ak
+
+
+def randutv_sketch(seed: int, step: int, rows: int, cols: int, device=None):
+    lib = load()
+    G = colmajor_empty(rows, cols, device)
+    _sync()
+    _check("randutv_sketch", lib.randutv_sketch(seed & (2**64 - 1), step, rows, cols, _ptr(G),
+                                                max(1, rows)))
+    return G
+
+
+def randutv_dgemm(transa: str, transb: str, alpha: float, A, B, beta: float = 0.0, C=None):
+    """C = alpha op(A) op(B) + beta C (FP64 MFMA kernels).  Returns C."""
+    lib = load()
+    A, lda = as_colmajor(A)
+    B, ldb = as_colmajor(B)
+    M = A.shape[1] if transa in "Tt" else A.shape[0]
+    K = A.shape[0] if transa in "Tt" else A.shape[1]
+    N = B.shape[0] if transb in "Tt" else B.shape[1]
+    if C is None:
+        C = colmajor_empty(M, N, A.device)
+        ldc = max(1, M)
+    else:
+        if C.stride(0) != 1:
+            raise ValueError("C must be column-major")
+        ldc = max(1, C.stride(1) if N > 1 else M)
+    _sync()
+    _check("randutv_dgemm", lib.randutv_dgemm(transa.encode(), transb.encode(), M, N, K, alpha,
+                                              _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C), ldc))
+    return C
+
+
+def randutv_geqrf(A):
+    """Householder QR in place (dgeqr2 conventions).  Returns (A_factored, tau)."""
+    torch = _torch()
+    lib = load()
+    A, lda = as_colmajor(A.clone())
+    m, k = A.shape
+    tau = torch.empty(k, dtype=torch.float64, device=A.device)
+    _sync()
+    _check("randutv_geqrf", lib.randutv_geqrf(m, k, _ptr(A), lda, _ptr(tau)))
+    return A, tau
+
+
+def randutv_larft(W, tau):
+    """Forward column-wise compact-WY factor of the reflectors below the diagonal of W."""
+    lib = load()
+    W, ldw = as_colmajor(W)
+    m, k = W.shape
+    Tf = colmajor_empty(k, k, W.device)
+    _sync()
+    _check("randutv_larft", lib.randutv_larft(m, k, _ptr(W), ldw, _ptr(tau), _ptr(Tf), max(1, k)))
+    return Tf
+
+
+def randutv_gesvj(R):
+    """One-sided Jacobi SVD of a square matrix: returns (Us, d, Vs, sweeps)."""
+    torch = _torch()
+    lib = load()
+    R, ldr = as_colmajor(R)
+    k = R.shape[0]
+    d = torch.empty(k, dtype=torch.float64, device=R.device)
+    Us = colmajor_empty(k, k, R.device)
+    Vs = colmajor_empty(k, k, R.device)
+    sw = _I32(0)
+    _sync()
+    _check("randutv_gesvj", lib.randutv_gesvj(k, _ptr(R), ldr, _ptr(d), _ptr(Us), _ptr(Vs),
+                                              ctypes.byref(sw)))
+    return Us, d, Vs, sw.value
+
+
+def randutv_set_timing(enable: bool):
+    _check("randutv_set_timing", load().randutv_set_timing(1 if enable else 0))
+
+
+def randutv_kernel_stats():
+    """{kernel class: (launches, ms, flops)} for the last timed randutv_factor call."""
+    lib = load()
+    cap = 32
+    names = (ctypes.c_char_p * cap)()
+    la = (_I64 * cap)()
+    ms = (_D * cap)()
+    fl = (_D * cap)()
+    n = lib.randutv_kernel_stats(cap, names, la, ms, fl)
+    return {names[i].decode(): (la[i], ms[i], fl[i]) for i in range(n)}
+
+
+def randutv_last_sweeps():
+    lib = load()
+    cap = 4096
+    buf = (_I32 * cap)()
+    n = lib.randutv_last_sweeps(cap, buf)
+    return [buf[i] for i in range(min(n, cap))]
+
+
+def randutv_strerror(code: int) -> str:
+    return load().randutv_strerror(code).decode()

@@ -1,0 +1,141 @@
+"""GPU checks of the individual kernels against the CPU oracle / numpy (FP64)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import paper_2002_06960_amd as pkg
+from oracle import randutv_oracle as ro
+from gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("seed,step,rows,cols", [
+    (0, 0, 512, 64), (7, 3, 777, 13), (2**63 + 5, 46, 12000, 256), (1, 1, 1, 1), (3, 2, 5, 3)])
+def test_sketch_matches_oracle(seed, step, rows, cols):
+    G = to_host(pkg.randutv_sketch(seed, step, rows, cols))
+    R = ro.sketch_block(seed, step, rows, cols)
+    # the Philox words are integers (bit-exact); log/cos/sin may differ in the last ulps
+    assert np.abs(G - R).max() <= 1e-13 * max(1.0, np.abs(R).max())
+
+
+GEMM_SHAPES = [(1, 1, 1), (37, 53, 29), (300, 257, 1000), (129, 65, 17), (2500, 256, 3000),
+               (256, 2000, 2400), (700, 700, 256), (64, 64, 0)]
+
+
+@pytest.mark.parametrize("ta,tb", list(itertools.product("NT", "NT")))
+@pytest.mark.parametrize("M,N,K", GEMM_SHAPES)
+def test_dgemm_matches_numpy(ta, tb, M, N, K):
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    A = rng.standard_normal((K, M) if ta == "T" else (M, K))
+    B = rng.standard_normal((N, K) if tb == "T" else (K, N))
+    C0 = rng.standard_normal((M, N))
+    opA = A.T if ta == "T" else A
+    opB = B.T if tb == "T" else B
+    for alpha, beta in ((1.0, 0.0), (-1.0, 1.0), (0.5, -2.0)):
+        C = pkg.randutv_dgemm(ta, tb, alpha, to_dev(A), to_dev(B), beta, to_dev(C0))
+        ref = alpha * (opA @ opB) + beta * C0
+        bound = (abs(alpha) * (np.abs(opA) @ np.abs(opB)) + abs(beta) * np.abs(C0)) * (K + 2) * 2.0**-52
+        err = np.abs(to_host(C) - ref)
+        assert np.all(err <= bound + 1e-300), (alpha, beta, err.max())
+
+
+def test_dgemm_large_skinny_split_k():
+    """The sketch shape of the 12000 x 12000, b = 256 workload (split over K)."""
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((12000, 12000))
+    G = rng.standard_normal((12000, 256))
+    Y = to_host(pkg.randutv_dgemm("T", "N", 1.0, to_dev(A), to_dev(G)))
+    ref = A.T @ G
+    assert np.abs(Y - ref).max() <= 12000 * 2.0**-52 * (np.abs(A).T @ np.abs(G)).max()
+
+
+def _reflectors(F):
+    k = F.shape[1]
+    W = np.tril(F[:, :k], -1)
+    W[np.arange(k), np.arange(k)] = 1.0
+    return W, np.triu(F[:k, :k])
+
+
+@pytest.mark.parametrize("m,k", [(50, 7), (1000, 64), (4000, 128), (12000, 256), (256, 256),
+                                 (16000, 64), (333, 33), (17, 1)])
+def test_geqrf_matches_oracle(m, k):
+    rng = np.random.default_rng(m + k)
+    A = rng.standard_normal((m, k))
+    F, tau = pkg.randutv_geqrf(to_dev(A))
+    Wg, Rg = _reflectors(to_host(F))
+    Wo, tauo, Ro = ro.householder_qr(A)
+    np.testing.assert_allclose(to_host(tau), tauo, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(Wg, Wo, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Rg, Ro, rtol=0, atol=1e-12 * np.abs(Ro).max())
+
+
+def test_geqrf_degenerate_columns():
+    # exactly zero sub-diagonal parts (tau = 0) and a zero column
+    A = np.zeros((300, 20))
+    A[:20, :20] = np.triu(np.arange(1.0, 401.0).reshape(20, 20))
+    A[:, 5] = 0.0
+    F, tau = pkg.randutv_geqrf(to_dev(A))
+    Wo, tauo, Ro = ro.householder_qr(A)
+    assert np.array_equal(to_host(tau), tauo)
+    np.testing.assert_allclose(_reflectors(to_host(F))[1], Ro, atol=0)
+
+
+@pytest.mark.parametrize("m,k", [(500, 64), (12000, 256), (4000, 100), (40, 33)])
+def test_larft_matches_oracle(m, k):
+    rng = np.random.default_rng(k)
+    A = rng.standard_normal((m, k))
+    Wo, tauo, _ = ro.householder_qr(A)
+    To = ro.block_reflector_T(Wo, tauo)
+    F = Wo.copy()
+    F[np.arange(k), np.arange(k)] = 123.0  # diagonal and upper part are ignored
+    F[:k, :k] += np.triu(np.ones((k, k)), 1) * 7.0
+    Tg = to_host(pkg.randutv_larft(to_dev(F), to_dev(tauo)))
+    np.testing.assert_allclose(Tg, To, rtol=0, atol=1e-12 * np.abs(To).max())
+
+
+def _svd_case(k, kind):
+    rng = np.random.default_rng(k)
+    if kind == "sep":  # well separated singular values, triangular like randUTV's R
+        Q1 = np.linalg.qr(rng.standard_normal((k, k)))[0]
+        Q2 = np.linalg.qr(rng.standard_normal((k, k)))[0]
+        s = 1.0 - np.arange(k) / (2.0 * k)
+        return np.linalg.qr(Q1 @ np.diag(s) @ Q2.T)[1]
+    if kind == "graded":
+        return (np.triu(rng.standard_normal((k, k))) / math.sqrt(k) + np.eye(k)) * (10.0 ** -np.linspace(0, 6, k))
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("k,kind", [(256, "sep"), (64, "sep"), (33, "sep"), (128, "graded"), (224, "sep")])
+def test_gesvj_matches_oracle(k, kind):
+    R = _svd_case(k, kind)
+    Us, d, Vs, sweeps = pkg.randutv_gesvj(to_dev(R))
+    Uo, do, Vo, so, ok = ro.jacobi_svd(R)
+    assert ok
+    d = to_host(d)
+    np.testing.assert_allclose(d, do, rtol=0, atol=4e-15 * k * do[0])
+    if kind == "sep":
+        np.testing.assert_allclose(to_host(Vs), Vo, rtol=0, atol=1e-11)
+        np.testing.assert_allclose(to_host(Us), Uo, rtol=0, atol=1e-11)
+    Ug, Vg = to_host(Us), to_host(Vs)
+    assert np.abs(Ug.T @ Ug - np.eye(k)).max() < 1e-13
+    assert np.abs(Vg.T @ Vg - np.eye(k)).max() < 1e-13
+    assert np.abs(Ug @ np.diag(d) @ Vg.T - R).max() < 1e-13 * do[0]
+    assert abs(sweeps - so) <= 2
+
+
+def test_gesvj_degenerate():
+    for R, expect in ((np.zeros((7, 7)), np.zeros(7)), (np.eye(9), np.ones(9))):
+        Us, d, Vs, sweeps = pkg.randutv_gesvj(to_dev(R))
+        k = R.shape[0]
+        assert np.array_equal(to_host(d), expect)
+        assert np.array_equal(to_host(Us), np.eye(k)) and np.array_equal(to_host(Vs), np.eye(k))
+    rng = np.random.default_rng(0)
+    R = np.triu(rng.standard_normal((8, 8)))
+    R[:, 3] = 0.0
+    Us, d, Vs, _ = pkg.randutv_gesvj(to_dev(R))
+    Uo, do, Vo, _, _ = ro.jacobi_svd(R)
+    assert to_host(d)[-1] == 0.0
+    np.testing.assert_allclose(to_host(Us), Uo, atol=1e-12)

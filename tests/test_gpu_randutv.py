@@ -1,0 +1,190 @@
+"""GPU randUTV (C ABI) against the FP64 CPU oracle.
+
+Gate (from the accuracy target of the method's FP64 path): ||S T_gpu S - T_ora||_F
+<= 1e-11 ||A||_F on the rows of T that the input determines, and the GPU
+residual ||A - U T V^T||_F / ||A||_F <= 1e-11 and within 10x of the oracle's.
+Rows beyond the determined ones are found by running the oracle a second time
+on A perturbed in the last bits: where the two oracle runs disagree by more
+than 1e-12 ||A||_F, several results are correct (the trailing sketch columns
+are then chosen by rounding) and those rows are checked by the invariants
+only (orthogonality, triangularity, diagonal blocks, residual).  S aligns the
+sign of each (u_j, v_j) pair with the oracle's.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2002_06960_amd as pkg
+from oracle import randutv_oracle as ro
+from randutv_inputs import make_matrix, make_matrix_device
+from gpu_util import diag_blocks_ok, invariants_dev, sign_align, stable_rows, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL_T = 1e-11
+TOL_RES = 1e-11
+TOL_ORTH = 1e-12
+
+
+def _perturbed(A, seed=123):
+    rng = np.random.default_rng(seed)
+    return A * (1.0 + 2.0**-52 * rng.standard_normal(A.shape))
+
+
+def check_against_oracle(A, b, q, seed, build_u=True, build_v=True, sensitivity=True):
+    m, n = A.shape
+    Ad = to_dev(A)
+    U, T, V = pkg.randutv_factor(Ad, b, q, seed, build_u=build_u, build_v=build_v)
+    Uo, To, Vo = ro.randutv(A, b, q, seed)
+    nA = np.linalg.norm(A)
+    Th = to_host(T)
+    # structure of T: exactly upper triangular, diagonal blocks exactly diagonal
+    assert np.abs(np.tril(Th, -1)).max() == 0.0
+    assert diag_blocks_ok(Th, min(b, n))
+    rows = m
+    if sensitivity:
+        _, To2, _ = ro.randutv(_perturbed(A), b, q, seed)
+        rows = stable_rows(To, To2, nA, min(b, n))
+    if build_v:
+        Ts, flips = sign_align(Th, to_host(V), Vo)
+    else:
+        Ts, flips = Th, 0
+    if rows > 0:
+        diff = np.linalg.norm(Ts[:rows] - To[:rows]) / nA
+        assert diff <= TOL_T, (diff, rows, flips)
+    if build_u and build_v:
+        res, eu, ev, lower = invariants_dev(Ad, U, T, V)
+        res_o = np.linalg.norm(A - Uo @ To @ Vo.T) / nA
+        assert res <= TOL_RES and res <= 10 * max(res_o, 1e-16), (res, res_o)
+        assert eu <= TOL_ORTH and ev <= TOL_ORTH, (eu, ev)
+    return Th, To, rows
+
+
+@pytest.mark.parametrize("m,n,b,q,kind", [
+    (512, 512, 64, 1, "log8"),    # 512 x 512, b = 64, q = 1, sketch seed 0
+    (300, 200, 32, 2, "exp"),     # tall, several steps
+    (257, 257, 64, 1, "iid"),     # ragged last block (257 = 4*64 + 1)
+    (100, 100, 128, 1, "exp"),    # b > n: one step = SVD
+    (640, 320, 64, 0, "log8"),    # tall, no power iteration
+    (200, 130, 48, 2, "log8"),    # b not a power of two, ragged
+    (64, 64, 1, 1, "exp"),        # b = 1
+])
+def test_randutv_small_parity(m, n, b, q, kind):
+    A = make_matrix(kind, m, n, seed=1)
+    check_against_oracle(A, b, q, seed=0)
+
+
+def test_config1_full_parity_and_step_closed_form():
+    A = make_matrix("log8", 512, seed=0)
+    Th, To, rows = check_against_oracle(A, 64, 1, 0)
+    assert rows == 512  # well-posed: every row of T is determined by the input
+    # step-0 closed form: d(0:b) = sigma(A orth((A^T A)^q A^T G(0)))
+    G0 = ro.sketch_block(0, 0, 512, 64)
+    Y0 = A.T @ (A @ (A.T @ G0))
+    d_ref = np.linalg.svd(A @ np.linalg.qr(Y0)[0], compute_uv=False)
+    np.testing.assert_allclose(np.diag(Th)[:64], d_ref, rtol=0, atol=1e-13)
+
+
+def test_single_step_equals_svd():
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((90, 60))
+    U, T, V = pkg.randutv_factor(to_dev(A), 64, 2, 5)
+    sv = np.linalg.svd(A, compute_uv=False)
+    Th = to_host(T)
+    np.testing.assert_allclose(np.diag(Th), sv, rtol=0, atol=1e-13 * sv[0])
+    Th[np.arange(60), np.arange(60)] = 0.0
+    assert np.abs(Th).max() == 0.0
+
+
+def test_zero_and_orthogonal_inputs():
+    U, T, V = pkg.randutv_factor(to_dev(np.zeros((70, 50))), 16, 2, 1)
+    assert np.array_equal(to_host(T), np.zeros((70, 50)))
+    assert np.array_equal(to_host(U), np.eye(70)) and np.array_equal(to_host(V), np.eye(50))
+    Q = np.linalg.qr(np.random.default_rng(2).standard_normal((96, 96)))[0]
+    U, T, V = pkg.randutv_factor(to_dev(Q), 32, 1, 0)
+    np.testing.assert_allclose(to_host(T), np.eye(96), atol=1e-13)
+
+
+def test_rank_deficient_input():
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((160, 12)) @ rng.standard_normal((12, 160))
+    U, T, V = pkg.randutv_factor(to_dev(A), 32, 2, 0)
+    Th = to_host(T)
+    assert np.linalg.norm(Th[12:, 12:]) <= 1e-13 * np.linalg.norm(A)
+    res, eu, ev, _ = invariants_dev(to_dev(A), U, T, V)
+    assert res <= TOL_RES and eu <= TOL_ORTH and ev <= TOL_ORTH
+
+
+def test_nonfinite_input_is_rejected():
+    A = np.ones((40, 30))
+    A[7, 3] = np.nan
+    with pytest.raises(pkg.RandUTVError) as e:
+        pkg.randutv_factor(to_dev(A), 8, 1, 0)
+    assert e.value.code == 3
+
+
+def test_no_uv_and_in_place_give_same_T():
+    A = make_matrix("exp", 300, 300, seed=4)
+    _, T1, _ = pkg.randutv_factor(to_dev(A), 64, 2, 9)
+    _, T2, _ = pkg.randutv_factor(to_dev(A), 64, 2, 9, build_u=False, build_v=False)
+    Ad = to_dev(A)
+    _, T3, _ = pkg.randutv_factor(Ad, 64, 2, 9, build_u=False, in_place=True)
+    assert T3.data_ptr() == Ad.data_ptr()
+    assert np.array_equal(to_host(T1), to_host(T2)) and np.array_equal(to_host(T1), to_host(T3))
+
+
+def test_deterministic():
+    A = make_matrix("iid", 700, 600, seed=2)
+    Ad = to_dev(A)
+    r1 = [to_host(x) for x in pkg.randutv_factor(Ad, 128, 2, 3)]
+    r2 = [to_host(x) for x in pkg.randutv_factor(Ad, 128, 2, 3)]
+    for a, c in zip(r1, r2):
+        assert np.array_equal(a, c)
+
+
+def test_truncate_matches_oracle():
+    A = make_matrix("log8", 400, 300, seed=6)
+    U, T, V = pkg.randutv_factor(to_dev(A), 50, 1, 2)
+    Uo, To, Vo = ro.randutv(A, 50, 1, 2)
+    for k in (0, 50, 77, 300):
+        Ak = to_host(pkg.randutv_truncate(U, T, V, k))
+        Ako = ro.truncate(Uo, To, Vo, k)
+        assert np.linalg.norm(Ak - Ako) <= 1e-11 * np.linalg.norm(A)
+    np.testing.assert_allclose(to_host(pkg.randutv_truncate(U, T, V, 300)), A, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["exp", "step", "iid"])
+def test_config2_parity(kind):
+    """4000 x 4000, b = 128, q = 2 for the three spectra."""
+    A = make_matrix(kind, 4000, seed=0)
+    Th, To, rows = check_against_oracle(A, 128, 2, 0)
+    # the leading block is always determined by the input
+    assert rows >= 128
+
+
+@pytest.mark.parametrize("m,n", [(12000, 12000), (16000, 8000)])
+def test_full_size_invariants_and_step0(m, n):
+    """The full workload sizes, in the configuration the benchmark times:
+    invariants of the whole factorization (any size) plus the first diagonal
+    block against the range-finder closed form computed on the CPU."""
+    import torch
+
+    b, q, seed = 256, 2, 0
+    A = make_matrix_device("exp", m, n, seed=0)
+    U, T, V = pkg.randutv_factor(A, b, q, seed)
+    res, eu, ev, lower = invariants_dev(A, U, T, V)
+    assert res <= TOL_RES and eu <= TOL_ORTH and ev <= TOL_ORTH and lower == 0.0
+    Th0 = to_host(T[:b, :b])
+    assert np.abs(Th0 - np.diag(np.diag(Th0))).max() == 0.0
+    Ah = to_host(A)
+    G0 = ro.sketch_block(seed, 0, m, b)
+    Y = Ah.T @ G0
+    for _ in range(q):
+        Y = Ah.T @ (Ah @ Y)
+    d_ref = np.linalg.svd(Ah @ np.linalg.qr(Y)[0], compute_uv=False)
+    np.testing.assert_allclose(np.diag(Th0), d_ref, rtol=0, atol=1e-12)
+    # interlacing of the first block: d_j <= sigma_j(A) = 0.99^j
+    assert np.all(np.diag(Th0) <= 0.99 ** np.arange(1, b + 1) * (1 + 1e-10))
+    del U, T, V, A
+    torch.cuda.empty_cache()
