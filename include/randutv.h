@@ -50,7 +50,8 @@ extern "C" {
  *   V       : n x n output, ld = n; or NULL to skip building V.
  * Each diagonal b x b block of T is diagonal with non-negative, descending
  * entries (the singular values of that block's triangular factor).
- * m == 0 or n == 0 returns 0 without touching memory.
+ * m == 0 or n == 0 returns 0 without touching memory.  A holding NaN or Inf
+ * returns RANDUTV_ERR_NONFINITE before any factorization work.
  * Errors: -1 m, -2 n (n < 0 or n > m), -3 A NULL, -4 lda, -5 b, -6 q,
  * -8 U aliases T or V, -9 T NULL (or T == A with lda != m), -10 V aliases T,
  * RANDUTV_ERR_TOO_LARGE for min(b, n) > 256, RANDUTV_ERR_* at run time.
@@ -112,7 +113,8 @@ int randutv_larft(int64_t m, int64_t k, const double* W, int64_t ldw,
  * largest-magnitude entry of v_j (lowest index on ties) is positive; u_j is
  * completed by Gram-Schmidt over e_1, e_2, ... where d_j == 0.  *sweeps
  * (host pointer, may be NULL) receives the sweep count.  Errors: -1 k, -2 R,
- * -3 ldr, -4 d, -5 Us, -6 Vs, RANDUTV_ERR_NOCONV after 30 sweeps. */
+ * -3 ldr, -4 d, -5 Us, -6 Vs, RANDUTV_ERR_NONFINITE if R holds NaN/Inf,
+ * RANDUTV_ERR_NOCONV after 30 sweeps. */
 int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d,
                   double* Us, double* Vs, int32_t* sweeps);
 

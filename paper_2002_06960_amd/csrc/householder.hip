@@ -21,20 +21,47 @@
 
 namespace rutv {
 
-constexpr int kPQThreads = 256;
-constexpr int kPQNB = 16;          // leaf width
-constexpr int kPQMaxRows = 320;    // rows of one workgroup's slab
+constexpr int kPQMaxRows = 384;           // rows of one workgroup's slab
+constexpr int kPQThreads = 512;           // 8 waves
+constexpr int kPQWaves = kPQThreads / WAVE;
+constexpr int kPQRowsPerLane = kPQMaxRows / WAVE;  // leaf rows per lane of wave 0
+constexpr int kPQNB = 16;                 // leaf width
+constexpr int kPQLd = kPQMaxRows + 1;     // padded leading dimension of the leaf in LDS
 constexpr int kPQColPart = kPQNB + 1;
 constexpr int kPQTrail = kPQNB * kPQNB + kPQNB * kPanelMaxCols;
+constexpr int kPQMaxWG = 64;
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 static int panel_grid(i64 m) {
-  i64 P = std::max<i64>(cdiv(m, kPQMaxRows), std::min<i64>(128, cdiv(m, 64)));
+  i64 P = std::max<i64>(cdiv(m, kPQMaxRows), std::min<i64>(32, cdiv(m, 128)));
   return (int)std::max<i64>(P, 1);
 }
 
 i64 panel_work_elems(i64 m) {
   const i64 P = panel_grid(m);
   return 2 * P * kPQColPart + 2 * kPQNB + P * kPQTrail + kPQTrail;
+}
+
+// arrival + wait of one workgroup at the panel's grid barrier, executed by a
+// single lane: release on arrival, relaxed polling, one acquire fence
+__device__ __forceinline__ void panel_arrive_wait(unsigned* counter, unsigned target, int* err) {
+  __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned spins = 0;
+  while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(err, RANDUTV_ERR_SYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ void panel_barrier(unsigned* counter, unsigned target, int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) panel_arrive_wait(counter, target, err);
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, double* __restrict__ A,
@@ -49,223 +76,348 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
   double* tpart = piv + 2 * kPQNB;                 // [P][kPQTrail]
   double* ttot = tpart + (i64)P * kPQTrail;        // [kPQTrail]
 
-  __shared__ double L[kPQNB * kPQMaxRows];
-  __shared__ double red[4 * kPQColPart];
+  // L: the leaf's slab (column a at L[a * kPQLd + r]); after the leaf, the explicit W
+  __shared__ double L[kPQNB * kPQLd];
+  // S: lane partials / gathered partials (leaf phase); reduced X, then Tl^T X
+  __shared__ double S[kPQNB * kPanelMaxCols];
   __shared__ double tot[kPQColPart];
-  __shared__ double bc[kPQNB + 4];
+  __shared__ double pv[kPQNB];
   __shared__ double Gs[kPQNB * kPQNB];
   __shared__ double Tl[kPQNB * kPQNB];
-  __shared__ double Yt[kPQNB * kPanelMaxCols];
   __shared__ double taul[kPQNB];
+  static_assert(kPQMaxWG * kPQColPart <= kPQNB * kPanelMaxCols, "S holds the gathered partials");
+  static_assert(WAVE * kPQColPart <= kPQNB * kPanelMaxCols, "S holds the lane partials");
   unsigned nbar = 0;
 
   for (int c0 = 0; c0 < k; c0 += kPQNB) {
     const int nbl = min(kPQNB, k - c0);
-    for (int e = tid; e < R * nbl; e += kPQThreads) {
-      const int r = e % R, c = e / R;
-      L[c * kPQMaxRows + r] = A[(i64)(r0 + r) + (i64)(c0 + c) * lda];
+    for (int e = tid; e < kPQNB * kPQMaxRows; e += kPQThreads) {
+      const int r = e % kPQMaxRows, c = e / kPQMaxRows;
+      L[c * kPQLd + r] = (r < R && c < nbl) ? A[(i64)(r0 + r) + (i64)(c0 + c) * lda] : 0.0;
     }
     __syncthreads();
 
-    for (int jj = 0; jj < nbl; ++jj) {
-      const int j = c0 + jj;
-      // ---- partial sums over own rows strictly below the diagonal
-      double acc[kPQColPart];
+    // ---- the leaf's columns, one at a time, by wave 0 alone (lane l owns
+    // rows l, l + 64, ... of the slab); waves 1-3 wait at the next barrier
+    if (wave == 0) {
+      for (int jj = 0; jj < nbl; ++jj) {
+        const int j = c0 + jj;
+        // column masks (branch-free loops; L is zero outside the slab and leaf)
+        double msk[kPQNB];
 #pragma unroll
-      for (int c = 0; c < kPQColPart; ++c) acc[c] = 0.0;
-      for (int r = tid; r < R; r += kPQThreads) {
-        if (r0 + r > j) {
-          const double x = L[jj * kPQMaxRows + r];
+        for (int c = 0; c < kPQNB; ++c) msk[c] = (c > jj && c < nbl) ? 1.0 : 0.0;
+        double acc[kPQColPart];
+#pragma unroll
+        for (int c = 0; c < kPQColPart; ++c) acc[c] = 0.0;
+#pragma unroll 2
+        for (int i = 0; i < kPQRowsPerLane; ++i) {
+          const int r = lane + WAVE * i;
+          const double x = (r0 + r > j) ? L[jj * kPQLd + r] : 0.0;
           acc[0] += x * x;
 #pragma unroll
-          for (int c = 0; c < kPQNB; ++c)
-            if (c > jj && c < nbl) acc[1 + c] += x * L[c * kPQMaxRows + r];
+          for (int c = 0; c < kPQNB; ++c) acc[1 + c] += x * L[c * kPQLd + r];
         }
-      }
 #pragma unroll
-      for (int c = 0; c < kPQColPart; ++c) {
-        const double v = wave_sum(acc[c]);
-        if (lane == 0) red[wave * kPQColPart + c] = v;
-      }
-      __syncthreads();
-      double* cp = colpart + ((j & 1) * P + wg) * kPQColPart;
-      if (tid < kPQColPart)
-        cp[tid] = ((red[tid] + red[kPQColPart + tid]) + red[2 * kPQColPart + tid]) +
-                  red[3 * kPQColPart + tid];
-      if (j >= r0 && j < r1 && tid >= jj && tid < nbl)
-        piv[(j & 1) * kPQNB + tid] = L[tid * kPQMaxRows + (j - r0)];
-      grid_barrier(bar, (++nbar) * (unsigned)P, err);
-
-      // ---- totals, summed in the same order in every workgroup
-      {
-        double v[kPQColPart];
+        for (int c = 0; c < kPQNB; ++c) acc[1 + c] *= msk[c];
+        // lane partials -> LDS, then lane c < 17 sums the 64 lanes in order
 #pragma unroll
-        for (int c = 0; c < kPQColPart; ++c) v[c] = 0.0;
+        for (int c = 0; c < kPQColPart; ++c) S[lane * kPQColPart + c] = acc[c];
+        __builtin_amdgcn_wave_barrier();
+        double* cp = colpart + ((j & 1) * P + wg) * kPQColPart;
+        {
+          // lane (c, h), h < 3: lanes 22h .. 22h+21 (in order), then the 3 in order
+          const int c = lane % kPQColPart, h = lane / kPQColPart;
+          double sv = 0.0;
+          if (h < 3) {
+            double v[22];
+#pragma unroll
+            for (int i = 0; i < 22; ++i) {
+              const int w = 22 * h + i;
+              v[i] = w < WAVE ? S[w * kPQColPart + c] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 22; ++i) sv += v[i];
+          }
+          const double s1 = __shfl(sv, c + kPQColPart, WAVE), s2 = __shfl(sv, c + 2 * kPQColPart, WAVE);
+          if (lane < kPQColPart) cp[lane] = (sv + s1) + s2;
+        }
+        if (j >= r0 && j < r1 && lane >= jj && lane < nbl)
+          piv[(j & 1) * kPQNB + lane] = L[lane * kPQLd + (j - r0)];
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) panel_arrive_wait(bar, (++nbar) * (unsigned)P, err);
+        else ++nbar;
+        __builtin_amdgcn_wave_barrier();
+        // gather all partials and the pivot row in one batch of loads
         const double* cpb = colpart + (j & 1) * P * kPQColPart;
-        if (tid < P) {
+        {
+          constexpr int NG = (kPQMaxWG * kPQColPart + WAVE - 1) / WAVE;
+          double g[NG];
 #pragma unroll
-          for (int c = 0; c < kPQColPart; ++c) v[c] = cpb[tid * kPQColPart + c];
-        }
+          for (int i = 0; i < NG; ++i) {
+            const int e = lane + WAVE * i;
+            g[i] = e < P * kPQColPart ? cpb[e] : 0.0;
+          }
+          const double pvv = (lane >= jj && lane < nbl) ? piv[(j & 1) * kPQNB + lane] : 0.0;
 #pragma unroll
-        for (int c = 0; c < kPQColPart; ++c) {
-          const double s = wave_sum(v[c]);
-          if (lane == 0) red[wave * kPQColPart + c] = s;
+          for (int i = 0; i < NG; ++i) {
+            const int e = lane + WAVE * i;
+            if (e < kPQMaxWG * kPQColPart) S[e] = g[i];
+          }
+          if (lane < kPQNB) pv[lane] = pvv;
         }
-        __syncthreads();
-        if (tid < kPQColPart)
-          tot[tid] = ((red[tid] + red[kPQColPart + tid]) + red[2 * kPQColPart + tid]) +
-                     red[3 * kPQColPart + tid];
-        __syncthreads();
-      }
-      if (tid == 0) {
-        const double s = tot[0];
-        const double alpha = piv[(j & 1) * kPQNB + jj];
+        __builtin_amdgcn_wave_barrier();
+        if (lane < kPQColPart) {
+          // S past P * 17 holds zeros (set by the gather above)
+          double v[kPQMaxWG];
+#pragma unroll
+          for (int w = 0; w < kPQMaxWG; ++w) v[w] = S[w * kPQColPart + lane];
+          double sv = 0.0;
+#pragma unroll
+          for (int w = 0; w < kPQMaxWG; ++w) sv += v[w];
+          tot[lane] = sv;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // every lane derives the reflector (identical arithmetic everywhere)
+        const double sq = tot[0];
+        const double alpha = pv[jj];
         double t = 0.0, scale = 0.0, beta = alpha;
-        if (s != 0.0) {
-          const double nrm = sqrt(alpha * alpha + s);
+        if (sq != 0.0) {
+          const double nrm = sqrt(alpha * alpha + sq);
           beta = alpha >= 0.0 ? -nrm : nrm;
           t = (beta - alpha) / beta;
           scale = 1.0 / (alpha - beta);
         }
-        bc[0] = t;
-        bc[1] = scale;
-        bc[2] = beta;
-        for (int c = jj + 1; c < nbl; ++c) bc[4 + c] = piv[(j & 1) * kPQNB + c] + scale * tot[1 + c];
-        taul[jj] = t;
-        if (wg == 0) tau[j] = t;
-      }
-      __syncthreads();
-      const double t = bc[0], scale = bc[1];
-      for (int r = tid; r < R; r += kPQThreads) {
-        const int gr = r0 + r;
-        if (gr > j) {
-          const double vr = L[jj * kPQMaxRows + r] * scale;
-          L[jj * kPQMaxRows + r] = vr;
-          for (int c = jj + 1; c < nbl; ++c) L[c * kPQMaxRows + r] -= t * vr * bc[4 + c];
-        } else if (gr == j) {
-          L[jj * kPQMaxRows + r] = bc[2];
-          for (int c = jj + 1; c < nbl; ++c) L[c * kPQMaxRows + r] -= t * bc[4 + c];
+        if (lane == 0) {
+          taul[jj] = t;
+          if (wg == 0) tau[j] = t;
         }
+        double wc[kPQNB];
+#pragma unroll
+        for (int c = 0; c < kPQNB; ++c) wc[c] = msk[c] * (pv[c] + scale * tot[1 + c]);
+#pragma unroll 1
+        for (int i = 0; i < kPQRowsPerLane; ++i) {
+          const int r = lane + WAVE * i;
+          const int gr = r0 + r;
+          const bool live = r < R && gr >= j;
+          double row[kPQNB];
+#pragma unroll
+          for (int c = 0; c < kPQNB; ++c) row[c] = L[c * kPQLd + r];
+          const double lj = L[jj * kPQLd + r];
+          const double vr = gr > j ? lj * scale : 1.0;
+          const double tv = live ? t * vr : 0.0;
+#pragma unroll
+          for (int c = 0; c < kPQNB; ++c) row[c] -= tv * wc[c];
+#pragma unroll
+          for (int c = 0; c < kPQNB; ++c) L[c * kPQLd + r] = row[c];
+          if (live) L[jj * kPQLd + r] = gr > j ? vr : beta;
+        }
+        __builtin_amdgcn_wave_barrier();
       }
-      __syncthreads();
+    } else {
+      nbar += nbl;
     }
+    __syncthreads();
 
-    // leaf back to memory
-    for (int e = tid; e < R * nbl; e += kPQThreads) {
-      const int r = e % R, c = e / R;
-      A[(i64)(r0 + r) + (i64)(c0 + c) * lda] = L[c * kPQMaxRows + r];
+    // leaf back to memory, then L := explicit W of the leaf (1 on the
+    // diagonal row, 0 above it, the reflector below it; zero past nbl)
+    for (int e = tid; e < kPQNB * kPQMaxRows; e += kPQThreads) {
+      const int r = e % kPQMaxRows, c = e / kPQMaxRows;
+      const int gr = r0 + r, dr = c0 + c;
+      const double lv = L[c * kPQLd + r];
+      if (r < R && c < nbl) A[(i64)gr + (i64)dr * lda] = lv;
+      L[c * kPQLd + r] = (r < R && c < nbl) ? (gr > dr ? lv : (gr == dr ? 1.0 : 0.0)) : 0.0;
     }
+    __syncthreads();
 
     const int ncr = k - c0 - nbl;
     if (ncr <= 0) break;
 
     // ---- trailing columns of the panel: C <- C - W (Tl^T (W^T C))
-    // W(r, a) = 0 above the diagonal row c0+a, 1 on it, L below it.
+    // partials on the matrix cores: wave w forms X(:, 16q:16q+16) =
+    // W_slab^T C_slab(:, 16q:16q+16) for the chunks q = w, w + 4, w + 8,
+    // w + 12; the Gram W^T W goes to wave 3 (it has at most 3 chunks)
     double* tp = tpart + (i64)wg * kPQTrail;
-    if (tid < ncr) {
-      double xa[kPQNB];
-#pragma unroll
-      for (int a = 0; a < kPQNB; ++a) xa[a] = 0.0;
-      const double* Ac = A + (i64)(c0 + nbl + tid) * lda;
-      for (int r = 0; r < R; ++r) {
-        const int gr = r0 + r;
-        const double av = Ac[gr];
-#pragma unroll
-        for (int a = 0; a < kPQNB; ++a) {
-          const int dr = c0 + a;
-          if (a < nbl && gr >= dr) xa[a] += (gr > dr ? L[a * kPQMaxRows + r] : 1.0) * av;
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < kPQNB; ++a)
-        if (a < nbl) tp[kPQNB * kPQNB + a * kPanelMaxCols + tid] = xa[a];
-    }
+    const int nchunk = (ncr + 15) / 16;
+    const int lr = lane >> 4, lc = lane & 15;
     {
-      const int a = tid % kPQNB, c = tid / kPQNB;  // 256 threads = 16 x 16 pairs
-      double g = 0.0;
-      if (a < c && c < nbl) {
-        for (int r = 0; r < R; ++r) {
-          const int gr = r0 + r, da = c0 + a, dc = c0 + c;
-          if (gr < dc) continue;
-          const double wc = gr > dc ? L[c * kPQMaxRows + r] : 1.0;
-          const double wa = gr > da ? L[a * kPQMaxRows + r] : 1.0;  // gr >= dc > da
-          g += wa * wc;
+      // wave w forms X(:, 16q:16q+16) = W_slab^T C_slab(:, 16q:16q+16) for
+      // the chunks q = w, w + 8 (ncr <= 240: at most 15 chunks); the last
+      // wave (one chunk at most) also forms the Gram W^T W.  Rows are taken 4
+      // per MFMA; the C values of the next kPF row groups are in flight.
+      constexpr int kPF = 8, NQ = 2;
+      const bool gram = wave == kPQWaves - 1;
+      const double* Ac[NQ];
+      bool cok[NQ], live[NQ];
+      dbl4 acc[NQ], accg = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int qd = 0; qd < NQ; ++qd) {
+        const int tcol = 16 * (wave + kPQWaves * qd) + lc;
+        live[qd] = wave + kPQWaves * qd < nchunk;
+        cok[qd] = tcol < ncr;
+        Ac[qd] = A + (i64)(c0 + nbl + min(tcol, ncr - 1)) * lda + r0;
+        acc[qd] = dbl4{0.0, 0.0, 0.0, 0.0};
+      }
+      const int nst = (R + 3) / 4;
+      double pf[NQ][kPF];
+#pragma unroll
+      for (int i = 0; i < kPF; ++i)
+#pragma unroll
+        for (int qd = 0; qd < NQ; ++qd) {
+          const int r = 4 * i + lr;
+          pf[qd][i] = (cok[qd] && r < R) ? Ac[qd][r] : 0.0;
+        }
+      for (int st0 = 0; st0 < nst; st0 += kPF) {
+        double cv[NQ][kPF];
+#pragma unroll
+        for (int i = 0; i < kPF; ++i)
+#pragma unroll
+          for (int qd = 0; qd < NQ; ++qd) {
+            cv[qd][i] = pf[qd][i];
+            const int r = 4 * (st0 + kPF + i) + lr;
+            pf[qd][i] = (cok[qd] && r < R) ? Ac[qd][r] : 0.0;
+          }
+#pragma unroll
+        for (int i = 0; i < kPF; ++i) {
+          const int r = 4 * (st0 + i) + lr;
+          const double wa = r < kPQMaxRows ? L[lc * kPQLd + r] : 0.0;  // W(r, a = lc)
+#pragma unroll
+          for (int qd = 0; qd < NQ; ++qd)
+            if (live[qd]) acc[qd] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, cv[qd][i], acc[qd], 0, 0, 0);
+          if (gram) accg = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, wa, accg, 0, 0, 0);
         }
       }
-      tp[tid] = g;
-    }
-    grid_barrier(bar, (++nbar) * (unsigned)P, err);
-    // two-phase reduction: entry e summed over workgroups in order by one thread
-    for (int e = wg * kPQThreads + tid; e < kPQTrail; e += P * kPQThreads) {
-      const int a = e < kPQNB * kPQNB ? -1 : (e - kPQNB * kPQNB) / kPanelMaxCols;
-      const int col = e < kPQNB * kPQNB ? 0 : (e - kPQNB * kPQNB) % kPanelMaxCols;
-      double s = 0.0;
-      if (e < kPQNB * kPQNB || (a < nbl && col < ncr))
-        for (int w = 0; w < P; ++w) s += tpart[(i64)w * kPQTrail + e];
-      ttot[e] = s;
-    }
-    grid_barrier(bar, (++nbar) * (unsigned)P, err);
-    Gs[tid] = ttot[tid];
-    for (int e = tid; e < nbl * kPanelMaxCols; e += kPQThreads) Yt[e] = ttot[kPQNB * kPQNB + e];
-    for (int e = tid; e < kPQNB * kPQNB; e += kPQThreads) Tl[e] = 0.0;
-    __syncthreads();
-    // leaf T factor, column by column: T(i, c) = -tau_c sum_{l=i}^{c-1} T(i, l) G(l, c)
-    for (int c = 0; c < nbl; ++c) {
-      if (tid < c) {
-        double s = 0.0;
-        for (int l = tid; l < c; ++l) s += Tl[tid + l * kPQNB] * Gs[l + c * kPQNB];
-        Tl[tid + c * kPQNB] = -taul[c] * s;
+      // D(4q + lr, lc): X[a = 4q + lr][t], Gram[a][c = lc]
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int a = 4 * qq + lr;
+#pragma unroll
+        for (int qd = 0; qd < NQ; ++qd) {
+          const int tcol = 16 * (wave + kPQWaves * qd) + lc;
+          if (live[qd] && tcol < ncr) tp[kPQNB * kPQNB + a * kPanelMaxCols + tcol] = acc[qd][qq];
+        }
+        if (gram) tp[a + lc * kPQNB] = accg[qq];
       }
-      if (tid == c) Tl[c + c * kPQNB] = taul[c];
-      __syncthreads();
     }
-    // Yt <- Tl^T X (each thread its own column)
+    panel_barrier(bar, (++nbar) * (unsigned)P, err);
+    // two-phase reduction: workgroup wg sums entries e = wg * 256 + ..., over
+    // the workgroups in order
+    for (int e = wg * kPQThreads + tid; e < kPQTrail; e += P * kPQThreads) {
+      const bool g = e < kPQNB * kPQNB;
+      const int a = g ? 0 : (e - kPQNB * kPQNB) / kPanelMaxCols;
+      const int col = g ? 0 : (e - kPQNB * kPQNB) % kPanelMaxCols;
+      double sv = 0.0;
+      if (g || (a < nbl && col < ncr)) {
+        double v[kPQMaxWG];
+#pragma unroll
+        for (int w = 0; w < kPQMaxWG; ++w) v[w] = w < P ? tpart[(i64)w * kPQTrail + e] : 0.0;
+#pragma unroll
+        for (int w = 0; w < kPQMaxWG; ++w) sv += v[w];
+      }
+      ttot[e] = sv;
+    }
+    panel_barrier(bar, (++nbar) * (unsigned)P, err);
+    if (tid < kPQNB * kPQNB) {
+      Gs[tid] = ttot[tid];
+      Tl[tid] = 0.0;
+    }
+    for (int e = tid; e < nbl * kPanelMaxCols; e += kPQThreads) S[e] = ttot[kPQNB * kPQNB + e];
+    __syncthreads();
+    // leaf T factor, column by column (wave 0 alone, lanes = rows):
+    // T(i, c) = -tau_c sum_{l=i}^{c-1} T(i, l) G(l, c)
+    if (wave == 0 && lane < kPQNB) {
+      double trow[kPQNB];
+#pragma unroll
+      for (int c = 0; c < kPQNB; ++c) trow[c] = 0.0;
+#pragma unroll
+      for (int c = 0; c < kPQNB; ++c) {
+        if (c >= nbl) break;
+        double sdot = 0.0;
+#pragma unroll
+        for (int l = 0; l < kPQNB; ++l)
+          if (l >= lane && l < c) sdot += trow[l] * Gs[l + c * kPQNB];
+        trow[c] = lane < c ? -taul[c] * sdot : (lane == c ? taul[c] : 0.0);
+      }
+#pragma unroll
+      for (int c = 0; c < kPQNB; ++c) Tl[lane + c * kPQNB] = trow[c];
+    }
+    __syncthreads();
+    // S <- Tl^T X (thread t owns column t; ncr <= 240 < threads)
     if (tid < ncr) {
       double x[kPQNB];
 #pragma unroll
-      for (int a = 0; a < kPQNB; ++a) x[a] = a < nbl ? Yt[a * kPanelMaxCols + tid] : 0.0;
+      for (int a = 0; a < kPQNB; ++a) x[a] = a < nbl ? S[a * kPanelMaxCols + tid] : 0.0;
 #pragma unroll
       for (int a = 0; a < kPQNB; ++a) {
-        double s = 0.0;
+        double sv = 0.0;
 #pragma unroll
-        for (int l = 0; l <= a; ++l) s += Tl[l + a * kPQNB] * x[l];
-        if (a < nbl) Yt[a * kPanelMaxCols + tid] = s;
+        for (int l = 0; l <= a; ++l) sv += Tl[l + a * kPQNB] * x[l];
+        S[a * kPanelMaxCols + tid] = a < nbl ? sv : 0.0;
       }
     }
     __syncthreads();
-    if (tid < ncr) {
-      double y[kPQNB];
+    // update on the matrix cores: 16-row x 16-column blocks of C -= W Y with
+    // Y = S (16 x ncr); the MFMA forms the block transposed, so a lane holds
+    // 4 columns of one row: C[rb + lc][t0 + 4q + lr] (16 rows per column per
+    // store).  Blocks are dealt to the waves; the next block's C is fetched
+    // while the current one is computed.
+    {
+      const int nrb = (R + 15) / 16;
+      const int nblocks = nrb * nchunk;
+      constexpr int kRing = 4;
+      double ring[kRing][4];
+      auto fetch = [&](int bi, double (&dst)[4]) {
+        const int rb = 16 * (bi % nrb), t0 = 16 * (bi / nrb);
+        const int r = rb + lc;
 #pragma unroll
-      for (int a = 0; a < kPQNB; ++a) y[a] = a < nbl ? Yt[a * kPanelMaxCols + tid] : 0.0;
-      double* Ac = A + (i64)(c0 + nbl + tid) * lda;
-      for (int r = 0; r < R; ++r) {
-        const int gr = r0 + r;
-        double s = 0.0;
-#pragma unroll
-        for (int a = 0; a < kPQNB; ++a) {
-          const int dr = c0 + a;
-          if (a < nbl && gr >= dr) s += (gr > dr ? L[a * kPQMaxRows + r] : 1.0) * y[a];
+        for (int q = 0; q < 4; ++q) {
+          const int t = t0 + 4 * q + lr;
+          dst[q] = (bi < nblocks && r < R && t < ncr) ? A[(i64)(r0 + r) + (i64)(c0 + nbl + t) * lda] : 0.0;
         }
-        Ac[gr] -= s;
+      };
+#pragma unroll
+      for (int u = 0; u < kRing; ++u) fetch(wave + kPQWaves * u, ring[u]);
+      for (int bidx = wave, it = 0; bidx < nblocks; bidx += kPQWaves, ++it) {
+        double cc[4];
+        const int slot = it % kRing;
+#pragma unroll
+        for (int u = 0; u < kRing; ++u)
+          if (u == slot)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cc[q] = ring[u][q];
+        double nx[4];
+        fetch(bidx + kPQWaves * kRing, nx);
+#pragma unroll
+        for (int u = 0; u < kRing; ++u)
+          if (u == slot)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ring[u][q] = nx[q];
+        const int rb = 16 * (bidx % nrb), t0 = 16 * (bidx / nrb);
+        dbl4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < kPQNB; kk += 4) {
+          const double yv = S[(kk + lr) * kPanelMaxCols + t0 + lc];   // Y^T(t0 + lc, kk + lr)
+          const double wv = L[(kk + lr) * kPQLd + rb + lc];           // W^T(kk + lr, rb + lc)
+          d = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, wv, d, 0, 0, 0);
+        }
+        const int r = rb + lc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int t = t0 + 4 * q + lr;
+          if (r < R && t < ncr) A[(i64)(r0 + r) + (i64)(c0 + nbl + t) * lda] = cc[q] - d[q];
+        }
       }
     }
     __syncthreads();
   }
 }
 
-__global__ void zero_u32_kernel(unsigned* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
 int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau, const PanelWork& w) {
   if (k <= 0 || m <= 0) return RANDUTV_OK;
   if (k > kPanelMaxCols || m < k) return RANDUTV_ERR_TOO_LARGE;
   const int P = panel_grid(m);
-  if (P > 256 || cdiv(m, P) > kPQMaxRows) return RANDUTV_ERR_TOO_LARGE;
+  if (P > kPQMaxWG || cdiv(m, P) > kPQMaxRows) return RANDUTV_ERR_TOO_LARGE;
   LaunchTimer* tm = launch_timer();
-  zero_u32_kernel<<<1, 64, 0, st>>>(w.bar, 1);
-  RUTV_TRY(hipGetLastError());
+  RUTV_CHECK(fill_zero_u32(st, w.bar, 1));
   if (tm) tm->begin(st, K_PANEL);
   panel_qr_kernel<<<P, kPQThreads, 0, st>>>((int)m, (int)k, A, lda, tau, w.part, w.bar, w.err);
   RUTV_TRY(hipGetLastError());

@@ -1,15 +1,24 @@
 // SVD of the b x b diagonal block (Figure 2, "[A11, U_SVD, V_SVD] := SVD(A11)")
-// by one-sided Jacobi in a single workgroup.
+// by one-sided Jacobi, spread over P <= 8 workgroups.
 //
-// W := R, V := I; sweeps of the round-robin tournament ordering (b-1 rounds of
-// b/2 disjoint column pairs, one wave per pair); pair (j, k) is rotated when
-// |w_j.w_k| > b u |w_j| |w_k| (u = 2^-53) with the Rutishauser rotation
-// zeta = (|w_k|^2 - |w_j|^2) / (2 w_j.w_k), t = sign(zeta)/(|zeta| + sqrt(1+zeta^2)).
+// W := R, V := I.  The k columns are split into 2P blocks of up to 16
+// columns.  A sweep is a round-robin tournament over the blocks (2P-1
+// rounds): in each round every workgroup takes one pair of blocks into LDS
+// (W and V columns), rotates every column pair across the two blocks (and,
+// in the first round, the pairs inside each block), and writes the blocks
+// back; a grid barrier separates rounds.  Every column pair is visited once
+// per sweep.  Pair (j, q), j < q, is rotated when |w_j.w_q| > k u |w_j||w_q|
+// (u = 2^-53) with the Rutishauser rotation
+//   zeta = (|w_q|^2 - |w_j|^2) / (2 w_j.w_q),
+//   t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),  c = 1/sqrt(1+t^2), s = c t,
+//   w_j <- c w_j - s w_q,  w_q <- s w_j + c w_q  (same on V).
 // A sweep without rotation ends the iteration (cap: 30 sweeps).  Then
 // d_j = |w_j|, columns sorted by descending d (ties keep order),
 // u_j = w_j / d_j (Gram-Schmidt completion over e_1, e_2, ... where d_j = 0),
 // and (u_j, v_j) negated when the largest-magnitude entry of v_j (lowest
 // index on ties) is negative.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace rutv {
@@ -17,8 +26,10 @@ namespace rutv {
 constexpr int kJThreads = 1024;
 constexpr int kJWaves = kJThreads / WAVE;
 constexpr int kJRows = kJacobiMaxN / WAVE;  // rows per lane
+constexpr int kJBW = 16;                    // columns per block
+constexpr int kJMaxWG = kJacobiMaxN / (2 * kJBW);
 
-i64 jacobi_work_elems(i64 k) { return 2 * k * k; }
+i64 jacobi_work_elems(i64 k) { return 2 * k * k + 64; }
 
 __device__ __forceinline__ int rr_player(int x, int round, int p) {
   if (x == 0) return 0;
@@ -27,88 +38,158 @@ __device__ __forceinline__ int rr_player(int x, int round, int p) {
   return 1 + v;
 }
 
-__global__ __launch_bounds__(kJThreads) void jacobi_kernel(int k, const double* __restrict__ R,
-                                                           i64 ldr, double* __restrict__ d,
-                                                           double* __restrict__ Us,
-                                                           double* __restrict__ Vs,
-                                                           double* __restrict__ work,
-                                                           int* __restrict__ status) {
+__device__ __forceinline__ void wave_sum3(double& a, double& b, double& c) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, WAVE);
+    b += __shfl_xor(b, off, WAVE);
+    c += __shfl_xor(c, off, WAVE);
+  }
+}
+
+// rotate columns x (global index gj) and y (global index gq) held in LDS
+// (W at wx/wy, V at vx/vy, k rows); returns 1 if rotated
+__device__ __forceinline__ int jacobi_pair(int k, int lane, double tol, double* wx, double* wy,
+                                           double* vx, double* vy) {
+  double xj[kJRows], xq[kJRows];
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int e = 0; e < kJRows; ++e) {
+    const int r = lane + WAVE * e;
+    xj[e] = r < k ? wx[r] : 0.0;
+    xq[e] = r < k ? wy[r] : 0.0;
+    al += xj[e] * xj[e];
+    be += xq[e] * xq[e];
+    ga += xj[e] * xq[e];
+  }
+  wave_sum3(al, be, ga);
+  if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) return 0;
+  const double zeta = (be - al) / (2.0 * ga);
+  double tn = 1.0;
+  if (zeta != 0.0) tn = (zeta > 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + tn * tn);
+  const double sn = cs * tn;
+#pragma unroll
+  for (int e = 0; e < kJRows; ++e) {
+    const int r = lane + WAVE * e;
+    if (r < k) {
+      wx[r] = cs * xj[e] - sn * xq[e];
+      wy[r] = sn * xj[e] + cs * xq[e];
+      const double yj = vx[r], yq = vy[r];
+      vx[r] = cs * yj - sn * yq;
+      vy[r] = sn * yj + cs * yq;
+    }
+  }
+  return 1;
+}
+
+// global work layout: W (k x k, ld k), V (k x k, ld k), then counters:
+// ctr[0] barrier, ctr[1] cumulative rotation count
+__global__ __launch_bounds__(kJThreads) void jacobi_block_kernel(int k, const double* __restrict__ R,
+                                                                 i64 ldr, double* __restrict__ d,
+                                                                 double* __restrict__ Us,
+                                                                 double* __restrict__ Vs,
+                                                                 double* __restrict__ work,
+                                                                 unsigned* __restrict__ ctr,
+                                                                 int* __restrict__ status) {
+  const int P = gridDim.x, wg = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* W = work;          // k x k, ld k
+  const int nblk = 2 * P;
+  double* W = work;
   double* V = work + (i64)k * k;
-  __shared__ int rotated;
+  __shared__ double Wl[2][kJBW][kJacobiMaxN];
+  __shared__ double Vl[2][kJBW][kJacobiMaxN];
+  __shared__ int lrot;
   __shared__ double dn[kJacobiMaxN];
   __shared__ int perm[kJacobiMaxN];
-  __shared__ double sgn[kJacobiMaxN];
+  __shared__ int s_done;
+  unsigned nbar = 0;
+  int* err = status + 2;
 
-  for (int e = tid; e < k * k; e += kJThreads) {
-    const int r = e % k, c = e / k;
+  // W := R, V := I (each workgroup its share of the columns)
+  for (i64 e = (i64)wg * kJThreads + tid; e < (i64)k * k; e += (i64)P * kJThreads) {
+    const int r = (int)(e % k), c = (int)(e / k);
     W[e] = R[r + (i64)c * ldr];
     V[e] = r == c ? 1.0 : 0.0;
   }
-  __syncthreads();
+  grid_barrier(ctr, (++nbar) * (unsigned)P, err);
 
   const double tol = (double)k * 0x1p-53;
-  const int p = k + (k & 1);
   int sweeps = 0;
   bool converged = k <= 1;
+  unsigned prev_total = 0;
   while (!converged && sweeps < kJacobiMaxSweeps) {
     ++sweeps;
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int round = 0; round < p - 1; ++round) {
-      for (int t = wave; t < p / 2; t += kJWaves) {
-        int a = rr_player(t, round, p), c = rr_player(p - 1 - t, round, p);
-        if (a >= k || c >= k) continue;
-        const int j = min(a, c), q = max(a, c);
-        double* wj = W + (i64)j * k;
-        double* wq = W + (i64)q * k;
-        double xj[kJRows], xq[kJRows];
-        double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-        for (int e = 0; e < kJRows; ++e) {
-          const int r = lane + WAVE * e;
-          xj[e] = r < k ? wj[r] : 0.0;
-          xq[e] = r < k ? wq[r] : 0.0;
-          al += xj[e] * xj[e];
-          be += xq[e] * xq[e];
-          ga += xj[e] * xq[e];
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        double tn = 1.0;
-        if (zeta != 0.0) tn = (zeta > 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + tn * tn);
-        const double sn = cs * tn;
-        double* vj = V + (i64)j * k;
-        double* vq = V + (i64)q * k;
-#pragma unroll
-        for (int e = 0; e < kJRows; ++e) {
-          const int r = lane + WAVE * e;
-          if (r < k) {
-            wj[r] = cs * xj[e] - sn * xq[e];
-            wq[r] = sn * xj[e] + cs * xq[e];
-            const double yj = vj[r], yq = vq[r];
-            vj[r] = cs * yj - sn * yq;
-            vq[r] = sn * yj + cs * yq;
-          }
-        }
-        if (lane == 0) rotated = 1;
+    if (tid == 0) lrot = 0;
+    for (int round = 0; round < nblk - 1 || (nblk == 2 && round == 0); ++round) {
+      const int pa = rr_player(wg, round, nblk), pb = rr_player(nblk - 1 - wg, round, nblk);
+      const int ba = min(pa, pb), bb = max(pa, pb);
+      const int blk[2] = {ba, bb};
+      // load both blocks (column c of block x is global column x*16 + c)
+      for (int e = tid; e < 2 * kJBW * k; e += kJThreads) {
+        const int r = e % k, cc = e / k, x = cc / kJBW, c = cc % kJBW;
+        const int gc = blk[x] * kJBW + c;
+        Wl[x][c][r] = gc < k ? W[r + (i64)gc * k] : 0.0;
+        Vl[x][c][r] = gc < k ? V[r + (i64)gc * k] : 0.0;
       }
       __syncthreads();
+      int myrot = 0;
+      if (round == 0) {
+        // pairs inside each block: 15 inner rounds of 8 pairs per block
+        const int x = wave / 8, p = wave % 8;
+        for (int ir = 0; ir < kJBW - 1; ++ir) {
+          const int c1 = rr_player(p, ir, kJBW), c2 = rr_player(kJBW - 1 - p, ir, kJBW);
+          const int cj = min(c1, c2), cq = max(c1, c2);
+          if (blk[x] * kJBW + cq < k)
+            myrot += jacobi_pair(k, lane, tol, Wl[x][cj], Wl[x][cq], Vl[x][cj], Vl[x][cq]);
+          __syncthreads();
+        }
+      }
+      // pairs across the two blocks: 16 inner steps of 16 disjoint pairs
+      for (int t = 0; t < kJBW; ++t) {
+        const int i = wave, j2 = (wave + t) % kJBW;
+        if (ba != bb && ba * kJBW + i < k && bb * kJBW + j2 < k)
+          myrot += jacobi_pair(k, lane, tol, Wl[0][i], Wl[1][j2], Vl[0][i], Vl[1][j2]);
+        __syncthreads();
+      }
+      if (lane == 0 && myrot) atomicAdd(&lrot, myrot);
+      // blocks back to global memory
+      for (int e = tid; e < 2 * kJBW * k; e += kJThreads) {
+        const int r = e % k, cc = e / k, x = cc / kJBW, c = cc % kJBW;
+        const int gc = blk[x] * kJBW + c;
+        if (gc < k) {
+          W[r + (i64)gc * k] = Wl[x][c][r];
+          V[r + (i64)gc * k] = Vl[x][c][r];
+        }
+      }
+      const bool last = (round == nblk - 2) || nblk == 2;
+      if (last) {
+        __syncthreads();
+        if (tid == 0)
+          __hip_atomic_fetch_add(&ctr[1], (unsigned)lrot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      grid_barrier(ctr, (++nbar) * (unsigned)P, err);
+      if (last) {
+        if (tid == 0) {
+          const unsigned tot = __hip_atomic_load(&ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_done = tot == prev_total ? 1 : 0;
+          lrot = (int)tot;  // reuse as broadcast of the total
+        }
+        __syncthreads();
+        converged = s_done != 0;
+        prev_total = (unsigned)lrot;
+        __syncthreads();
+        break;
+      }
     }
-    converged = rotated == 0;
-    __syncthreads();
   }
-  if (tid == 0) {
+  if (wg == 0 && tid == 0) {
     status[0] = sweeps;
     status[1] = converged ? 1 : 0;
   }
 
-  // column norms
+  // ---- outputs: norms, stable descending order, signs (every workgroup
+  // derives the same order; each writes its share of the columns)
   for (int c = wave; c < k; c += kJWaves) {
     const double* wc = W + (i64)c * k;
     double s = 0.0;
@@ -121,20 +202,22 @@ __global__ __launch_bounds__(kJThreads) void jacobi_kernel(int k, const double* 
     if (lane == 0) dn[c] = sqrt(s);
   }
   __syncthreads();
-  // stable descending order
+  // rank with a total order (a non-finite norm ranks last), so perm is a
+  // permutation of 0..k-1 whatever the values
   if (tid < k) {
-    const double dj = dn[tid];
+    const double dj = isfinite(dn[tid]) ? dn[tid] : -1.0;
     int rank = 0;
     for (int i = 0; i < k; ++i) {
-      const double di = dn[i];
+      const double di = isfinite(dn[i]) ? dn[i] : -1.0;
       rank += (di > dj || (di == dj && i < tid)) ? 1 : 0;
     }
     perm[rank] = tid;
   }
   __syncthreads();
-  // sign of each output column from its v: largest |entry|, lowest index on ties
+  bool any_zero = false;
   for (int qo = wave; qo < k; qo += kJWaves) {
-    const double* vc = V + (i64)perm[qo] * k;
+    const int src = perm[qo];
+    const double* vc = V + (i64)src * k;
     double mx = 0.0;
     int idx = k;
 #pragma unroll
@@ -142,85 +225,116 @@ __global__ __launch_bounds__(kJThreads) void jacobi_kernel(int k, const double* 
       const int r = lane + WAVE * e;
       if (r < k) {
         const double a = fabs(vc[r]);
-        if (a > mx || idx == k) { mx = a; idx = r; }
+        if (a > mx || idx == k) {
+          mx = a;
+          idx = r;
+        }
       }
     }
-    // reduce (max |v|, then min index)
-    double gmx = wave_max(mx);
+    const double gmx = wave_max(mx);
     int cand = (mx == gmx && idx < k) ? idx : k;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off, WAVE));
-    if (lane == 0) sgn[qo] = vc[cand] < 0.0 ? -1.0 : 1.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < k * k; e += kJThreads) {
-    const int r = e % k, qo = e / k;
-    const int src = perm[qo];
-    const double s = sgn[qo];
-    Vs[r + (i64)qo * k] = s * V[r + (i64)src * k];
+    if (cand >= k) cand = 0;  // only when v holds NaN
+    const double sg = vc[cand] < 0.0 ? -1.0 : 1.0;
+    if (qo % P != wg) continue;
     const double dv = dn[src];
-    Us[r + (i64)qo * k] = dv > 0.0 ? s * (W[r + (i64)src * k] / dv) : 0.0;
+    const double* wc = W + (i64)src * k;
+#pragma unroll
+    for (int e = 0; e < kJRows; ++e) {
+      const int r = lane + WAVE * e;
+      if (r < k) {
+        Vs[r + (i64)qo * k] = sg * vc[r];
+        Us[r + (i64)qo * k] = dv > 0.0 ? sg * (wc[r] / dv) : 0.0;
+      }
+    }
+    if (lane == 0) d[qo] = dv;
   }
-  if (tid < k) d[tid] = dn[perm[tid]];
-  __syncthreads();
-  // completion of u_j where d_j == 0 (they sit at the end of the order)
-  if (wave == 0) {
-    int cand = 0;
-    for (int qo = 0; qo < k; ++qo) {
-      if (dn[perm[qo]] > 0.0) continue;
-      while (cand < k) {
-        double x[kJRows];
+  any_zero = dn[perm[k - 1]] == 0.0;
+  if (!any_zero) return;
+  // rare: exact zero singular values -> complete U (workgroup 0, wave 0)
+  grid_barrier(ctr, (++nbar) * (unsigned)P, err);
+  if (wg != 0 || wave != 0) return;
+  int cand = 0;
+  for (int qo = 0; qo < k; ++qo) {
+    const int src = perm[qo];
+    if (dn[src] > 0.0) continue;
+    // sign of v for this column
+    const double* vc = V + (i64)src * k;
+    double mx = 0.0;
+    int idx = k;
+    for (int e = 0; e < kJRows; ++e) {
+      const int r = lane + WAVE * e;
+      if (r < k && (fabs(vc[r]) > mx || idx == k)) {
+        mx = fabs(vc[r]);
+        idx = r;
+      }
+    }
+    const double gmx = wave_max(mx);
+    int ci = (mx == gmx && idx < k) ? idx : k;
+    for (int off = 32; off > 0; off >>= 1) ci = min(ci, __shfl_xor(ci, off, WAVE));
+    if (ci >= k) ci = 0;
+    const double sg = vc[ci] < 0.0 ? -1.0 : 1.0;
+    while (cand < k) {
+      double x[kJRows];
 #pragma unroll
-        for (int e = 0; e < kJRows; ++e) x[e] = (lane + WAVE * e) == cand ? 1.0 : 0.0;
-        ++cand;
-        for (int pass = 0; pass < 2; ++pass) {
-          // x -= Us (Us^T x), columns of Us in order
-          double y[kJRows];
+      for (int e = 0; e < kJRows; ++e) x[e] = (lane + WAVE * e) == cand ? 1.0 : 0.0;
+      ++cand;
+      for (int pass = 0; pass < 2; ++pass) {
+        double y[kJRows];
 #pragma unroll
-          for (int e = 0; e < kJRows; ++e) y[e] = x[e];
-          for (int c = 0; c < k; ++c) {
-            const double* uc = Us + (i64)c * k;
-            double s = 0.0;
-#pragma unroll
-            for (int e = 0; e < kJRows; ++e) {
-              const int r = lane + WAVE * e;
-              if (r < k) s += uc[r] * x[e];
-            }
-            s = wave_sum(s);
-#pragma unroll
-            for (int e = 0; e < kJRows; ++e) {
-              const int r = lane + WAVE * e;
-              if (r < k) y[e] -= uc[r] * s;
-            }
-          }
-#pragma unroll
-          for (int e = 0; e < kJRows; ++e) x[e] = y[e];
-        }
-        double nr = 0.0;
-#pragma unroll
-        for (int e = 0; e < kJRows; ++e) nr += x[e] * x[e];
-        nr = sqrt(wave_sum(nr));
-        if (nr > 0.5) {
-          const double s = sgn[qo] / nr;
+        for (int e = 0; e < kJRows; ++e) y[e] = x[e];
+        for (int c = 0; c < k; ++c) {
+          const double* uc = Us + (i64)c * k;
+          double s = 0.0;
 #pragma unroll
           for (int e = 0; e < kJRows; ++e) {
             const int r = lane + WAVE * e;
-            if (r < k) Us[r + (i64)qo * k] = s * x[e];
+            if (r < k) s += uc[r] * x[e];
           }
-          break;
+          s = wave_sum(s);
+#pragma unroll
+          for (int e = 0; e < kJRows; ++e) {
+            const int r = lane + WAVE * e;
+            if (r < k) y[e] -= uc[r] * s;
+          }
         }
+#pragma unroll
+        for (int e = 0; e < kJRows; ++e) x[e] = y[e];
+      }
+      double nr = 0.0;
+#pragma unroll
+      for (int e = 0; e < kJRows; ++e) nr += x[e] * x[e];
+      nr = sqrt(wave_sum(nr));
+      if (nr > 0.5) {
+        const double s = sg / nr;
+#pragma unroll
+        for (int e = 0; e < kJRows; ++e) {
+          const int r = lane + WAVE * e;
+          if (r < k) Us[r + (i64)qo * k] = s * x[e];
+        }
+        break;
       }
     }
   }
+}
+
+__global__ void jacobi_zero_kernel(unsigned* ctr, int* status) {
+  if (threadIdx.x < 2) ctr[threadIdx.x] = 0u;
+  if (threadIdx.x < 3) status[threadIdx.x] = 0;
 }
 
 int jacobi_svd(hipStream_t st, i64 k, const double* R, i64 ldr, double* d, double* Us, double* Vs,
                double* work, int* status) {
   if (k <= 0) return RANDUTV_OK;
   if (k > kJacobiMaxN) return RANDUTV_ERR_TOO_LARGE;
+  const int P = (int)std::max<i64>(1, std::min<i64>(kJMaxWG, cdiv(k, 2 * kJBW)));
+  unsigned* ctr = reinterpret_cast<unsigned*>(work + 2 * k * k);
   LaunchTimer* tm = launch_timer();
+  jacobi_zero_kernel<<<1, 64, 0, st>>>(ctr, status);
+  RUTV_TRY(hipGetLastError());
   if (tm) tm->begin(st, K_JACOBI);
-  jacobi_kernel<<<1, kJThreads, 0, st>>>((int)k, R, ldr, d, Us, Vs, work, status);
+  jacobi_block_kernel<<<P, kJThreads, 0, st>>>((int)k, R, ldr, d, Us, Vs, work, ctr, status);
   RUTV_TRY(hipGetLastError());
   if (tm) tm->end(st, K_JACOBI, 0.0);
   return RANDUTV_OK;

@@ -173,7 +173,7 @@ struct Carver {
 struct FactorWS {
   double *G, *Y, *Zp, *WV, *ZV, *TV, *tauV, *Gram, *X, *WU, *ZU, *TU, *tauU, *X3, *Rb;
   double *dall, *Usall, *Vsall, *jwork, *splitk, *panel;
-  int* status;  // [0] finite flag, [1] panel sync error, [2 + 2i] sweeps, [3 + 2i] converged
+  int* status;  // [0] finite flag, [1] panel sync error, [2 + 3i ..] sweeps, converged, sync error
   unsigned* bar;
   i64 splitk_elems;
 };
@@ -235,7 +235,7 @@ static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wa
   w.splitk_elems = splitk_need(m, n, b, q, wantU, wantV);
   w.splitk = c.take<double>(w.splitk_elems);
   w.panel = c.take<double>(panel_work_elems(mx));
-  w.status = c.take<int>(2 + 2 * nsteps);
+  w.status = c.take<int>(2 + 3 * nsteps);
   w.bar = c.take<unsigned>(64);
   return c.off;
 }
@@ -291,12 +291,19 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     ~Reset() { set_launch_timer(nullptr); }
   } reset_timer;
 
-  RUTV_TRY(hipMemsetAsync(w.status, 0, sizeof(int) * (2 + 2 * nsteps), st));
+  RUTV_TRY(hipMemsetAsync(w.status, 0, sizeof(int) * (2 + 3 * nsteps), st));
   // T := A (checking finiteness on the way)
   if (T != A)
     RUTV_CHECK(copy_check(st, m, n, A, lda, T, ldt, &w.status[0]));
   else
     RUTV_CHECK(check_finite(st, m, n, T, ldt, &w.status[0]));
+  {
+    // refuse non-finite input before any factorization kernel runs
+    int flag = 0;
+    RUTV_TRY(hipMemcpyAsync(&flag, &w.status[0], sizeof(int), hipMemcpyDeviceToHost, st));
+    RUTV_TRY(hipStreamSynchronize(st));
+    if (flag) return RANDUTV_ERR_NONFINITE;
+  }
   if (wantU) RUTV_CHECK(set_identity(st, m, U, ldu));
   if (wantV) RUTV_CHECK(set_identity(st, n, V, ldv));
 
@@ -333,7 +340,7 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     double* d = w.dall + i * b;
     double* Us = w.Usall + i * b * b;
     double* Vs = w.Vsall + i * b * b;
-    RUTV_CHECK(jacobi_svd(st, bi, w.Rb, bi, d, Us, Vs, w.jwork, &w.status[2 + 2 * i]));
+    RUTV_CHECK(jacobi_svd(st, bi, w.Rb, bi, d, Us, Vs, w.jwork, &w.status[2 + 3 * i]));
     RUTV_CHECK(set_diag_block(st, bi, d, Bm, ldt));
     if (s > 0) {
       RUTV_CHECK(gemm(st, w, false, false, s, bi, bi, 1.0, T + s * ldt, ldt, Vs, bi, 0.0, w.X, s));
@@ -363,14 +370,16 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
   }
   RUTV_TRY(hipStreamSynchronize(st));
   if (cx.timing) cx.timer.collect();
-  std::vector<int> stat(2 + 2 * nsteps);
+  std::vector<int> stat(2 + 3 * nsteps);
   RUTV_TRY(hipMemcpy(stat.data(), w.status, sizeof(int) * stat.size(), hipMemcpyDeviceToHost));
   cx.sweeps.assign(nsteps, 0);
-  for (i64 i = 0; i < nsteps; ++i) cx.sweeps[i] = stat[2 + 2 * i];
+  for (i64 i = 0; i < nsteps; ++i) cx.sweeps[i] = stat[2 + 3 * i];
   if (stat[0]) return RANDUTV_ERR_NONFINITE;
   if (stat[1]) return RANDUTV_ERR_SYNC;
   for (i64 i = 0; i < nsteps; ++i)
-    if (!stat[3 + 2 * i]) return RANDUTV_ERR_NOCONV;
+    if (stat[4 + 3 * i]) return RANDUTV_ERR_SYNC;
+  for (i64 i = 0; i < nsteps; ++i)
+    if (!stat[3 + 3 * i]) return RANDUTV_ERR_NOCONV;
   return RANDUTV_OK;
 }
 
@@ -565,11 +574,20 @@ int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d, double* Us
   double* wk = r.take<double>(jacobi_work_elems(k));
   int* status = r.take<int>(4);
   set_launch_timer(nullptr);
+  {
+    int flag = 0;
+    RUTV_TRY(hipMemsetAsync(status, 0, sizeof(int), cx.st));
+    RUTV_CHECK(check_finite(cx.st, k, k, R, ldr, status));
+    RUTV_TRY(hipMemcpyAsync(&flag, status, sizeof(int), hipMemcpyDeviceToHost, cx.st));
+    RUTV_TRY(hipStreamSynchronize(cx.st));
+    if (flag) return RANDUTV_ERR_NONFINITE;
+  }
   RUTV_CHECK(jacobi_svd(cx.st, k, R, ldr, d, Us, Vs, wk, status));
-  int hs[2] = {0, 0};
+  int hs[3] = {0, 0, 0};
   RUTV_TRY(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, cx.st));
   RUTV_TRY(hipStreamSynchronize(cx.st));
   if (sweeps) *sweeps = hs[0];
+  if (hs[2]) return RANDUTV_ERR_SYNC;
   return hs[1] ? RANDUTV_OK : RANDUTV_ERR_NOCONV;
 }
 

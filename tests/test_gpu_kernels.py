@@ -139,3 +139,11 @@ def test_gesvj_degenerate():
     Uo, do, Vo, _, _ = ro.jacobi_svd(R)
     assert to_host(d)[-1] == 0.0
     np.testing.assert_allclose(to_host(Us), Uo, atol=1e-12)
+
+
+def test_gesvj_rejects_nonfinite():
+    R = np.triu(np.ones((40, 40)))
+    R[3, 7] = np.nan
+    with pytest.raises(pkg.RandUTVError) as e:
+        pkg.randutv_gesvj(to_dev(R))
+    assert e.value.code == 3
