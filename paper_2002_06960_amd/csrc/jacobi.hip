@@ -83,16 +83,28 @@ __device__ __forceinline__ int jacobi_pair(int k, int lane, double tol, double* 
   return 1;
 }
 
-// global work layout: W (k x k, ld k), V (k x k, ld k), then counters:
+// Batched: problem p = blockIdx.x / P uses R + p rs, d + p ds, Us/Vs + p us,
+// work + p ws, status + 3 p; every problem is k x k except the last (k_last).
+// Per-problem work layout: W (k x k, ld k), V (k x k, ld k), then counters:
 // ctr[0] barrier, ctr[1] cumulative rotation count
-__global__ __launch_bounds__(kJThreads) void jacobi_block_kernel(int k, const double* __restrict__ R,
-                                                                 i64 ldr, double* __restrict__ d,
-                                                                 double* __restrict__ Us,
-                                                                 double* __restrict__ Vs,
-                                                                 double* __restrict__ work,
-                                                                 unsigned* __restrict__ ctr,
-                                                                 int* __restrict__ status) {
-  const int P = gridDim.x, wg = blockIdx.x;
+__global__ __launch_bounds__(kJThreads) void jacobi_block_kernel(int kfull, int k_last, int P,
+                                                                 const double* __restrict__ Rall,
+                                                                 i64 ldr, i64 rs,
+                                                                 double* __restrict__ dall, i64 ds,
+                                                                 double* __restrict__ Usall,
+                                                                 double* __restrict__ Vsall, i64 us,
+                                                                 double* __restrict__ wall, i64 ws,
+                                                                 int* __restrict__ stall) {
+  const int prob = blockIdx.x / P, wg = blockIdx.x % P;
+  const int count = gridDim.x / P;
+  const int k = prob == count - 1 ? k_last : kfull;
+  const double* R = Rall + prob * rs;
+  double* d = dall + prob * ds;
+  double* Us = Usall + prob * us;
+  double* Vs = Vsall + prob * us;
+  double* work = wall + prob * ws;
+  int* status = stall + 3 * prob;
+  unsigned* ctr = reinterpret_cast<unsigned*>(work + 2 * (i64)kfull * kfull);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nblk = 2 * P;
   double* W = work;
@@ -319,25 +331,37 @@ __global__ __launch_bounds__(kJThreads) void jacobi_block_kernel(int k, const do
   }
 }
 
-__global__ void jacobi_zero_kernel(unsigned* ctr, int* status) {
-  if (threadIdx.x < 2) ctr[threadIdx.x] = 0u;
-  if (threadIdx.x < 3) status[threadIdx.x] = 0;
+__global__ void jacobi_zero_kernel(int count, int kfull, double* __restrict__ wall, i64 ws,
+                                   int* __restrict__ stall) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  unsigned* ctr = reinterpret_cast<unsigned*>(wall + p * ws + 2 * (i64)kfull * kfull);
+  ctr[0] = 0u;
+  ctr[1] = 0u;
+  stall[3 * p] = stall[3 * p + 1] = stall[3 * p + 2] = 0;
+}
+
+int jacobi_svd_batched(hipStream_t st, int count, i64 k, i64 k_last, const double* R, i64 ldr,
+                       i64 rs, double* d, i64 ds, double* Us, double* Vs, i64 us, double* work,
+                       int* status) {
+  if (count <= 0 || k <= 0) return RANDUTV_OK;
+  if (k > kJacobiMaxN || k_last > k || k_last <= 0) return RANDUTV_ERR_TOO_LARGE;
+  const int P = (int)std::max<i64>(1, std::min<i64>(kJMaxWG, cdiv(k, 2 * kJBW)));
+  const i64 ws = jacobi_work_elems(k);
+  LaunchTimer* tm = launch_timer();
+  jacobi_zero_kernel<<<(count + 63) / 64, 64, 0, st>>>(count, (int)k, work, ws, status);
+  RUTV_TRY(hipGetLastError());
+  if (tm) tm->begin(st, K_JACOBI);
+  jacobi_block_kernel<<<P * count, kJThreads, 0, st>>>((int)k, (int)k_last, P, R, ldr, rs, d, ds, Us,
+                                                       Vs, us, work, ws, status);
+  RUTV_TRY(hipGetLastError());
+  if (tm) tm->end(st, K_JACOBI, 0.0);
+  return RANDUTV_OK;
 }
 
 int jacobi_svd(hipStream_t st, i64 k, const double* R, i64 ldr, double* d, double* Us, double* Vs,
                double* work, int* status) {
-  if (k <= 0) return RANDUTV_OK;
-  if (k > kJacobiMaxN) return RANDUTV_ERR_TOO_LARGE;
-  const int P = (int)std::max<i64>(1, std::min<i64>(kJMaxWG, cdiv(k, 2 * kJBW)));
-  unsigned* ctr = reinterpret_cast<unsigned*>(work + 2 * k * k);
-  LaunchTimer* tm = launch_timer();
-  jacobi_zero_kernel<<<1, 64, 0, st>>>(ctr, status);
-  RUTV_TRY(hipGetLastError());
-  if (tm) tm->begin(st, K_JACOBI);
-  jacobi_block_kernel<<<P, kJThreads, 0, st>>>((int)k, R, ldr, d, Us, Vs, work, ctr, status);
-  RUTV_TRY(hipGetLastError());
-  if (tm) tm->end(st, K_JACOBI, 0.0);
-  return RANDUTV_OK;
+  return jacobi_svd_batched(st, 1, k, k, R, ldr, 0, d, 0, Us, Vs, 0, work, status);
 }
 
 }  // namespace rutv

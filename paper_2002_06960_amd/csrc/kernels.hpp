@@ -53,9 +53,15 @@ int larft_from_gram(hipStream_t st, i64 k, const double* G, i64 ldg,
 constexpr int kJacobiMaxN = 256;
 constexpr int kJacobiMaxSweeps = 30;
 i64 jacobi_work_elems(i64 k);
-// status[0] = sweeps, status[1] = converged flag (device ints)
+// status[0] = sweeps, status[1] = converged flag, status[2] = barrier error (device ints)
 int jacobi_svd(hipStream_t st, i64 k, const double* R, i64 ldr, double* d, double* Us,
                double* Vs, double* work, int* status);
+// count independent SVDs in one launch: problem p is R + p*rs (k x k, ld ldr;
+// the last one k_last x k_last), outputs d + p*ds, Us/Vs + p*us (ld = its k),
+// work + p*jacobi_work_elems(k), status + 3p.
+int jacobi_svd_batched(hipStream_t st, int count, i64 k, i64 k_last, const double* R, i64 ldr,
+                       i64 rs, double* d, i64 ds, double* Us, double* Vs, i64 us, double* work,
+                       int* status);
 
 // ---- sketch and utilities (util.hip) ----------------------------------------
 int sketch(hipStream_t st, uint64_t seed, uint64_t step, i64 rows, i64 cols, double* G,

@@ -106,12 +106,19 @@ struct EventTimer final : LaunchTimer {
 };
 
 // ---------------------------------------------------------------------------
-// per-process library state: stream, workspace, timing
+// per-process library state: streams, events, workspace, timing
 // ---------------------------------------------------------------------------
+enum { ST_T = 0, ST_P, ST_UV, ST_S, NSTREAMS };
+constexpr int kEvRing = 4;  // events of a kind are reused every kEvRing steps
+enum { EV_V = 0, EV_COLS, EV_U, EV_UV, EV_KINDS };
+
 struct Context {
   std::mutex mu;
   int device = -1;
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;  // == streams[ST_T]
+  hipStream_t streams[NSTREAMS] = {};
+  hipEvent_t ev[EV_KINDS][kEvRing] = {};
+  hipEvent_t ev_misc[4] = {};
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool timing = false;
@@ -123,20 +130,27 @@ struct Context {
     RUTV_TRY(hipGetDevice(&dev));
     if (st && dev == device) return RANDUTV_OK;
     if (st) {
-      (void)hipStreamDestroy(st);
+      for (auto& x : streams) (void)hipStreamDestroy(x);
+      for (auto& kind : ev)
+        for (auto& e : kind) (void)hipEventDestroy(e);
+      for (auto& e : ev_misc) (void)hipEventDestroy(e);
       st = nullptr;
       if (ws) (void)hipFree(ws);
       ws = nullptr;
       ws_bytes = 0;
     }
     device = dev;
-    RUTV_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    for (auto& x : streams) RUTV_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    for (auto& kind : ev)
+      for (auto& e : kind) RUTV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& e : ev_misc) RUTV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    st = streams[ST_T];
     return RANDUTV_OK;
   }
   int reserve(size_t bytes) {
     if (bytes <= ws_bytes) return RANDUTV_OK;
     if (ws) {
-      RUTV_TRY(hipStreamSynchronize(st));
+      RUTV_TRY(hipDeviceSynchronize());
       (void)hipFree(ws);
       ws = nullptr;
       ws_bytes = 0;
@@ -170,12 +184,24 @@ struct Carver {
   }
 };
 
+// scratch owned by one stream
+struct StreamWS {
+  double* splitk = nullptr;
+  i64 splitk_elems = 0;
+  double* Gram = nullptr;  // b x b
+  double* Tf = nullptr;    // b x b
+  double* X = nullptr;     // max(m, n) x b
+  PanelWork pw;
+};
+
+constexpr int kSvdGroup = 8;  // SVDs per batched launch
+
 struct FactorWS {
-  double *G, *Y, *Zp, *WV, *ZV, *TV, *tauV, *Gram, *X, *WU, *ZU, *TU, *tauU, *X3, *Rb;
-  double *dall, *Usall, *Vsall, *jwork, *splitk, *panel;
+  StreamWS sw[NSTREAMS];
+  double *G, *Y, *Zp, *tauV, *tauU, *X3;
+  double *WV[2], *ZV[2], *WU[2], *ZU[2];
+  double *Rall, *dall, *Usall, *Vsall, *jwork;
   int* status;  // [0] finite flag, [1] panel sync error, [2 + 3i ..] sweeps, converged, sync error
-  unsigned* bar;
-  i64 splitk_elems;
 };
 
 static i64 splitk_need(i64 m, i64 n, i64 b, int q, bool wantU, bool wantV) {
@@ -188,10 +214,12 @@ static i64 splitk_need(i64 m, i64 n, i64 b, int q, bool wantU, bool wantV) {
     upd(bi, bi, ni);
     upd(ni, bi, bi);
     upd(m, bi, ni);
-    upd(m, ni, bi);
+    upd(m, bi, bi);
+    upd(m, ni - bi, bi);
     if (wantV) {
       upd(n, bi, ni);
       upd(n, ni, bi);
+      upd(n, bi, bi);
     }
     upd(bi, bi, mi);
     upd(mi, bi, bi);
@@ -213,57 +241,69 @@ static i64 splitk_need(i64 m, i64 n, i64 b, int q, bool wantU, bool wantV) {
 static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wantU, bool wantV) {
   const i64 nsteps = cdiv(n, b);
   const i64 mx = std::max(m, n);
+  const i64 sk = splitk_need(m, n, b, q, wantU, wantV);
+  for (int t = 0; t < NSTREAMS; ++t) {
+    StreamWS& x = w.sw[t];
+    x.splitk_elems = sk;
+    x.splitk = c.take<double>(sk);
+    x.Gram = c.take<double>(b * b);
+    x.Tf = c.take<double>(b * b);
+    x.X = c.take<double>(mx * b);
+    x.pw.part = c.take<double>(panel_work_elems(mx));
+    x.pw.bar = c.take<unsigned>(64);
+  }
   w.G = c.take<double>(m * b);
   w.Y = c.take<double>(n * b);
   w.Zp = c.take<double>(m * b);
-  w.WV = c.take<double>(n * b);
-  w.ZV = c.take<double>(n * b);
-  w.TV = c.take<double>(b * b);
   w.tauV = c.take<double>(b);
-  w.Gram = c.take<double>(b * b);
-  w.X = c.take<double>(mx * b);
-  w.WU = c.take<double>(m * b);
-  w.ZU = c.take<double>(m * b);
-  w.TU = c.take<double>(b * b);
   w.tauU = c.take<double>(b);
   w.X3 = c.take<double>(b * n);
-  w.Rb = c.take<double>(b * b);
+  for (int t = 0; t < 2; ++t) {
+    w.WV[t] = c.take<double>(n * b);
+    w.ZV[t] = c.take<double>(n * b);
+    w.WU[t] = c.take<double>(m * b);
+    w.ZU[t] = c.take<double>(m * b);
+  }
+  w.Rall = c.take<double>(nsteps * b * b);
   w.dall = c.take<double>(nsteps * b);
   w.Usall = c.take<double>(nsteps * b * b);
   w.Vsall = c.take<double>(nsteps * b * b);
-  w.jwork = c.take<double>(jacobi_work_elems(b));
-  w.splitk_elems = splitk_need(m, n, b, q, wantU, wantV);
-  w.splitk = c.take<double>(w.splitk_elems);
-  w.panel = c.take<double>(panel_work_elems(mx));
+  w.jwork = c.take<double>(kSvdGroup * jacobi_work_elems(b));
   w.status = c.take<int>(2 + 3 * nsteps);
-  w.bar = c.take<unsigned>(64);
   return c.off;
 }
 
-static int gemm(hipStream_t st, const FactorWS& w, bool ta, bool tb, i64 M, i64 N, i64 K,
+static int gemm(hipStream_t st, const StreamWS& x, bool ta, bool tb, i64 M, i64 N, i64 K,
                 double alpha, const double* A, i64 lda, const double* B, i64 ldb, double beta,
                 double* C, i64 ldc) {
-  return dgemm(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, w.splitk,
-               w.splitk_elems);
+  return dgemm(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, x.splitk, x.splitk_elems);
 }
 
 // compact-WY factor of the reflectors in P (rows x k, ld ldp): W explicit,
 // T from the Gram matrix, Z = W T^T
-static int wy_factor(hipStream_t st, const FactorWS& w, i64 rows, i64 k, double* P, i64 ldp,
-                     const double* tau, double* W, double* Tf, double* Z, double* R,
-                     bool zero_panel) {
-  RUTV_CHECK(extract_reflectors(st, rows, k, P, ldp, W, rows, R, k, zero_panel));
-  RUTV_CHECK(gemm(st, w, true, false, k, k, rows, 1.0, W, rows, W, rows, 0.0, w.Gram, k));
-  RUTV_CHECK(larft_from_gram(st, k, w.Gram, k, tau, Tf, k));
-  RUTV_CHECK(gemm(st, w, false, true, rows, k, k, 1.0, W, rows, Tf, k, 0.0, Z, rows));
+static int wy_factor(hipStream_t st, const StreamWS& x, i64 rows, i64 k, double* P, i64 ldp,
+                     const double* tau, double* W, double* Z, double* R, i64 ldr, bool zero_panel) {
+  RUTV_CHECK(extract_reflectors(st, rows, k, P, ldp, W, rows, R, ldr, zero_panel));
+  RUTV_CHECK(gemm(st, x, true, false, k, k, rows, 1.0, W, rows, W, rows, 0.0, x.Gram, k));
+  RUTV_CHECK(larft_from_gram(st, k, x.Gram, k, tau, x.Tf, k));
+  RUTV_CHECK(gemm(st, x, false, true, rows, k, k, 1.0, W, rows, x.Tf, k, 0.0, Z, rows));
   return RANDUTV_OK;
 }
 
-// C(rows x cols, ld ldc) <- C (I - W T W^T) = C - (C W) Z^T, X scratch (rows x k)
-static int right_apply(hipStream_t st, const FactorWS& w, i64 rows, i64 cols, i64 k, double* C,
-                       i64 ldc, const double* W, const double* Z, double* X) {
-  RUTV_CHECK(gemm(st, w, false, false, rows, k, cols, 1.0, C, ldc, W, cols, 0.0, X, rows));
-  RUTV_CHECK(gemm(st, w, false, true, rows, cols, k, -1.0, X, rows, Z, cols, 1.0, C, ldc));
+// C(rows x cols, ld ldc) <- C (I - W T W^T) = C - (C W) Z^T, W/Z: cols x k (ld cols)
+static int right_apply(hipStream_t st, const StreamWS& x, i64 rows, i64 cols, i64 k, double* C,
+                       i64 ldc, const double* W, const double* Z) {
+  RUTV_CHECK(gemm(st, x, false, false, rows, k, cols, 1.0, C, ldc, W, cols, 0.0, x.X, rows));
+  RUTV_CHECK(gemm(st, x, false, true, rows, cols, k, -1.0, x.X, rows, Z, cols, 1.0, C, ldc));
+  return RANDUTV_OK;
+}
+
+// C(rows x k, ld ldc) <- C S (S: k x k, ld k), through the stream's X buffer
+static int right_mul_small(hipStream_t st, const StreamWS& x, i64 rows, i64 k, double* C, i64 ldc,
+                           const double* S) {
+  if (rows <= 0) return RANDUTV_OK;
+  RUTV_CHECK(gemm(st, x, false, false, rows, k, k, 1.0, C, ldc, S, k, 0.0, x.X, rows));
+  RUTV_CHECK(copy_matrix(st, rows, k, x.X, rows, C, ldc));
   return RANDUTV_OK;
 }
 
@@ -271,11 +311,13 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
                        double* U, double* T, double* V) {
   Context& cx = ctx();
   RUTV_CHECK(cx.init());
-  hipStream_t st = cx.st;
+  hipStream_t sT = cx.streams[ST_T], sP = cx.streams[ST_P], sUV = cx.streams[ST_UV],
+              sS = cx.streams[ST_S];
   const bool wantU = U != nullptr, wantV = V != nullptr;
   const i64 ldt = m, ldu = m, ldv = n;
   if (b > n) b = n;
   const i64 nsteps = cdiv(n, b);
+  const i64 b_last = n - (nsteps - 1) * b;
 
   FactorWS w{};
   Carver probe;
@@ -284,97 +326,122 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
   Carver real;
   real.base = cx.ws;
   layout(real, w, m, n, b, q, wantU, wantV);
+  for (auto& x : w.sw) x.pw.err = &w.status[1];
+  const StreamWS &xT = w.sw[ST_T], &xP = w.sw[ST_P], &xUV = w.sw[ST_UV], &xS = w.sw[ST_S];
 
   cx.timer.start_call();
   set_launch_timer(cx.timing ? &cx.timer : nullptr);
   struct Reset {
     ~Reset() { set_launch_timer(nullptr); }
   } reset_timer;
+  auto ev = [&](int kind, i64 i) { return cx.ev[kind][i % kEvRing]; };
 
-  RUTV_TRY(hipMemsetAsync(w.status, 0, sizeof(int) * (2 + 3 * nsteps), st));
-  // T := A (checking finiteness on the way)
+  // ---- prologue (stream T): status, T := A with a finiteness check
+  RUTV_TRY(hipMemsetAsync(w.status, 0, sizeof(int) * (2 + 3 * nsteps), sT));
   if (T != A)
-    RUTV_CHECK(copy_check(st, m, n, A, lda, T, ldt, &w.status[0]));
+    RUTV_CHECK(copy_check(sT, m, n, A, lda, T, ldt, &w.status[0]));
   else
-    RUTV_CHECK(check_finite(st, m, n, T, ldt, &w.status[0]));
+    RUTV_CHECK(check_finite(sT, m, n, T, ldt, &w.status[0]));
   {
-    // refuse non-finite input before any factorization kernel runs
     int flag = 0;
-    RUTV_TRY(hipMemcpyAsync(&flag, &w.status[0], sizeof(int), hipMemcpyDeviceToHost, st));
-    RUTV_TRY(hipStreamSynchronize(st));
+    RUTV_TRY(hipMemcpyAsync(&flag, &w.status[0], sizeof(int), hipMemcpyDeviceToHost, sT));
+    RUTV_TRY(hipStreamSynchronize(sT));
     if (flag) return RANDUTV_ERR_NONFINITE;
   }
-  if (wantU) RUTV_CHECK(set_identity(st, m, U, ldu));
-  if (wantV) RUTV_CHECK(set_identity(st, n, V, ldv));
+  if (wantU) RUTV_CHECK(set_identity(sUV, m, U, ldu));
+  if (wantV) RUTV_CHECK(set_identity(sUV, n, V, ldv));
 
-  PanelWork pw;
-  pw.part = w.panel;
-  pw.bar = w.bar;
-  pw.err = &w.status[1];
-
-  i64 s = 0;
+  i64 s = 0, g0 = 0;
   for (i64 i = 0; s < n; ++i) {
     const i64 bi = std::min(b, n - s), e = s + bi, mi = m - s, ni = n - s;
+    const int buf = (int)(i & 1);
     double* Bm = T + s + s * ldt;
-    // ---- right transform: sketch, power iteration, QR(Y), T(:, s:n) and V updates
-    RUTV_CHECK(sketch(st, seed, (uint64_t)i, mi, bi, w.G, mi));
-    RUTV_CHECK(gemm(st, w, true, false, ni, bi, mi, 1.0, Bm, ldt, w.G, mi, 0.0, w.Y, ni));
+    // ---- stream T: sketch, power iteration, QR(Y), compact WY of V^
+    if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_UV, i - 2), 0));  // WV/ZV[buf] free
+    RUTV_CHECK(sketch(sT, seed, (uint64_t)i, mi, bi, w.G, mi));
+    RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.G, mi, 0.0, w.Y, ni));
     for (int it = 0; it < q; ++it) {
-      RUTV_CHECK(gemm(st, w, false, false, mi, bi, ni, 1.0, Bm, ldt, w.Y, ni, 0.0, w.Zp, mi));
-      RUTV_CHECK(gemm(st, w, true, false, ni, bi, mi, 1.0, Bm, ldt, w.Zp, mi, 0.0, w.Y, ni));
+      RUTV_CHECK(gemm(sT, xT, false, false, mi, bi, ni, 1.0, Bm, ldt, w.Y, ni, 0.0, w.Zp, mi));
+      RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.Zp, mi, 0.0, w.Y, ni));
     }
-    RUTV_CHECK(panel_qr(st, ni, bi, w.Y, ni, w.tauV, pw));
-    RUTV_CHECK(wy_factor(st, w, ni, bi, w.Y, ni, w.tauV, w.WV, w.TV, w.ZV, nullptr, false));
-    RUTV_CHECK(right_apply(st, w, m, ni, bi, T + s * ldt, ldt, w.WV, w.ZV, w.X));
-    if (wantV) RUTV_CHECK(right_apply(st, w, n, ni, bi, V + s * ldv, ldv, w.WV, w.ZV, w.X));
-    // ---- left transform: QR of the column block, rest of the rows, U update
-    RUTV_CHECK(panel_qr(st, mi, bi, Bm, ldt, w.tauU, pw));
-    RUTV_CHECK(wy_factor(st, w, mi, bi, Bm, ldt, w.tauU, w.WU, w.TU, w.ZU, w.Rb, true));
+    RUTV_CHECK(panel_qr(sT, ni, bi, w.Y, ni, w.tauV, xT.pw));
+    RUTV_CHECK(wy_factor(sT, xT, ni, bi, w.Y, ni, w.tauV, w.WV[buf], w.ZV[buf], nullptr, 0, false));
+    RUTV_TRY(hipEventRecord(ev(EV_V, i), sT));
+    // right transform of all m rows: first the current column block (it
+    // feeds the panel QR on stream P), then the rest
+    RUTV_CHECK(gemm(sT, xT, false, false, m, bi, ni, 1.0, T + s * ldt, ldt, w.WV[buf], ni, 0.0, xT.X, m));
+    RUTV_CHECK(gemm(sT, xT, false, true, m, bi, bi, -1.0, xT.X, m, w.ZV[buf], ni, 1.0, T + s * ldt, ldt));
+    RUTV_TRY(hipEventRecord(ev(EV_COLS, i), sT));
+    if (e < n)
+      RUTV_CHECK(gemm(sT, xT, false, true, m, ni - bi, bi, -1.0, xT.X, m, w.ZV[buf] + bi, ni, 1.0,
+                      T + e * ldt, ldt));
+    // ---- stream P: panel QR of the column block, compact WY of U^
+    RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_COLS, i), 0));
+    if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_UV, i - 2), 0));  // WU/ZU[buf] free
+    RUTV_CHECK(panel_qr(sP, mi, bi, Bm, ldt, w.tauU, xP.pw));
+    RUTV_CHECK(wy_factor(sP, xP, mi, bi, Bm, ldt, w.tauU, w.WU[buf], w.ZU[buf], w.Rall + i * b * b, b,
+                         true));
+    RUTV_TRY(hipEventRecord(ev(EV_U, i), sP));
+    // ---- stream T: left transform of the remaining columns
+    RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_U, i), 0));
     if (e < n) {
       double* C = T + s + e * ldt;
-      RUTV_CHECK(gemm(st, w, true, false, bi, ni - bi, mi, 1.0, w.WU, mi, C, ldt, 0.0, w.X3, bi));
-      RUTV_CHECK(gemm(st, w, false, false, mi, ni - bi, bi, -1.0, w.ZU, mi, w.X3, bi, 1.0, C, ldt));
+      RUTV_CHECK(gemm(sT, xT, true, false, bi, ni - bi, mi, 1.0, w.WU[buf], mi, C, ldt, 0.0, w.X3, bi));
+      RUTV_CHECK(gemm(sT, xT, false, false, mi, ni - bi, bi, -1.0, w.ZU[buf], mi, w.X3, bi, 1.0, C, ldt));
     }
-    if (wantU) RUTV_CHECK(right_apply(st, w, m, mi, bi, U + s * ldu, ldu, w.WU, w.ZU, w.X));
-    // ---- SVD of the b_i x b_i triangular factor
-    double* d = w.dall + i * b;
-    double* Us = w.Usall + i * b * b;
-    double* Vs = w.Vsall + i * b * b;
-    RUTV_CHECK(jacobi_svd(st, bi, w.Rb, bi, d, Us, Vs, w.jwork, &w.status[2 + 3 * i]));
-    RUTV_CHECK(set_diag_block(st, bi, d, Bm, ldt));
-    if (s > 0) {
-      RUTV_CHECK(gemm(st, w, false, false, s, bi, bi, 1.0, T + s * ldt, ldt, Vs, bi, 0.0, w.X, s));
-      RUTV_CHECK(copy_matrix(st, s, bi, w.X, s, T + s * ldt, ldt));
-    }
-    if (wantV) {
-      RUTV_CHECK(gemm(st, w, false, false, n, bi, bi, 1.0, V + s * ldv, ldv, Vs, bi, 0.0, w.X, n));
-      RUTV_CHECK(copy_matrix(st, n, bi, w.X, n, V + s * ldv, ldv));
-    }
-    if (wantU) {
-      RUTV_CHECK(gemm(st, w, false, false, m, bi, bi, 1.0, U + s * ldu, ldu, Us, bi, 0.0, w.X, m));
-      RUTV_CHECK(copy_matrix(st, m, bi, w.X, m, U + s * ldu, ldu));
+    // ---- stream UV: V and U updates of this step
+    RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_V, i), 0));
+    if (wantV) RUTV_CHECK(right_apply(sUV, xUV, n, ni, bi, V + s * ldv, ldv, w.WV[buf], w.ZV[buf]));
+    RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_U, i), 0));
+    if (wantU) RUTV_CHECK(right_apply(sUV, xUV, m, mi, bi, U + s * ldu, ldu, w.WU[buf], w.ZU[buf]));
+    RUTV_TRY(hipEventRecord(ev(EV_UV, i), sUV));
+    // ---- stream S: b x b SVDs in groups, then their right factors
+    const bool last = e >= n;
+    if ((i + 1 - g0) == kSvdGroup || last) {
+      const int cnt = (int)(i + 1 - g0);
+      RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_U, i), 0));
+      RUTV_CHECK(jacobi_svd_batched(sS, cnt, b, last ? b_last : b, w.Rall + g0 * b * b, b, b * b,
+                                    w.dall + g0 * b, b, w.Usall + g0 * b * b, w.Vsall + g0 * b * b,
+                                    b * b, w.jwork, &w.status[2 + 3 * g0]));
+      for (i64 t = g0; t <= i; ++t) {
+        const i64 st_ = t * b, bt = std::min(b, n - st_);
+        const double* d = w.dall + t * b;
+        const double* Vs = w.Vsall + t * b * b;
+        const double* Us = w.Usall + t * b * b;
+        RUTV_CHECK(set_diag_block(sS, bt, d, T + st_ + st_ * ldt, ldt));
+        RUTV_CHECK(right_mul_small(sS, xS, st_, bt, T + st_ * ldt, ldt, Vs));
+        RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_UV, t), 0));
+        if (wantV) RUTV_CHECK(right_mul_small(sS, xS, n, bt, V + st_ * ldv, ldv, Vs));
+        if (wantU) RUTV_CHECK(right_mul_small(sS, xS, m, bt, U + st_ * ldu, ldu, Us));
+      }
+      g0 = i + 1;
     }
     s = e;
   }
-  // ---- deferred left factors of the SVDs: T(s:e, e:n) <- U_S^T T(s:e, e:n)
+  // ---- join, then the deferred left factors: T(s:e, e:n) <- U_S^T T(s:e, e:n)
+  RUTV_TRY(hipEventRecord(cx.ev_misc[0], sS));
+  RUTV_TRY(hipEventRecord(cx.ev_misc[1], sUV));
+  RUTV_TRY(hipEventRecord(cx.ev_misc[2], sP));
+  RUTV_TRY(hipStreamWaitEvent(sT, cx.ev_misc[0], 0));
+  RUTV_TRY(hipStreamWaitEvent(sT, cx.ev_misc[1], 0));
+  RUTV_TRY(hipStreamWaitEvent(sT, cx.ev_misc[2], 0));
   s = 0;
   for (i64 i = 0; s < n; ++i) {
     const i64 bi = std::min(b, n - s), e = s + bi;
     if (e < n) {
       const double* Us = w.Usall + i * b * b;
       double* C = T + s + e * ldt;
-      RUTV_CHECK(gemm(st, w, true, false, bi, n - e, bi, 1.0, Us, bi, C, ldt, 0.0, w.X3, bi));
-      RUTV_CHECK(copy_matrix(st, bi, n - e, w.X3, bi, C, ldt));
+      RUTV_CHECK(gemm(sT, xT, true, false, bi, n - e, bi, 1.0, Us, bi, C, ldt, 0.0, w.X3, bi));
+      RUTV_CHECK(copy_matrix(sT, bi, n - e, w.X3, bi, C, ldt));
     }
     s = e;
   }
-  RUTV_TRY(hipStreamSynchronize(st));
+  RUTV_TRY(hipStreamSynchronize(sT));
   if (cx.timing) cx.timer.collect();
   std::vector<int> stat(2 + 3 * nsteps);
   RUTV_TRY(hipMemcpy(stat.data(), w.status, sizeof(int) * stat.size(), hipMemcpyDeviceToHost));
   cx.sweeps.assign(nsteps, 0);
   for (i64 i = 0; i < nsteps; ++i) cx.sweeps[i] = stat[2 + 3 * i];
-  if (stat[0]) return RANDUTV_ERR_NONFINITE;
   if (stat[1]) return RANDUTV_ERR_SYNC;
   for (i64 i = 0; i < nsteps; ++i)
     if (stat[4 + 3 * i]) return RANDUTV_ERR_SYNC;
