@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="block steps of the same problem timed for the CPU oracle baseline (0: skip)")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the factorizations, run one plain device copy of this many MiB "
+                         "(a kernel of known HBM traffic, to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -87,6 +90,15 @@ def main():
     U = pkg.colmajor_empty(m, m, dev)
     T = pkg.colmajor_empty(m, n, dev)
     V = pkg.colmajor_empty(n, n, dev)
+    if args.copy_calibration_mib > 0:
+        nel = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {nel * 8} bytes read, {nel * 8} bytes written", file=sys.stderr)
+        del src, dst
     torch.cuda.synchronize()
     print(f"# workload randutv fp64 {m}x{n} b={b} q={q} spectrum={args.spectrum}", file=sys.stderr, flush=True)
 

@@ -6,226 +6,315 @@
 // tau_j = (beta_j - alpha_j)/beta_j, sign(0) = +1, tau_j = 0 when the part
 // below the diagonal is exactly zero.
 //
-// Panel kernel layout: P workgroups each own a contiguous slab of rows.  The
-// panel is processed in leaves of 16 columns.  Within a leaf each column
-// needs one grid-wide reduction (sum of squares below the diagonal plus the
-// dot products with the leaf's remaining columns, combined with the pivot
-// row): every workgroup publishes its partial sums, passes a grid barrier and
-// sums all partials in the same order, so every workgroup derives the
-// bit-identical reflector and updates its own rows.  After a leaf, the rest
-// of the panel receives the leaf's block reflector C <- (I - W Tl W^T)^T C
-// (Gram of the leaf vectors and W^T C reduced across workgroups).
+// Panel kernel layout: P workgroups each own a contiguous slab of at most 512
+// rows (two rows per thread).  The panel is processed in leaves of 16 columns
+// whose rows stay in registers.  Within a leaf each column needs one sum over
+// all rows (squares below the diagonal plus the dot products with the leaf's
+// remaining columns, combined with the pivot row): every workgroup publishes
+// its partial sums, reads everybody's and adds them in the same order, so all
+// workgroups derive the bit-identical reflector and update their own rows.
+// After a leaf, the rest of the panel receives the leaf's block reflector
+// C <- (I - W Tl W^T)^T C, with the Gram matrix of the leaf vectors and W^T C
+// summed over the workgroups in two rounds (each workgroup reduces a share of
+// the entries, then everybody reads the totals).
+//
+// Workgroups exchange values without grid barriers or memory fences: a double
+// travels as two 64-bit words, each holding one 32-bit half of it and the
+// 32-bit number of the exchange round, written and read with relaxed
+// device-scope atomics.  A reader polls until every word it needs carries the
+// current round number; since each word validates itself, only per-location
+// coherence is needed.  Round numbers start at 1 in every launch, whose
+// exchange area is cleared before the launch.  Column rounds alternate
+// between two buffers: a workgroup can only be one round ahead of the
+// slowest reader.
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 
 namespace rutv {
 
-constexpr int kPQMaxRows = 384;           // rows of one workgroup's slab
-constexpr int kPQThreads = 512;           // 8 waves
-constexpr int kPQWaves = kPQThreads / WAVE;
-constexpr int kPQRowsPerLane = kPQMaxRows / WAVE;  // leaf rows per lane of wave 0
-constexpr int kPQNB = 16;                 // leaf width
-constexpr int kPQLd = kPQMaxRows + 1;     // padded leading dimension of the leaf in LDS
-constexpr int kPQColPart = kPQNB + 1;
-constexpr int kPQTrail = kPQNB * kPQNB + kPQNB * kPanelMaxCols;
-constexpr int kPQMaxWG = 64;
-
+typedef unsigned long long u64;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPQThreads = 256;  // 4 waves
+constexpr int kPQWaves = kPQThreads / WAVE;
+constexpr int kPQRpt = 2;        // slab rows per thread
+constexpr int kPQMaxRows = kPQThreads * kPQRpt;
+constexpr int kPQNB = 16;                  // leaf width
+constexpr int kPQLdW = kPQMaxRows + 1;     // padded leading dimension of the leaf's W in LDS
+constexpr int kPQMaxWG = 64;
+constexpr int kPQTrail = kPQNB * kPQNB + kPQNB * (kPanelMaxCols - kPQNB);  // Gram + W^T C entries
+constexpr unsigned kPQSpinLimit = 1u << 22;
+
+// exchange area (64-bit words; a double is a pair of words)
+constexpr i64 kXCol = 0;                                 // [2][kPQMaxWG][kPQNB][2] column partials
+constexpr i64 kXPiv = kXCol + 2 * kPQMaxWG * kPQNB * 2;  // [2][kPQNB][2] pivot row
+constexpr i64 kXTot = kXPiv + 2 * kPQNB * 2;             // [kPQTrail][2] reduced trailing sums
+constexpr i64 kXPart = kXTot + kPQTrail * 2;             // [P][kPQTrail][2] trailing partials
 
 static int panel_grid(i64 m) {
   i64 P = std::max<i64>(cdiv(m, kPQMaxRows), std::min<i64>(32, cdiv(m, 128)));
   return (int)std::max<i64>(P, 1);
 }
 
-i64 panel_work_elems(i64 m) {
-  const i64 P = panel_grid(m);
-  return 2 * P * kPQColPart + 2 * kPQNB + P * kPQTrail + kPQTrail;
+static i64 panel_words(int P) { return kXPart + (i64)P * kPQTrail * 2; }
+
+i64 panel_work_elems(i64 m) { return panel_words(panel_grid(m)); }
+
+__device__ __forceinline__ void xput(u64* p, double v, unsigned tag) {
+  const u64 b = (u64)__double_as_longlong(v), t = (u64)tag << 32;
+  __hip_atomic_store(p, (b & 0xffffffffull) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 1, (b >> 32) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 xget(u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool xhas(u64 w, unsigned tag) { return (unsigned)(w >> 32) == tag; }
+__device__ __forceinline__ double xval(u64 lo, u64 hi) {
+  return __longlong_as_double((long long)((lo & 0xffffffffull) | (hi << 32)));
 }
 
-// arrival + wait of one workgroup at the panel's grid barrier, executed by a
-// single lane: release on arrival, relaxed polling, one acquire fence
-__device__ __forceinline__ void panel_arrive_wait(unsigned* counter, unsigned target, int* err) {
-  __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  unsigned spins = 0;
-  while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    __builtin_amdgcn_s_sleep(1);
-    if (++spins > kSpinLimit) {
-      __hip_atomic_store(err, RANDUTV_ERR_SYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      break;
+// one halving step of a wave reduce-scatter of kPQNB values: lanes with bit
+// OFF set keep values N..2N-1, the others 0..N-1, each adding its partner's
+template <int N, int OFF>
+__device__ __forceinline__ void reduce_scatter_step(double (&v)[kPQNB], int lane) {
+  const bool up = (lane & OFF) != 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double send = up ? v[i] : v[i + N];
+    const double keep = up ? v[i + N] : v[i];
+    v[i] = keep + __shfl_xor(send, OFF, WAVE);
+  }
+}
+
+// calls f(integral_constant<int, J>) for J = J0, J0 + 1, ... while J < n
+template <int J0>
+struct ForColumns {
+  template <class F>
+  __device__ __forceinline__ static void run(int n, F& f) {
+    if (J0 < n) {
+      f(std::integral_constant<int, J0>{});
+      ForColumns<J0 + 1>::run(n, f);
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-__device__ __forceinline__ void panel_barrier(unsigned* counter, unsigned target, int* err) {
-  __syncthreads();
-  if (threadIdx.x == 0) panel_arrive_wait(counter, target, err);
-  __syncthreads();
-}
+};
+template <>
+struct ForColumns<kPQNB> {
+  template <class F>
+  __device__ __forceinline__ static void run(int, F&) {}
+};
 
 __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, double* __restrict__ A,
                                                               i64 lda, double* __restrict__ tau,
-                                                              double* __restrict__ work,
-                                                              unsigned* __restrict__ bar,
+                                                              u64* __restrict__ xch,
                                                               int* __restrict__ err) {
-  const int P = gridDim.x, wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int P = gridDim.x, wg = blockIdx.x;
   const int r0 = (int)((i64)m * wg / P), r1 = (int)((i64)m * (wg + 1) / P), R = r1 - r0;
-  double* colpart = work;                          // [2][P][kPQColPart]
-  double* piv = colpart + 2 * P * kPQColPart;      // [2][kPQNB]
-  double* tpart = piv + 2 * kPQNB;                 // [P][kPQTrail]
-  double* ttot = tpart + (i64)P * kPQTrail;        // [kPQTrail]
 
-  // L: the leaf's slab (column a at L[a * kPQLd + r]); after the leaf, the explicit W
-  __shared__ double L[kPQNB * kPQLd];
-  // S: lane partials / gathered partials (leaf phase); reduced X, then Tl^T X
-  __shared__ double S[kPQNB * kPanelMaxCols];
-  __shared__ double tot[kPQColPart];
-  __shared__ double pv[kPQNB];
+  __shared__ double Wl[kPQNB * kPQLdW];        // explicit W of the finished leaf
+  __shared__ double S[kPQNB * kPanelMaxCols];  // X = W^T C, then Tl^T X
+  __shared__ double red[kPQWaves * kPQNB];     // per-wave column sums
+  __shared__ double pivl[kPQNB];               // pivot row (its owner only)
+  __shared__ double tsum[kPQWaves * kPQNB];    // per-wave shares of the column totals
+  __shared__ double pivs[kPQNB];               // the pivot row as read back
   __shared__ double Gs[kPQNB * kPQNB];
   __shared__ double Tl[kPQNB * kPQNB];
   __shared__ double taul[kPQNB];
-  static_assert(kPQMaxWG * kPQColPart <= kPQNB * kPanelMaxCols, "S holds the gathered partials");
-  static_assert(WAVE * kPQColPart <= kPQNB * kPanelMaxCols, "S holds the lane partials");
-  unsigned nbar = 0;
+  __shared__ int dead;
+  if (threadIdx.x == 0) dead = 0;
+  __syncthreads();
+  unsigned rnd = 0;
+
+  // a bounded wait: on expiry record the error and stop waiting for good
+  auto give_up = [&](unsigned& spins) -> bool {
+    if (*(volatile int*)&dead) return true;
+    if (++spins > kPQSpinLimit) {
+      dead = 1;
+      __hip_atomic_store(err, RANDUTV_ERR_SYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return false;
+  };
 
   for (int c0 = 0; c0 < k; c0 += kPQNB) {
     const int nbl = min(kPQNB, k - c0);
-    for (int e = tid; e < kPQNB * kPQMaxRows; e += kPQThreads) {
-      const int r = e % kPQMaxRows, c = e / kPQMaxRows;
-      L[c * kPQLd + r] = (r < R && c < nbl) ? A[(i64)(r0 + r) + (i64)(c0 + c) * lda] : 0.0;
+    // opaque zero and thread index: every address below is recomputed per leaf
+    // instead of being hoisted out of this loop (they would not fit in registers)
+    int z = 0, tid = threadIdx.x;
+    asm volatile("" : "+s"(z), "+v"(tid));
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    double* const Ab = A + z;
+    u64* const xcol = xch + z + kXCol;
+    u64* const xpiv = xch + z + kXPiv;
+    u64* const xtot = xch + z + kXTot;
+    u64* const xpart = xch + z + kXPart;
+    double row[kPQRpt][kPQNB];
+    int gr[kPQRpt];
+    bool own[kPQRpt];
+#pragma unroll
+    for (int i = 0; i < kPQRpt; ++i) {
+      const int r = tid + kPQThreads * i;
+      own[i] = r < R;
+      gr[i] = r0 + r;
+#pragma unroll
+      for (int c = 0; c < kPQNB; ++c)
+        row[i][c] = (own[i] && c < nbl) ? Ab[(i64)gr[i] + (i64)(c0 + c) * lda] : 0.0;
     }
-    __syncthreads();
 
-    // ---- the leaf's columns, one at a time, by wave 0 alone (lane l owns
-    // rows l, l + 64, ... of the slab); waves 1-3 wait at the next barrier
-    if (wave == 0) {
-      for (int jj = 0; jj < nbl; ++jj) {
-        const int j = c0 + jj;
-        // column masks (branch-free loops; L is zero outside the slab and leaf)
-        double msk[kPQNB];
+    // one column of the leaf; jj is a compile-time constant in each instance
+    auto column = [&](auto jc) {
+      constexpr int jj = decltype(jc)::value;
+      const int j = c0 + jj;
+      const unsigned tag = ++rnd;
+      int zc = 0;
+      asm volatile("" : "+s"(zc));
+      // column masks (constants: the loop is unrolled, so the leaf stays in registers)
+      double msk[kPQNB];
 #pragma unroll
-        for (int c = 0; c < kPQNB; ++c) msk[c] = (c > jj && c < nbl) ? 1.0 : 0.0;
-        double acc[kPQColPart];
+      for (int c = 0; c < kPQNB; ++c) msk[c] = c > jj ? 1.0 : 0.0;
+      double x[kPQRpt];
 #pragma unroll
-        for (int c = 0; c < kPQColPart; ++c) acc[c] = 0.0;
-#pragma unroll 2
-        for (int i = 0; i < kPQRowsPerLane; ++i) {
-          const int r = lane + WAVE * i;
-          const double x = (r0 + r > j) ? L[jj * kPQLd + r] : 0.0;
-          acc[0] += x * x;
+      for (int i = 0; i < kPQRpt; ++i) {
+        double xj = 0.0;
 #pragma unroll
-          for (int c = 0; c < kPQNB; ++c) acc[1 + c] += x * L[c * kPQLd + r];
-        }
+        for (int c = 0; c < kPQNB; ++c) xj = c == jj ? row[i][c] : xj;
+        x[i] = (own[i] && gr[i] > j) ? xj : 0.0;
+      }
+      // slot 0: squares below the diagonal; slot c > jj: dot with column c
+      double v[kPQNB];
+      v[0] = 0.0;
 #pragma unroll
-        for (int c = 0; c < kPQNB; ++c) acc[1 + c] *= msk[c];
-        // lane partials -> LDS, then lane c < 17 sums the 64 lanes in order
+      for (int i = 0; i < kPQRpt; ++i) v[0] += x[i] * x[i];
 #pragma unroll
-        for (int c = 0; c < kPQColPart; ++c) S[lane * kPQColPart + c] = acc[c];
-        __builtin_amdgcn_wave_barrier();
-        double* cp = colpart + ((j & 1) * P + wg) * kPQColPart;
-        {
-          // lane (c, h), h < 3: lanes 22h .. 22h+21 (in order), then the 3 in order
-          const int c = lane % kPQColPart, h = lane / kPQColPart;
-          double sv = 0.0;
-          if (h < 3) {
-            double v[22];
+      for (int c = 1; c < kPQNB; ++c) {
+        v[c] = 0.0;
 #pragma unroll
-            for (int i = 0; i < 22; ++i) {
-              const int w = 22 * h + i;
-              v[i] = w < WAVE ? S[w * kPQColPart + c] : 0.0;
-            }
+        for (int i = 0; i < kPQRpt; ++i) v[c] += x[i] * row[i][c];
+        v[c] *= msk[c];
+      }
+      // wave reduce-scatter: afterwards lane l holds slot l / 4
+      reduce_scatter_step<8, 32>(v, lane);
+      reduce_scatter_step<4, 16>(v, lane);
+      reduce_scatter_step<2, 8>(v, lane);
+      reduce_scatter_step<1, 4>(v, lane);
+      v[0] += __shfl_xor(v[0], 2, WAVE);
+      v[0] += __shfl_xor(v[0], 1, WAVE);
+      if ((lane & 3) == 0) red[wave * kPQNB + (lane >> 2)] = v[0];
 #pragma unroll
-            for (int i = 0; i < 22; ++i) sv += v[i];
+      for (int i = 0; i < kPQRpt; ++i)
+        if (own[i] && gr[i] == j)
+#pragma unroll
+          for (int c = 0; c < kPQNB; ++c) pivl[c] = row[i][c];
+      __syncthreads();
+
+      {
+        const int s = lane & 15, g = lane >> 4;
+        u64* const xc = xcol + zc + (i64)(tag & 1) * kPQMaxWG * kPQNB * 2;
+        u64* const xp = xpiv + zc + (i64)(tag & 1) * kPQNB * 2;
+        if (wave == 0) {
+          if (g == 0) {
+            double ts = red[s];
+#pragma unroll
+            for (int w = 1; w < kPQWaves; ++w) ts += red[w * kPQNB + s];
+            xput(xc + ((i64)wg * kPQNB + s) * 2, ts, tag);
+          } else if (g == 1 && j >= r0 && j < r1) {
+            xput(xp + s * 2, pivl[s], tag);
           }
-          const double s1 = __shfl(sv, c + kPQColPart, WAVE), s2 = __shfl(sv, c + 2 * kPQColPart, WAVE);
-          if (lane < kPQColPart) cp[lane] = (sv + s1) + s2;
         }
-        if (j >= r0 && j < r1 && lane >= jj && lane < nbl)
-          piv[(j & 1) * kPQNB + lane] = L[lane * kPQLd + (j - r0)];
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) panel_arrive_wait(bar, (++nbar) * (unsigned)P, err);
-        else ++nbar;
-        __builtin_amdgcn_wave_barrier();
-        // gather all partials and the pivot row in one batch of loads
-        const double* cpb = colpart + (j & 1) * P * kPQColPart;
-        {
-          constexpr int NG = (kPQMaxWG * kPQColPart + WAVE - 1) / WAVE;
-          double g[NG];
+        // lane (s, g) of wave w reads slot s of workgroups 4 w + g + 16 i;
+        // lanes g = 0 of wave 0 also read the pivot row
+        constexpr int NG = kPQMaxWG / (4 * kPQWaves);
+        const int wb = 4 * wave + g;
+        const bool pl = wave == 0 && g == 0;
+        u64 lo[NG], hi[NG], plo, phi;
+        unsigned spins = 0;
+        while (true) {
+          // branch-free: every lane loads valid words (clamped indices), the
+          // masks decide what counts
 #pragma unroll
           for (int i = 0; i < NG; ++i) {
-            const int e = lane + WAVE * i;
-            g[i] = e < P * kPQColPart ? cpb[e] : 0.0;
+            const int w = min(wb + 16 * i, P - 1);
+            lo[i] = xget(xc + ((i64)w * kPQNB + s) * 2);
+            hi[i] = xget(xc + ((i64)w * kPQNB + s) * 2 + 1);
           }
-          const double pvv = (lane >= jj && lane < nbl) ? piv[(j & 1) * kPQNB + lane] : 0.0;
+          plo = xget(xp + s * 2);
+          phi = xget(xp + s * 2 + 1);
+          int have = !pl | (xhas(plo, tag) & xhas(phi, tag));
 #pragma unroll
-          for (int i = 0; i < NG; ++i) {
-            const int e = lane + WAVE * i;
-            if (e < kPQMaxWG * kPQColPart) S[e] = g[i];
-          }
-          if (lane < kPQNB) pv[lane] = pvv;
+          for (int i = 0; i < NG; ++i)
+            have &= (wb + 16 * i >= P) | (xhas(lo[i], tag) & xhas(hi[i], tag));
+          if (__all(have)) break;
+          if (give_up(spins)) break;
         }
-        __builtin_amdgcn_wave_barrier();
-        if (lane < kPQColPart) {
-          // S past P * 17 holds zeros (set by the gather above)
-          double v[kPQMaxWG];
+        double acc = 0.0;
 #pragma unroll
-          for (int w = 0; w < kPQMaxWG; ++w) v[w] = S[w * kPQColPart + lane];
-          double sv = 0.0;
-#pragma unroll
-          for (int w = 0; w < kPQMaxWG; ++w) sv += v[w];
-          tot[lane] = sv;
+        for (int i = 0; i < NG; ++i) acc += wb + 16 * i < P ? xval(lo[i], hi[i]) : 0.0;
+        acc += __shfl_xor(acc, 16, WAVE);
+        acc += __shfl_xor(acc, 32, WAVE);
+        if (lane < kPQNB) {
+          tsum[wave * kPQNB + lane] = acc;
+          if (wave == 0) pivs[lane] = xval(plo, phi);
         }
-        __builtin_amdgcn_wave_barrier();
-        // every lane derives the reflector (identical arithmetic everywhere)
+      }
+      __syncthreads();
+
+      // every thread derives the reflector from the same totals
+      double t = 0.0, scale = 0.0, beta, wc[kPQNB];
+      {
+        double tot[kPQNB];
+#pragma unroll
+        for (int c = 0; c < kPQNB; ++c) {
+          tot[c] = tsum[c];
+#pragma unroll
+          for (int w = 1; w < kPQWaves; ++w) tot[c] += tsum[w * kPQNB + c];
+        }
+        double alpha = 0.0;
+#pragma unroll
+        for (int c = 0; c < kPQNB; ++c) alpha = c == jj ? pivs[c] : alpha;
         const double sq = tot[0];
-        const double alpha = pv[jj];
-        double t = 0.0, scale = 0.0, beta = alpha;
+        beta = alpha;
         if (sq != 0.0) {
           const double nrm = sqrt(alpha * alpha + sq);
           beta = alpha >= 0.0 ? -nrm : nrm;
           t = (beta - alpha) / beta;
           scale = 1.0 / (alpha - beta);
         }
-        if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < kPQNB; ++c) wc[c] = (c < nbl) ? msk[c] * (pivs[c] + scale * tot[c]) : 0.0;
+        if (tid == 0) {
           taul[jj] = t;
           if (wg == 0) tau[j] = t;
         }
-        double wc[kPQNB];
-#pragma unroll
-        for (int c = 0; c < kPQNB; ++c) wc[c] = msk[c] * (pv[c] + scale * tot[1 + c]);
-#pragma unroll 1
-        for (int i = 0; i < kPQRowsPerLane; ++i) {
-          const int r = lane + WAVE * i;
-          const int gr = r0 + r;
-          const bool live = r < R && gr >= j;
-          double row[kPQNB];
-#pragma unroll
-          for (int c = 0; c < kPQNB; ++c) row[c] = L[c * kPQLd + r];
-          const double lj = L[jj * kPQLd + r];
-          const double vr = gr > j ? lj * scale : 1.0;
-          const double tv = live ? t * vr : 0.0;
-#pragma unroll
-          for (int c = 0; c < kPQNB; ++c) row[c] -= tv * wc[c];
-#pragma unroll
-          for (int c = 0; c < kPQNB; ++c) L[c * kPQLd + r] = row[c];
-          if (live) L[jj * kPQLd + r] = gr > j ? vr : beta;
-        }
-        __builtin_amdgcn_wave_barrier();
       }
-    } else {
-      nbar += nbl;
-    }
-    __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kPQRpt; ++i) {
+        const bool live = own[i] && gr[i] >= j, below = gr[i] > j;
+        const double vr = below ? x[i] * scale : 1.0;
+        const double tv = live ? t * vr : 0.0;
+        const double nj = below ? vr : beta;
+#pragma unroll
+        for (int c = 0; c < kPQNB; ++c) {
+          row[i][c] -= tv * wc[c];
+          if (c == jj && live) row[i][c] = nj;
+        }
+      }
+    };
+    ForColumns<0>::run(nbl, column);
 
-    // leaf back to memory, then L := explicit W of the leaf (1 on the
-    // diagonal row, 0 above it, the reflector below it; zero past nbl)
-    for (int e = tid; e < kPQNB * kPQMaxRows; e += kPQThreads) {
-      const int r = e % kPQMaxRows, c = e / kPQMaxRows;
-      const int gr = r0 + r, dr = c0 + c;
-      const double lv = L[c * kPQLd + r];
-      if (r < R && c < nbl) A[(i64)gr + (i64)dr * lda] = lv;
-      L[c * kPQLd + r] = (r < R && c < nbl) ? (gr > dr ? lv : (gr == dr ? 1.0 : 0.0)) : 0.0;
+    // leaf back to memory; Wl := explicit W of the leaf (1 on the diagonal
+    // row, 0 above it, the reflector below it; zero past nbl and past the slab)
+#pragma unroll
+    for (int i = 0; i < kPQRpt; ++i) {
+      const int r = tid + kPQThreads * i;
+#pragma unroll
+      for (int c = 0; c < kPQNB; ++c) {
+        const bool live = own[i] && c < nbl;
+        if (live) Ab[(i64)gr[i] + (i64)(c0 + c) * lda] = row[i][c];
+        const int dr = c0 + c;
+        Wl[c * kPQLdW + r] = live ? (gr[i] > dr ? row[i][c] : (gr[i] == dr ? 1.0 : 0.0)) : 0.0;
+      }
     }
     __syncthreads();
 
@@ -233,28 +322,27 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
     if (ncr <= 0) break;
 
     // ---- trailing columns of the panel: C <- C - W (Tl^T (W^T C))
-    // partials on the matrix cores: wave w forms X(:, 16q:16q+16) =
-    // W_slab^T C_slab(:, 16q:16q+16) for the chunks q = w, w + 4, w + 8,
-    // w + 12; the Gram W^T W goes to wave 3 (it has at most 3 chunks)
-    double* tp = tpart + (i64)wg * kPQTrail;
     const int nchunk = (ncr + 15) / 16;
     const int lr = lane >> 4, lc = lane & 15;
+    const int E = kPQNB * kPQNB + kPQNB * ncr;  // Gram entries, then X(a, t) at 256 + a ncr + t
+    const unsigned tag1 = ++rnd, tag2 = ++rnd;
     {
-      // wave w forms X(:, 16q:16q+16) = W_slab^T C_slab(:, 16q:16q+16) for
-      // the chunks q = w, w + 8 (ncr <= 240: at most 15 chunks); the last
-      // wave (one chunk at most) also forms the Gram W^T W.  Rows are taken 4
-      // per MFMA; the C values of the next kPF row groups are in flight.
-      constexpr int kPF = 8, NQ = 2;
+      // wave w forms X(:, 16q:16q+16) = W_slab^T C_slab(:, 16q:16q+16) for the
+      // chunks q = w, w + 4, ... (ncr <= 240: at most 15 chunks); the last wave
+      // (3 chunks at most) also forms the Gram W^T W.  Rows are taken 4 per
+      // MFMA; the C values of the next kPF row groups are in flight.
+      constexpr int kPF = 8, NQ = 4;
       const bool gram = wave == kPQWaves - 1;
+      // live chunks of this wave (uniform); loads are unconditional at clamped
+      // addresses: rows past the slab meet zero rows of Wl, columns past ncr
+      // are never stored
+      const int nq = min(NQ, max(0, (nchunk - wave + kPQWaves - 1) / kPQWaves));
       const double* Ac[NQ];
-      bool cok[NQ], live[NQ];
       dbl4 acc[NQ], accg = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int qd = 0; qd < NQ; ++qd) {
-        const int tcol = 16 * (wave + kPQWaves * qd) + lc;
-        live[qd] = wave + kPQWaves * qd < nchunk;
-        cok[qd] = tcol < ncr;
-        Ac[qd] = A + (i64)(c0 + nbl + min(tcol, ncr - 1)) * lda + r0;
+        const int tcol = min(16 * (wave + kPQWaves * qd) + lc, ncr - 1);
+        Ac[qd] = Ab + (i64)(c0 + nbl + tcol) * lda + r0;
         acc[qd] = dbl4{0.0, 0.0, 0.0, 0.0};
       }
       const int nst = (R + 3) / 4;
@@ -262,10 +350,7 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
 #pragma unroll
       for (int i = 0; i < kPF; ++i)
 #pragma unroll
-        for (int qd = 0; qd < NQ; ++qd) {
-          const int r = 4 * i + lr;
-          pf[qd][i] = (cok[qd] && r < R) ? Ac[qd][r] : 0.0;
-        }
+        for (int qd = 0; qd < NQ; ++qd) pf[qd][i] = Ac[qd][min(4 * i + lr, R - 1)];
       for (int st0 = 0; st0 < nst; st0 += kPF) {
         double cv[NQ][kPF];
 #pragma unroll
@@ -273,54 +358,91 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
 #pragma unroll
           for (int qd = 0; qd < NQ; ++qd) {
             cv[qd][i] = pf[qd][i];
-            const int r = 4 * (st0 + kPF + i) + lr;
-            pf[qd][i] = (cok[qd] && r < R) ? Ac[qd][r] : 0.0;
+            pf[qd][i] = Ac[qd][min(4 * (st0 + kPF + i) + lr, R - 1)];
           }
 #pragma unroll
         for (int i = 0; i < kPF; ++i) {
           const int r = 4 * (st0 + i) + lr;
-          const double wa = r < kPQMaxRows ? L[lc * kPQLd + r] : 0.0;  // W(r, a = lc)
+          const double wa = r < kPQMaxRows ? Wl[lc * kPQLdW + min(r, kPQMaxRows - 1)] : 0.0;  // W(r, a = lc)
 #pragma unroll
           for (int qd = 0; qd < NQ; ++qd)
-            if (live[qd]) acc[qd] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, cv[qd][i], acc[qd], 0, 0, 0);
+            if (qd < nq) acc[qd] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, cv[qd][i], acc[qd], 0, 0, 0);
           if (gram) accg = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, wa, accg, 0, 0, 0);
         }
       }
-      // D(4q + lr, lc): X[a = 4q + lr][t], Gram[a][c = lc]
+      // D(4qq + lr, lc): X[a = 4qq + lr][t], Gram[a][c = lc]
+      u64* const mine = xpart + (i64)wg * kPQTrail * 2;
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
         const int a = 4 * qq + lr;
 #pragma unroll
         for (int qd = 0; qd < NQ; ++qd) {
           const int tcol = 16 * (wave + kPQWaves * qd) + lc;
-          if (live[qd] && tcol < ncr) tp[kPQNB * kPQNB + a * kPanelMaxCols + tcol] = acc[qd][qq];
+          if (qd < nq && tcol < ncr)
+            xput(mine + (i64)(kPQNB * kPQNB + a * ncr + tcol) * 2, acc[qd][qq], tag1);
         }
-        if (gram) tp[a + lc * kPQNB] = accg[qq];
+        if (gram) xput(mine + (i64)(a + lc * kPQNB) * 2, accg[qq], tag1);
       }
     }
-    panel_barrier(bar, (++nbar) * (unsigned)P, err);
-    // two-phase reduction: workgroup wg sums entries e = wg * 256 + ..., over
-    // the workgroups in order
-    for (int e = wg * kPQThreads + tid; e < kPQTrail; e += P * kPQThreads) {
-      const bool g = e < kPQNB * kPQNB;
-      const int a = g ? 0 : (e - kPQNB * kPQNB) / kPanelMaxCols;
-      const int col = g ? 0 : (e - kPQNB * kPQNB) % kPanelMaxCols;
-      double sv = 0.0;
-      if (g || (a < nbl && col < ncr)) {
-        double v[kPQMaxWG];
+    // round 1: workgroup wg sums entries [e0, e1) over all workgroups, in order
+    {
+      const int e0 = (int)((i64)E * wg / P), e1 = (int)((i64)E * (wg + 1) / P);
+      constexpr int NB = 16;
+      for (int e = e0 + tid; e < e1; e += kPQThreads) {
+        double sv = 0.0;
+        for (int w0 = 0; w0 < P; w0 += NB) {
+          u64 lo[NB], hi[NB];
+          unsigned spins = 0;
+          while (true) {
 #pragma unroll
-        for (int w = 0; w < kPQMaxWG; ++w) v[w] = w < P ? tpart[(i64)w * kPQTrail + e] : 0.0;
+            for (int i = 0; i < NB; ++i) {
+              u64* p = xpart + ((i64)min(w0 + i, P - 1) * kPQTrail + e) * 2;
+              lo[i] = xget(p);
+              hi[i] = xget(p + 1);
+            }
+            int have = 1;
 #pragma unroll
-        for (int w = 0; w < kPQMaxWG; ++w) sv += v[w];
+            for (int i = 0; i < NB; ++i) have &= (w0 + i >= P) | (xhas(lo[i], tag1) & xhas(hi[i], tag1));
+            if (have || give_up(spins)) break;
+          }
+#pragma unroll
+          for (int i = 0; i < NB; ++i) sv += w0 + i < P ? xval(lo[i], hi[i]) : 0.0;
+        }
+        xput(xtot + (i64)e * 2, sv, tag2);
       }
-      ttot[e] = sv;
     }
-    panel_barrier(bar, (++nbar) * (unsigned)P, err);
-    if (tid < kPQNB * kPQNB) {
-      Gs[tid] = ttot[tid];
-      Tl[tid] = 0.0;
+    // round 2: every workgroup reads all totals
+    {
+      constexpr int NE = kPQTrail / kPQThreads;
+      u64 lo[NE], hi[NE];
+      unsigned spins = 0;
+      while (true) {
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+          const int e = min(tid + kPQThreads * i, E - 1);
+          lo[i] = xget(xtot + (i64)e * 2);
+          hi[i] = xget(xtot + (i64)e * 2 + 1);
+        }
+        int have = 1;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) have &= (xhas(lo[i], tag2) & xhas(hi[i], tag2));
+        if (have || give_up(spins)) break;
+      }
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int e = tid + kPQThreads * i;
+        if (e < E) {
+          const double val = xval(lo[i], hi[i]);
+          if (e < kPQNB * kPQNB) {
+            Gs[e] = val;
+          } else {
+            const int a = (e - kPQNB * kPQNB) / ncr, tc = (e - kPQNB * kPQNB) % ncr;
+            S[a * kPanelMaxCols + tc] = val;
+          }
+        }
+      }
+      if (tid < kPQNB * kPQNB) Tl[tid] = 0.0;
     }
-    for (int e = tid; e < nbl * kPanelMaxCols; e += kPQThreads) S[e] = ttot[kPQNB * kPQNB + e];
     __syncthreads();
     // leaf T factor, column by column (wave 0 alone, lanes = rows):
     // T(i, c) = -tau_c sum_{l=i}^{c-1} T(i, l) G(l, c)
@@ -330,12 +452,11 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
       for (int c = 0; c < kPQNB; ++c) trow[c] = 0.0;
 #pragma unroll
       for (int c = 0; c < kPQNB; ++c) {
-        if (c >= nbl) break;
         double sdot = 0.0;
 #pragma unroll
-        for (int l = 0; l < kPQNB; ++l)
-          if (l >= lane && l < c) sdot += trow[l] * Gs[l + c * kPQNB];
-        trow[c] = lane < c ? -taul[c] * sdot : (lane == c ? taul[c] : 0.0);
+        for (int l = 0; l < c; ++l) sdot += l >= lane ? trow[l] * Gs[l + c * kPQNB] : 0.0;
+        const double tc = lane < c ? -taul[c] * sdot : (lane == c ? taul[c] : 0.0);
+        trow[c] = c < nbl ? tc : 0.0;
       }
 #pragma unroll
       for (int c = 0; c < kPQNB; ++c) Tl[lane + c * kPQNB] = trow[c];
@@ -343,14 +464,14 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
     __syncthreads();
     // S <- Tl^T X (thread t owns column t; ncr <= 240 < threads)
     if (tid < ncr) {
-      double x[kPQNB];
+      double xv[kPQNB];
 #pragma unroll
-      for (int a = 0; a < kPQNB; ++a) x[a] = a < nbl ? S[a * kPanelMaxCols + tid] : 0.0;
+      for (int a = 0; a < kPQNB; ++a) xv[a] = a < nbl ? S[a * kPanelMaxCols + tid] : 0.0;
 #pragma unroll
       for (int a = 0; a < kPQNB; ++a) {
         double sv = 0.0;
 #pragma unroll
-        for (int l = 0; l <= a; ++l) sv += Tl[l + a * kPQNB] * x[l];
+        for (int l = 0; l <= a; ++l) sv += Tl[l + a * kPQNB] * xv[l];
         S[a * kPanelMaxCols + tid] = a < nbl ? sv : 0.0;
       }
     }
@@ -358,52 +479,50 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
     // update on the matrix cores: 16-row x 16-column blocks of C -= W Y with
     // Y = S (16 x ncr); the MFMA forms the block transposed, so a lane holds
     // 4 columns of one row: C[rb + lc][t0 + 4q + lr] (16 rows per column per
-    // store).  Blocks are dealt to the waves; the next block's C is fetched
-    // while the current one is computed.
+    // store).  Blocks are dealt to the waves; the next blocks' C values are
+    // fetched while the current one is computed.
     {
       const int nrb = (R + 15) / 16;
       const int nblocks = nrb * nchunk;
       constexpr int kRing = 4;
       double ring[kRing][4];
+      // unconditional loads at clamped addresses (the stores are guarded)
       auto fetch = [&](int bi, double (&dst)[4]) {
-        const int rb = 16 * (bi % nrb), t0 = 16 * (bi / nrb);
-        const int r = rb + lc;
+        const int bc = min(bi, nblocks - 1);
+        const int rb = 16 * (bc % nrb), t0 = 16 * (bc / nrb);
+        const int r = min(rb + lc, R - 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int t = t0 + 4 * q + lr;
-          dst[q] = (bi < nblocks && r < R && t < ncr) ? A[(i64)(r0 + r) + (i64)(c0 + nbl + t) * lda] : 0.0;
+          const int tc = min(t0 + 4 * q + lr, ncr - 1);
+          dst[q] = Ab[(i64)(r0 + r) + (i64)(c0 + nbl + tc) * lda];
         }
       };
 #pragma unroll
       for (int u = 0; u < kRing; ++u) fetch(wave + kPQWaves * u, ring[u]);
-      for (int bidx = wave, it = 0; bidx < nblocks; bidx += kPQWaves, ++it) {
-        double cc[4];
-        const int slot = it % kRing;
+      for (int b0 = wave; b0 < nblocks; b0 += kPQWaves * kRing) {
 #pragma unroll
-        for (int u = 0; u < kRing; ++u)
-          if (u == slot)
+        for (int u = 0; u < kRing; ++u) {
+          const int bidx = b0 + kPQWaves * u;
+          double cc[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) cc[q] = ring[u][q];
-        double nx[4];
-        fetch(bidx + kPQWaves * kRing, nx);
+          for (int q = 0; q < 4; ++q) cc[q] = ring[u][q];
+          fetch(bidx + kPQWaves * kRing, ring[u]);
+          if (bidx < nblocks) {
+            const int rb = 16 * (bidx % nrb), t0 = 16 * (bidx / nrb);
+            dbl4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int u = 0; u < kRing; ++u)
-          if (u == slot)
+            for (int kk = 0; kk < kPQNB; kk += 4) {
+              const double yv = S[(kk + lr) * kPanelMaxCols + t0 + lc];  // Y^T(t0 + lc, kk + lr)
+              const double wv = Wl[(kk + lr) * kPQLdW + rb + lc];        // W^T(kk + lr, rb + lc)
+              d = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, wv, d, 0, 0, 0);
+            }
+            const int r = rb + lc;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) ring[u][q] = nx[q];
-        const int rb = 16 * (bidx % nrb), t0 = 16 * (bidx / nrb);
-        dbl4 d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < kPQNB; kk += 4) {
-          const double yv = S[(kk + lr) * kPanelMaxCols + t0 + lc];   // Y^T(t0 + lc, kk + lr)
-          const double wv = L[(kk + lr) * kPQLd + rb + lc];           // W^T(kk + lr, rb + lc)
-          d = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, wv, d, 0, 0, 0);
-        }
-        const int r = rb + lc;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int t = t0 + 4 * q + lr;
-          if (r < R && t < ncr) A[(i64)(r0 + r) + (i64)(c0 + nbl + t) * lda] = cc[q] - d[q];
+            for (int q = 0; q < 4; ++q) {
+              const int tc = t0 + 4 * q + lr;
+              if (r < R && tc < ncr) Ab[(i64)(r0 + r) + (i64)(c0 + nbl + tc) * lda] = cc[q] - d[q];
+            }
+          }
         }
       }
     }
@@ -417,9 +536,9 @@ int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau, cons
   const int P = panel_grid(m);
   if (P > kPQMaxWG || cdiv(m, P) > kPQMaxRows) return RANDUTV_ERR_TOO_LARGE;
   LaunchTimer* tm = launch_timer();
-  RUTV_CHECK(fill_zero_u32(st, w.bar, 1));
+  RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(w.xch), 2 * panel_words(P)));
   if (tm) tm->begin(st, K_PANEL);
-  panel_qr_kernel<<<P, kPQThreads, 0, st>>>((int)m, (int)k, A, lda, tau, w.part, w.bar, w.err);
+  panel_qr_kernel<<<P, kPQThreads, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err);
   RUTV_TRY(hipGetLastError());
   if (tm) tm->end(st, K_PANEL, 2.0 * m * k * k - 2.0 * k * k * k / 3.0);
   return RANDUTV_OK;

@@ -32,11 +32,10 @@ i64 dgemm_work_elems(i64 M, i64 N, i64 K);
 // ---- Householder panel QR and compact-WY factor (householder.hip) ----------
 constexpr int kPanelMaxCols = 256;
 struct PanelWork {
-  double* part = nullptr;   // per-workgroup partial sums
-  double* tot = nullptr;    // reduced sums
-  unsigned* bar = nullptr;  // grid barrier counter
-  int* err = nullptr;       // device status word
+  unsigned long long* xch = nullptr;  // exchange words between workgroups
+  int* err = nullptr;                 // device status word
 };
+// size (64-bit words) of PanelWork::xch for panels of up to m rows
 i64 panel_work_elems(i64 m);
 int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau,
              const PanelWork& w);

@@ -249,8 +249,7 @@ static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wa
     x.Gram = c.take<double>(b * b);
     x.Tf = c.take<double>(b * b);
     x.X = c.take<double>(mx * b);
-    x.pw.part = c.take<double>(panel_work_elems(mx));
-    x.pw.bar = c.take<unsigned>(64);
+    x.pw.xch = c.take<unsigned long long>(panel_work_elems(mx));
   }
   w.G = c.take<double>(m * b);
   w.Y = c.take<double>(n * b);
@@ -568,15 +567,13 @@ int randutv_geqrf(int64_t m, int64_t k, double* A, int64_t lda, double* tau) {
   std::lock_guard<std::mutex> lk(cx.mu);
   RUTV_CHECK(cx.init());
   Carver c;
-  c.take<double>(panel_work_elems(m));
-  c.take<unsigned>(64);
+  c.take<unsigned long long>(panel_work_elems(m));
   c.take<int>(4);
   RUTV_CHECK(cx.reserve(c.off));
   Carver r;
   r.base = cx.ws;
   PanelWork pw;
-  pw.part = r.take<double>(panel_work_elems(m));
-  pw.bar = r.take<unsigned>(64);
+  pw.xch = r.take<unsigned long long>(panel_work_elems(m));
   pw.err = r.take<int>(4);
   set_launch_timer(nullptr);
   RUTV_TRY(hipMemsetAsync(pw.err, 0, sizeof(int), cx.st));
