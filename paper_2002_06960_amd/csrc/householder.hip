@@ -6,9 +6,10 @@
 // tau_j = (beta_j - alpha_j)/beta_j, sign(0) = +1, tau_j = 0 when the part
 // below the diagonal is exactly zero.
 //
-// Panel kernel layout: P workgroups each own a contiguous slab of at most 512
-// rows (two rows per thread).  The panel is processed in leaves of 16 columns
-// whose rows stay in registers.  Within a leaf each column needs one sum over
+// Panel kernel layout: P workgroups of 8 waves each own a contiguous slab of
+// at most 512 rows.  The panel is processed in leaves of 16 columns whose rows
+// stay in the registers of waves 0-3 (two rows per thread); all 8 waves share
+// the matrix-core work of the trailing updates.  Within a leaf each column needs one sum over
 // all rows (squares below the diagonal plus the dot products with the leaf's
 // remaining columns, combined with the pivot row): every workgroup publishes
 // its partial sums, reads everybody's and adds them in the same order, so all
@@ -37,10 +38,12 @@ namespace rutv {
 typedef unsigned long long u64;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int kPQThreads = 256;  // 4 waves
+constexpr int kPQThreads = 512;  // 8 waves (two per SIMD keep the FP64 matrix cores busy)
 constexpr int kPQWaves = kPQThreads / WAVE;
-constexpr int kPQRpt = 2;        // slab rows per thread
-constexpr int kPQMaxRows = kPQThreads * kPQRpt;
+constexpr int kPQLeafThreads = 256;  // waves 0-3 hold the leaf rows
+constexpr int kPQLeafWaves = kPQLeafThreads / WAVE;
+constexpr int kPQRpt = 2;            // leaf rows per thread
+constexpr int kPQMaxRows = kPQLeafThreads * kPQRpt;
 constexpr int kPQNB = 16;                  // leaf width
 constexpr int kPQLdW = kPQMaxRows + 1;     // padded leading dimension of the leaf's W in LDS
 constexpr int kPQMaxWG = 64;
@@ -114,9 +117,9 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
 
   __shared__ double Wl[kPQNB * kPQLdW];        // explicit W of the finished leaf
   __shared__ double S[kPQNB * kPanelMaxCols];  // X = W^T C, then Tl^T X
-  __shared__ double red[kPQWaves * kPQNB];     // per-wave column sums
+  __shared__ double red[kPQLeafWaves * kPQNB]; // per-wave column sums
   __shared__ double pivl[kPQNB];               // pivot row (its owner only)
-  __shared__ double tsum[kPQWaves * kPQNB];    // per-wave shares of the column totals
+  __shared__ double tsum[kPQNB];               // column totals
   __shared__ double pivs[kPQNB];               // the pivot row as read back
   __shared__ double Gs[kPQNB * kPQNB];
   __shared__ double Tl[kPQNB * kPQNB];
@@ -155,8 +158,8 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
     bool own[kPQRpt];
 #pragma unroll
     for (int i = 0; i < kPQRpt; ++i) {
-      const int r = tid + kPQThreads * i;
-      own[i] = r < R;
+      const int r = tid + kPQLeafThreads * i;
+      own[i] = tid < kPQLeafThreads && r < R;
       gr[i] = r0 + r;
 #pragma unroll
       for (int c = 0; c < kPQNB; ++c)
@@ -183,6 +186,7 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
         x[i] = (own[i] && gr[i] > j) ? xj : 0.0;
       }
       // slot 0: squares below the diagonal; slot c > jj: dot with column c
+      if (wave < kPQLeafWaves) {
       double v[kPQNB];
       v[0] = 0.0;
 #pragma unroll
@@ -202,6 +206,7 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
       v[0] += __shfl_xor(v[0], 2, WAVE);
       v[0] += __shfl_xor(v[0], 1, WAVE);
       if ((lane & 3) == 0) red[wave * kPQNB + (lane >> 2)] = v[0];
+      }
 #pragma unroll
       for (int i = 0; i < kPQRpt; ++i)
         if (own[i] && gr[i] == j)
@@ -217,45 +222,48 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
           if (g == 0) {
             double ts = red[s];
 #pragma unroll
-            for (int w = 1; w < kPQWaves; ++w) ts += red[w * kPQNB + s];
+            for (int w = 1; w < kPQLeafWaves; ++w) ts += red[w * kPQNB + s];
             xput(xc + ((i64)wg * kPQNB + s) * 2, ts, tag);
           } else if (g == 1 && j >= r0 && j < r1) {
             xput(xp + s * 2, pivl[s], tag);
           }
         }
-        // lane (s, g) of wave w reads slot s of workgroups 4 w + g + 16 i;
-        // lanes g = 0 of wave 0 also read the pivot row
-        constexpr int NG = kPQMaxWG / (4 * kPQWaves);
-        const int wb = 4 * wave + g;
-        const bool pl = wave == 0 && g == 0;
-        u64 lo[NG], hi[NG], plo, phi;
-        unsigned spins = 0;
-        while (true) {
-          // branch-free: every lane loads valid words (clamped indices), the
-          // masks decide what counts
+        // wave w < 4 gathers slots 4 w .. 4 w + 3: lane (s4, g) reads slot
+        // 4 w + s4 of workgroups g, g + 16, ...; lanes g = 0 also the pivot row
+        if (wave < kPQLeafWaves) {
+          constexpr int NG = kPQMaxWG / 16;
+          const int s4 = lane & 3, gq = lane >> 2, slot = 4 * wave + s4;
+          u64 lo[NG], hi[NG], plo, phi;
+          unsigned spins = 0;
+          while (true) {
+            // branch-free: every lane loads valid words (clamped indices), the
+            // masks decide what counts
 #pragma unroll
-          for (int i = 0; i < NG; ++i) {
-            const int w = min(wb + 16 * i, P - 1);
-            lo[i] = xget(xc + ((i64)w * kPQNB + s) * 2);
-            hi[i] = xget(xc + ((i64)w * kPQNB + s) * 2 + 1);
+            for (int i = 0; i < NG; ++i) {
+              const int w = min(gq + 16 * i, P - 1);
+              lo[i] = xget(xc + ((i64)w * kPQNB + slot) * 2);
+              hi[i] = xget(xc + ((i64)w * kPQNB + slot) * 2 + 1);
+            }
+            plo = xget(xp + slot * 2);
+            phi = xget(xp + slot * 2 + 1);
+            int have = (gq != 0) | (xhas(plo, tag) & xhas(phi, tag));
+#pragma unroll
+            for (int i = 0; i < NG; ++i)
+              have &= (gq + 16 * i >= P) | (xhas(lo[i], tag) & xhas(hi[i], tag));
+            if (__all(have)) break;
+            if (give_up(spins)) break;
           }
-          plo = xget(xp + s * 2);
-          phi = xget(xp + s * 2 + 1);
-          int have = !pl | (xhas(plo, tag) & xhas(phi, tag));
+          double acc = 0.0;
 #pragma unroll
-          for (int i = 0; i < NG; ++i)
-            have &= (wb + 16 * i >= P) | (xhas(lo[i], tag) & xhas(hi[i], tag));
-          if (__all(have)) break;
-          if (give_up(spins)) break;
-        }
-        double acc = 0.0;
-#pragma unroll
-        for (int i = 0; i < NG; ++i) acc += wb + 16 * i < P ? xval(lo[i], hi[i]) : 0.0;
-        acc += __shfl_xor(acc, 16, WAVE);
-        acc += __shfl_xor(acc, 32, WAVE);
-        if (lane < kPQNB) {
-          tsum[wave * kPQNB + lane] = acc;
-          if (wave == 0) pivs[lane] = xval(plo, phi);
+          for (int i = 0; i < NG; ++i) acc += gq + 16 * i < P ? xval(lo[i], hi[i]) : 0.0;
+          acc += __shfl_xor(acc, 4, WAVE);
+          acc += __shfl_xor(acc, 8, WAVE);
+          acc += __shfl_xor(acc, 16, WAVE);
+          acc += __shfl_xor(acc, 32, WAVE);
+          if (gq == 0) {
+            tsum[slot] = acc;
+            pivs[slot] = xval(plo, phi);
+          }
         }
       }
       __syncthreads();
@@ -265,11 +273,7 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
       {
         double tot[kPQNB];
 #pragma unroll
-        for (int c = 0; c < kPQNB; ++c) {
-          tot[c] = tsum[c];
-#pragma unroll
-          for (int w = 1; w < kPQWaves; ++w) tot[c] += tsum[w * kPQNB + c];
-        }
+        for (int c = 0; c < kPQNB; ++c) tot[c] = tsum[c];
         double alpha = 0.0;
 #pragma unroll
         for (int c = 0; c < kPQNB; ++c) alpha = c == jj ? pivs[c] : alpha;
@@ -290,6 +294,7 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
       }
 #pragma unroll
       for (int i = 0; i < kPQRpt; ++i) {
+        if (wave >= kPQLeafWaves) break;
         const bool live = own[i] && gr[i] >= j, below = gr[i] > j;
         const double vr = below ? x[i] * scale : 1.0;
         const double tv = live ? t * vr : 0.0;
@@ -307,7 +312,8 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
     // row, 0 above it, the reflector below it; zero past nbl and past the slab)
 #pragma unroll
     for (int i = 0; i < kPQRpt; ++i) {
-      const int r = tid + kPQThreads * i;
+      if (tid >= kPQLeafThreads) break;
+      const int r = tid + kPQLeafThreads * i;
 #pragma unroll
       for (int c = 0; c < kPQNB; ++c) {
         const bool live = own[i] && c < nbl;
@@ -328,10 +334,10 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
     const unsigned tag1 = ++rnd, tag2 = ++rnd;
     {
       // wave w forms X(:, 16q:16q+16) = W_slab^T C_slab(:, 16q:16q+16) for the
-      // chunks q = w, w + 4, ... (ncr <= 240: at most 15 chunks); the last wave
-      // (3 chunks at most) also forms the Gram W^T W.  Rows are taken 4 per
-      // MFMA; the C values of the next kPF row groups are in flight.
-      constexpr int kPF = 8, NQ = 4;
+      // chunks q = w, w + W, ... (W waves; ncr <= 240: at most 15 chunks); the
+      // last wave also forms the Gram W^T W.  Rows are taken 4 per MFMA; the
+      // C values of the next kPF row groups are in flight.
+      constexpr int kPF = 8, NQ = (kPanelMaxCols / 16 - 1 + kPQWaves - 1) / kPQWaves;
       const bool gram = wave == kPQWaves - 1;
       // live chunks of this wave (uniform); loads are unconditional at clamped
       // addresses: rows past the slab meet zero rows of Wl, columns past ncr
