@@ -24,8 +24,81 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGemmThreads = 256;
 
-template <bool TA, bool TB, int BM, int BN, int BK>
-__global__ __launch_bounds__(kGemmThreads, 2) void dgemm_mfma_kernel(
+// Global -> register loads of one operand slice.  An operand is either
+// contiguous along the tile edge ("edge-major": op(A) = A, op(B) = B^T) or
+// contiguous along K ("k-major": op(A) = A^T, op(B) = B).  Every thread keeps
+// its own base offsets; indices are clamped into the matrix and out-of-range
+// values replaced by zero, so the loads are unconditional (no branches around
+// them, so the wait counters can pipeline them).
+// x if keep else +0.0, as a bit mask (a select would let the compiler move
+// the load into a branch)
+__device__ __forceinline__ double keep_or_zero(double x, bool keep) {
+  const long long m = -(long long)keep;
+  return __longlong_as_double(__double_as_longlong(x) & m);
+}
+
+template <bool KMAJOR, int BE_, int BX, int BK>
+struct SliceLoader {
+  static constexpr int kStride = kGemmThreads / (KMAJOR ? BK : BX);  // tile-edge (or k) step per r
+  const double* base;  // matrix pointer
+  i64 ld;
+  int e0;              // this thread's first edge index (edge-major: fixed; k-major: + kStride r)
+  int k_off;           // this thread's first k offset (edge-major: + kStride r; k-major: fixed)
+  int edge_lim;        // rows/columns of the matrix past the tile start
+  i64 eoff[KMAJOR ? BE_ : 1];  // k-major: clamped edge index * ld per r
+  bool eok[KMAJOR ? BE_ : 1];
+
+  __device__ __forceinline__ void init(const double* p, i64 ldp, int tid, int tile0, int edge_total) {
+    base = p;
+    ld = ldp;
+    if (KMAJOR) {
+      k_off = tid % BK;
+      e0 = tid / BK;
+#pragma unroll
+      for (int r = 0; r < BE_; ++r) {
+        const int e = tile0 + e0 + kStride * r;
+        eok[r] = e < edge_total;
+        eoff[r] = (i64)min(e, edge_total - 1) * ld;
+      }
+    } else {
+      e0 = tid % BX;
+      k_off = tid / BX;
+      const int e = tile0 + e0;
+      eok[0] = e < edge_total;
+      eoff[0] = min(e, edge_total - 1);
+    }
+    (void)edge_lim;
+  }
+  // raw values of slice [k0, k0 + BK) (clamped addresses) and which of them
+  // lie inside the matrix (k < kend); the mask is applied when the values are
+  // written to LDS, after the matrix-core work that hides the loads
+  __device__ __forceinline__ void load(double (&v)[BE_], bool (&keep)[BE_], int k0, int kend) const {
+    if (KMAJOR) {
+      const int k = k0 + k_off;
+      const bool kok = k < kend;
+      const double* p = base + min(k, kend - 1);
+#pragma unroll
+      for (int r = 0; r < BE_; ++r) {
+        v[r] = p[eoff[r]];
+        keep[r] = kok && eok[r];
+      }
+    } else {
+      const double* p = base + eoff[0];
+#pragma unroll
+      for (int r = 0; r < BE_; ++r) {
+        const int k = k0 + k_off + kStride * r;
+        v[r] = p[(i64)min(k, kend - 1) * ld];
+        keep[r] = eok[0] && k < kend;
+      }
+    }
+  }
+  // LDS position (k, edge) of value r
+  __device__ __forceinline__ int lds_k(int r) const { return KMAJOR ? k_off : k_off + kStride * r; }
+  __device__ __forceinline__ int lds_e(int r) const { return KMAJOR ? e0 + kStride * r : e0; }
+};
+
+template <bool TA, bool TB, int BM, int BN, int BK, int MINB = 2>
+__global__ __launch_bounds__(kGemmThreads, MINB) void dgemm_mfma_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, i64 lda,
     const double* __restrict__ B, i64 ldb, double beta, double* __restrict__ C, i64 ldc,
     int kchunk, double* __restrict__ part, int tilesM, int ntiles) {
@@ -50,44 +123,17 @@ __global__ __launch_bounds__(kGemmThreads, 2) void dgemm_mfma_kernel(
   const int kbeg = kz * kchunk;
   const int kend = min(K, kbeg + kchunk);
 
+  SliceLoader<TA, AE, BM, BK> la;
+  SliceLoader<!TB, BE, BN, BK> lb;
+  la.init(A, lda, tid, m0, M);
+  lb.init(B, ldb, tid, n0, N);
   double ra[AE], rb[BE];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < AE; ++r) {
-      const int e = tid + kGemmThreads * r;
-      const int mm = TA ? e / BK : e % BM;
-      const int kk = TA ? e % BK : e / BM;
-      const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < M && gk < kend) v = TA ? A[(i64)gk + (i64)gm * lda] : A[(i64)gm + (i64)gk * lda];
-      ra[r] = v;
-    }
-#pragma unroll
-    for (int r = 0; r < BE; ++r) {
-      const int e = tid + kGemmThreads * r;
-      const int nn = TB ? e % BN : e / BK;
-      const int kk = TB ? e / BN : e % BK;
-      const int gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < N && gk < kend) v = TB ? B[(i64)gn + (i64)gk * ldb] : B[(i64)gk + (i64)gn * ldb];
-      rb[r] = v;
-    }
-  };
+  bool ka[AE], kb[BE];
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < AE; ++r) {
-      const int e = tid + kGemmThreads * r;
-      const int mm = TA ? e / BK : e % BM;
-      const int kk = TA ? e % BK : e / BM;
-      As[buf][kk * LDAS + mm] = ra[r];
-    }
+    for (int r = 0; r < AE; ++r) As[buf][la.lds_k(r) * LDAS + la.lds_e(r)] = keep_or_zero(ra[r], ka[r]);
 #pragma unroll
-    for (int r = 0; r < BE; ++r) {
-      const int e = tid + kGemmThreads * r;
-      const int nn = TB ? e % BN : e / BK;
-      const int kk = TB ? e / BN : e % BK;
-      Bs[buf][kk * LDBS + nn] = rb[r];
-    }
+    for (int r = 0; r < BE; ++r) Bs[buf][lb.lds_k(r) * LDBS + lb.lds_e(r)] = keep_or_zero(rb[r], kb[r]);
   };
 
   dbl4 acc[MI][NJ];
@@ -98,12 +144,16 @@ __global__ __launch_bounds__(kGemmThreads, 2) void dgemm_mfma_kernel(
 
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   if (nk > 0) {
-    gload(kbeg);
+    la.load(ra, ka, kbeg, kend);
+    lb.load(rb, kb, kbeg, kend);
     sstore(0);
     __syncthreads();
     for (int t = 0; t < nk; ++t) {
       const int cur = t & 1;
-      if (t + 1 < nk) gload(kbeg + (t + 1) * BK);
+      if (t + 1 < nk) {
+        la.load(ra, ka, kbeg + (t + 1) * BK, kend);
+        lb.load(rb, kb, kbeg + (t + 1) * BK, kend);
+      }
       const double* as = As[cur];
       const double* bs = Bs[cur];
 #pragma unroll
@@ -127,25 +177,35 @@ __global__ __launch_bounds__(kGemmThreads, 2) void dgemm_mfma_kernel(
 
   // v_mfma_f64_16x16x4 leaves D(4r + lane/16, lane%16) in register r; with the
   // swapped operands D is the transposed C block, so the lane holds
-  // C[m0+wm0+16i+(lane&15)][n0+wn0+16j+4r+(lane>>4)], r = 0..3
+  // C[m0+wm0+16i+(lane&15)][n0+wn0+16j+4r+(lane>>4)], r = 0..3.  The C values
+  // of one row block are loaded together (clamped addresses), then stored.
   const int cm = lane & 15, cn = lane >> 4;
 #pragma unroll
   for (int i = 0; i < MI; ++i) {
     const int gm = m0 + wm0 + 16 * i + cm;
-    if (gm >= M) continue;
+    const int gmc = min(gm, M - 1);
+    double cv[NJ][4];
+    if (!part && beta != 0.0) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gnc = min(n0 + wn0 + 16 * j + 4 * r + cn, N - 1);
+          cv[j][r] = C[gmc + (i64)gnc * ldc];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gn = n0 + wn0 + 16 * j + 4 * r + cn;
-        if (gn >= N) continue;
         double v = alpha * acc[i][j][r];
-        if (part) {
-          part[(i64)kz * M * N + gm + (i64)gn * M] = v;
-        } else {
-          double* c = C + gm + (i64)gn * ldc;
-          if (beta != 0.0) v += beta * *c;
-          *c = v;
+        if (!part && beta != 0.0) v += beta * cv[j][r];
+        if (gm < M && gn < N) {
+          if (part)
+            part[(i64)kz * M * N + gm + (i64)gn * M] = v;
+          else
+            C[gm + (i64)gn * ldc] = v;
         }
       }
     }
@@ -177,24 +237,32 @@ struct Plan {
 };
 
 constexpr int kBK = 16;
-constexpr i64 kTargetWG = 1024;  // about four workgroups per CU
+constexpr i64 kResident = 512;  // workgroups resident at once (two per CU)
 
 Plan choose_plan(i64 M, i64 N, i64 K) {
   const i64 t128 = cdiv(M, 128) * cdiv(N, 128);
-  const i64 t64 = cdiv(M, 64) * cdiv(N, 64);
   Plan p{128, 1, (int)std::max<i64>(K, 1)};
   if (K <= 512) {  // rank-b updates and small products: no split
-    p.bm = t128 >= 256 ? 128 : 64;
+    if (t128 < kResident) p.bm = 64;
     return p;
   }
-  if (t128 >= kTargetWG) return p;
-  p.bm = 64;
-  if (t64 >= kTargetWG) return p;
-  // skinny output with long K: split K over blockIdx.y
-  i64 s = cdiv(kTargetWG, t64);
-  const i64 max_s = std::max<i64>(1, K / 256);  // keep at least 256 of K per split
-  if (s > max_s) s = max_s;
-  const i64 chunk = cdiv(cdiv(K, s), kBK) * kBK;
+  if (t128 >= 2 * kResident) return p;
+  // skinny output with long K: split K over blockIdx.y.  Cost model: rounds
+  // of resident workgroups times (K per split + a fixed per-tile overhead of
+  // about 256 of K); at least 128 of K per split.
+  i64 best_s = 1;
+  double best = 1e300;
+  for (i64 s = 1; s <= 32; ++s) {
+    const i64 chunk = cdiv(cdiv(K, s), kBK) * kBK;
+    const i64 ns = cdiv(K, chunk);
+    if (ns != s || (s > 1 && chunk < 128)) continue;
+    const double cost = (double)cdiv(t128 * s, kResident) * (double)(chunk + 256);
+    if (cost < best * 0.999) {
+      best = cost;
+      best_s = s;
+    }
+  }
+  const i64 chunk = cdiv(cdiv(K, best_s), kBK) * kBK;
   p.splits = (int)cdiv(K, chunk);
   p.kchunk = (int)chunk;
   return p;
