@@ -13,9 +13,9 @@
 // covers 4 columns x 16 consecutive rows, i.e. full 128-byte segments of
 // column-major C.
 //
-// Skinny products (an n x b output with K in the thousands) split K over
-// blockIdx.y; each split writes alpha * partial to a buffer and a second
-// kernel sums the splits in a fixed order (deterministic).
+// Skinny products (an n x b output with K in the thousands) split K; each
+// split writes alpha * partial to a buffer and a second kernel sums the splits
+// in a fixed order (deterministic).
 #include "kernels.hpp"
 
 namespace rutv {
@@ -44,34 +44,19 @@ struct SliceLoader {
   i64 ld;
   int e0;              // this thread's first edge index (edge-major: fixed; k-major: + kStride r)
   int k_off;           // this thread's first k offset (edge-major: + kStride r; k-major: fixed)
-  int edge_lim;        // rows/columns of the matrix past the tile start
-  i64 eoff[KMAJOR ? BE_ : 1];  // k-major: clamped edge index * ld per r
-  bool eok[KMAJOR ? BE_ : 1];
+  int tile0, edge_total;
 
-  __device__ __forceinline__ void init(const double* p, i64 ldp, int tid, int tile0, int edge_total) {
+  __device__ __forceinline__ void init(const double* p, i64 ldp, int tid, int t0, int et) {
     base = p;
     ld = ldp;
-    if (KMAJOR) {
-      k_off = tid % BK;
-      e0 = tid / BK;
-#pragma unroll
-      for (int r = 0; r < BE_; ++r) {
-        const int e = tile0 + e0 + kStride * r;
-        eok[r] = e < edge_total;
-        eoff[r] = (i64)min(e, edge_total - 1) * ld;
-      }
-    } else {
-      e0 = tid % BX;
-      k_off = tid / BX;
-      const int e = tile0 + e0;
-      eok[0] = e < edge_total;
-      eoff[0] = min(e, edge_total - 1);
-    }
-    (void)edge_lim;
+    tile0 = t0;
+    edge_total = et;
+    e0 = KMAJOR ? tid / BK : tid % BX;
+    k_off = KMAJOR ? tid % BK : tid / BX;
   }
   // raw values of slice [k0, k0 + BK) (clamped addresses) and which of them
-  // lie inside the matrix (k < kend); the mask is applied when the values are
-  // written to LDS, after the matrix-core work that hides the loads
+  // lie inside the matrix; the mask is applied when the values are written to
+  // LDS, after the matrix-core work that hides the loads
   __device__ __forceinline__ void load(double (&v)[BE_], bool (&keep)[BE_], int k0, int kend) const {
     if (KMAJOR) {
       const int k = k0 + k_off;
@@ -79,16 +64,19 @@ struct SliceLoader {
       const double* p = base + min(k, kend - 1);
 #pragma unroll
       for (int r = 0; r < BE_; ++r) {
-        v[r] = p[eoff[r]];
-        keep[r] = kok && eok[r];
+        const int e = tile0 + e0 + kStride * r;
+        v[r] = p[(i64)min(e, edge_total - 1) * ld];
+        keep[r] = kok && e < edge_total;
       }
     } else {
-      const double* p = base + eoff[0];
+      const int e = tile0 + e0;
+      const bool eok = e < edge_total;
+      const double* p = base + min(e, edge_total - 1);
 #pragma unroll
       for (int r = 0; r < BE_; ++r) {
         const int k = k0 + k_off + kStride * r;
         v[r] = p[(i64)min(k, kend - 1) * ld];
-        keep[r] = eok[0] && k < kend;
+        keep[r] = eok && k < kend;
       }
     }
   }
@@ -97,11 +85,33 @@ struct SliceLoader {
   __device__ __forceinline__ int lds_e(int r) const { return KMAJOR ? e0 + kStride * r : e0; }
 };
 
+// Work item of workgroup L.  Workgroups are dealt to the 8 XCDs round-robin
+// (L mod 8), so XCD x receives the x-th contiguous range of an ordering in
+// which K splits are slowest and, within a split, the tile grid is walked in
+// groups of kGroupM tile rows (all tile columns of a group, rows fastest):
+// the concurrent workgroups of one XCD then share op(A) row panels and op(B)
+// column panels in its L2.
+constexpr int kGroupM = 8;
+
+__device__ __forceinline__ void tile_of(int L, int tilesM, int tilesN, int splits, int& mt,
+                                        int& nt, int& kz) {
+  const int per = tilesM * tilesN, total = per * splits;
+  const int q = total >> 3, r = total & 7, x = L & 7;
+  const int idx = x * q + min(x, r) + (L >> 3);
+  kz = idx / per;
+  const int t = idx - kz * per;
+  const int g = t / (kGroupM * tilesN);
+  const int mb = g * kGroupM, gm = min(kGroupM, tilesM - mb);
+  const int t2 = t - g * kGroupM * tilesN;
+  mt = mb + t2 % gm;
+  nt = t2 / gm;
+}
+
 template <bool TA, bool TB, int BM, int BN, int BK, int MINB = 2>
 __global__ __launch_bounds__(kGemmThreads, MINB) void dgemm_mfma_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, i64 lda,
     const double* __restrict__ B, i64 ldb, double beta, double* __restrict__ C, i64 ldc,
-    int kchunk, double* __restrict__ part, int tilesM, int ntiles) {
+    int kchunk, double* __restrict__ part, int tilesM, int tilesN, int splits) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int MI = WM / 16, NJ = WN / 16;
   constexpr int LDAS = BM + 1, LDBS = BN + 1;  // +1 double: conflict-free transposing stores
@@ -113,13 +123,9 @@ __global__ __launch_bounds__(kGemmThreads, MINB) void dgemm_mfma_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave & 1) * WM, wn0 = (wave >> 1) * WN;
 
-  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
-  // give each XCD a contiguous run of tiles (column-major over the tile grid,
-  // neighbours share the op(B) panel) when the count divides evenly.
-  int bid = blockIdx.x;
-  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
-  const int m0 = (bid % tilesM) * BM, n0 = (bid / tilesM) * BN;
-  const int kz = blockIdx.y;
+  int mt, nt, kz;
+  tile_of(blockIdx.x, tilesM, tilesN, splits, mt, nt, kz);
+  const int m0 = mt * BM, n0 = nt * BN;
   const int kbeg = kz * kchunk;
   const int kend = min(K, kbeg + kchunk);
 
@@ -184,23 +190,21 @@ __global__ __launch_bounds__(kGemmThreads, MINB) void dgemm_mfma_kernel(
   for (int i = 0; i < MI; ++i) {
     const int gm = m0 + wm0 + 16 * i + cm;
     const int gmc = min(gm, M - 1);
-    double cv[NJ][4];
-    if (!part && beta != 0.0) {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j)
+    for (int j = 0; j < NJ; ++j) {
+      double cv[4];
+      if (!part && beta != 0.0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int gnc = min(n0 + wn0 + 16 * j + 4 * r + cn, N - 1);
-          cv[j][r] = C[gmc + (i64)gnc * ldc];
+          cv[r] = C[gmc + (i64)gnc * ldc];
         }
-    }
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gn = n0 + wn0 + 16 * j + 4 * r + cn;
         double v = alpha * acc[i][j][r];
-        if (!part && beta != 0.0) v += beta * cv[j][r];
+        if (!part && beta != 0.0) v += beta * cv[r];
         if (gm < M && gn < N) {
           if (part)
             part[(i64)kz * M * N + gm + (i64)gn * M] = v;
@@ -247,7 +251,7 @@ Plan choose_plan(i64 M, i64 N, i64 K) {
     return p;
   }
   if (t128 >= 2 * kResident) return p;
-  // skinny output with long K: split K over blockIdx.y.  Cost model: rounds
+  // skinny output with long K: split K.  Cost model: rounds
   // of resident workgroups times (K per split + a fixed per-tile overhead of
   // about 256 of K); at least 128 of K per split.
   i64 best_s = 1;
@@ -269,15 +273,17 @@ Plan choose_plan(i64 M, i64 N, i64 K) {
 }
 
 template <bool TA, bool TB>
-void launch_tile(hipStream_t st, int bm, dim3 grid, int M, int N, int K, double alpha,
-                 const double* A, i64 lda, const double* B, i64 ldb, double beta, double* C,
-                 i64 ldc, int kchunk, double* part, int tilesM, int ntiles) {
+void launch_tile(hipStream_t st, int bm, int M, int N, int K, double alpha, const double* A,
+                 i64 lda, const double* B, i64 ldb, double beta, double* C, i64 ldc, int kchunk,
+                 int splits, double* part) {
+  const int tilesM = (int)cdiv(M, bm), tilesN = (int)cdiv(N, bm);
+  const dim3 grid(tilesM * tilesN * splits);
   if (bm == 128)
     dgemm_mfma_kernel<TA, TB, 128, 128, kBK><<<grid, kGemmThreads, 0, st>>>(
-        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, ntiles);
+        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, tilesN, splits);
   else
     dgemm_mfma_kernel<TA, TB, 64, 64, kBK><<<grid, kGemmThreads, 0, st>>>(
-        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, ntiles);
+        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, tilesN, splits);
 }
 
 }  // namespace
@@ -305,25 +311,23 @@ int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha, c
       p.kchunk = (int)chunk;
     }
   }
-  const int tilesM = (int)cdiv(M, p.bm), tilesN = (int)cdiv(N, p.bm);
-  const int ntiles = tilesM * tilesN;
-  dim3 grid(ntiles, p.splits);
+  if (cdiv(M, p.bm) * cdiv(N, p.bm) * p.splits > INT32_MAX) return RANDUTV_ERR_TOO_LARGE;
   double* part = p.splits > 1 ? work : nullptr;
   const int cls = ta ? (tb ? K_GEMM_TT : K_GEMM_TN) : (tb ? K_GEMM_NT : K_GEMM_NN);
   LaunchTimer* tm = launch_timer();
   if (tm) tm->begin(st, cls);
   if (!ta && !tb)
-    launch_tile<false, false>(st, p.bm, grid, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb,
-                              beta, C, ldc, p.kchunk, part, tilesM, ntiles);
+    launch_tile<false, false>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C,
+                              ldc, p.kchunk, p.splits, part);
   else if (ta && !tb)
-    launch_tile<true, false>(st, p.bm, grid, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb,
-                             beta, C, ldc, p.kchunk, part, tilesM, ntiles);
+    launch_tile<true, false>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C,
+                             ldc, p.kchunk, p.splits, part);
   else if (!ta && tb)
-    launch_tile<false, true>(st, p.bm, grid, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb,
-                             beta, C, ldc, p.kchunk, part, tilesM, ntiles);
+    launch_tile<false, true>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C,
+                             ldc, p.kchunk, p.splits, part);
   else
-    launch_tile<true, true>(st, p.bm, grid, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb,
-                            beta, C, ldc, p.kchunk, part, tilesM, ntiles);
+    launch_tile<true, true>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C,
+                            ldc, p.kchunk, p.splits, part);
   RUTV_TRY(hipGetLastError());
   if (tm) tm->end(st, cls, 2.0 * (double)M * (double)N * (double)K);
   if (part) {

@@ -110,7 +110,7 @@ struct EventTimer final : LaunchTimer {
 // ---------------------------------------------------------------------------
 enum { ST_T = 0, ST_P, ST_UV, ST_S, NSTREAMS };
 constexpr int kEvRing = 4;  // events of a kind are reused every kEvRing steps
-enum { EV_V = 0, EV_COLS, EV_U, EV_UV, EV_KINDS };
+enum { EV_V = 0, EV_COLS, EV_U, EV_UV, EV_PRE, EV_KINDS };
 
 struct Context {
   std::mutex mu;
@@ -350,7 +350,45 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
   if (wantU) RUTV_CHECK(set_identity(sUV, m, U, ldu));
   if (wantV) RUTV_CHECK(set_identity(sUV, n, V, ldv));
 
-  i64 s = 0, g0 = 0;
+  // stream UV: V and U updates of step j; they are enqueued one step late,
+  // behind the event that marks the end of the next step's power iteration,
+  // so that they fill the chip during the next QR of the sketch (a latency-
+  // bound kernel on 32 CUs) instead of competing with the power iteration
+  i64 g0 = 0;
+  auto uv_and_svd = [&](i64 j, bool wait_pre) -> int {
+    const i64 sj = j * b, bj = std::min(b, n - sj), mj = m - sj, nj = n - sj;
+    const int bf = (int)(j & 1);
+    if (wait_pre) RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_PRE, j + 1), 0));
+    RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_V, j), 0));
+    if (wantV) RUTV_CHECK(right_apply(sUV, xUV, n, nj, bj, V + sj * ldv, ldv, w.WV[bf], w.ZV[bf]));
+    RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_U, j), 0));
+    if (wantU) RUTV_CHECK(right_apply(sUV, xUV, m, mj, bj, U + sj * ldu, ldu, w.WU[bf], w.ZU[bf]));
+    RUTV_TRY(hipEventRecord(ev(EV_UV, j), sUV));
+    // stream S: b x b SVDs in groups, then their right factors
+    const bool last = sj + bj >= n;
+    if ((j + 1 - g0) == kSvdGroup || last) {
+      const int cnt = (int)(j + 1 - g0);
+      RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_U, j), 0));
+      RUTV_CHECK(jacobi_svd_batched(sS, cnt, b, last ? b_last : b, w.Rall + g0 * b * b, b, b * b,
+                                    w.dall + g0 * b, b, w.Usall + g0 * b * b, w.Vsall + g0 * b * b,
+                                    b * b, w.jwork, &w.status[2 + 3 * g0]));
+      for (i64 t = g0; t <= j; ++t) {
+        const i64 st_ = t * b, bt = std::min(b, n - st_);
+        const double* d = w.dall + t * b;
+        const double* Vs = w.Vsall + t * b * b;
+        const double* Us = w.Usall + t * b * b;
+        RUTV_CHECK(set_diag_block(sS, bt, d, T + st_ + st_ * ldt, ldt));
+        RUTV_CHECK(right_mul_small(sS, xS, st_, bt, T + st_ * ldt, ldt, Vs));
+        RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_UV, t), 0));
+        if (wantV) RUTV_CHECK(right_mul_small(sS, xS, n, bt, V + st_ * ldv, ldv, Vs));
+        if (wantU) RUTV_CHECK(right_mul_small(sS, xS, m, bt, U + st_ * ldu, ldu, Us));
+      }
+      g0 = j + 1;
+    }
+    return RANDUTV_OK;
+  };
+
+  i64 s = 0;
   for (i64 i = 0; s < n; ++i) {
     const i64 bi = std::min(b, n - s), e = s + bi, mi = m - s, ni = n - s;
     const int buf = (int)(i & 1);
@@ -363,6 +401,8 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
       RUTV_CHECK(gemm(sT, xT, false, false, mi, bi, ni, 1.0, Bm, ldt, w.Y, ni, 0.0, w.Zp, mi));
       RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.Zp, mi, 0.0, w.Y, ni));
     }
+    RUTV_TRY(hipEventRecord(ev(EV_PRE, i), sT));
+    if (i >= 1) RUTV_CHECK(uv_and_svd(i - 1, true));
     RUTV_CHECK(panel_qr(sT, ni, bi, w.Y, ni, w.tauV, xT.pw));
     RUTV_CHECK(wy_factor(sT, xT, ni, bi, w.Y, ni, w.tauV, w.WV[buf], w.ZV[buf], nullptr, 0, false));
     RUTV_TRY(hipEventRecord(ev(EV_V, i), sT));
@@ -388,35 +428,9 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
       RUTV_CHECK(gemm(sT, xT, true, false, bi, ni - bi, mi, 1.0, w.WU[buf], mi, C, ldt, 0.0, w.X3, bi));
       RUTV_CHECK(gemm(sT, xT, false, false, mi, ni - bi, bi, -1.0, w.ZU[buf], mi, w.X3, bi, 1.0, C, ldt));
     }
-    // ---- stream UV: V and U updates of this step
-    RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_V, i), 0));
-    if (wantV) RUTV_CHECK(right_apply(sUV, xUV, n, ni, bi, V + s * ldv, ldv, w.WV[buf], w.ZV[buf]));
-    RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_U, i), 0));
-    if (wantU) RUTV_CHECK(right_apply(sUV, xUV, m, mi, bi, U + s * ldu, ldu, w.WU[buf], w.ZU[buf]));
-    RUTV_TRY(hipEventRecord(ev(EV_UV, i), sUV));
-    // ---- stream S: b x b SVDs in groups, then their right factors
-    const bool last = e >= n;
-    if ((i + 1 - g0) == kSvdGroup || last) {
-      const int cnt = (int)(i + 1 - g0);
-      RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_U, i), 0));
-      RUTV_CHECK(jacobi_svd_batched(sS, cnt, b, last ? b_last : b, w.Rall + g0 * b * b, b, b * b,
-                                    w.dall + g0 * b, b, w.Usall + g0 * b * b, w.Vsall + g0 * b * b,
-                                    b * b, w.jwork, &w.status[2 + 3 * g0]));
-      for (i64 t = g0; t <= i; ++t) {
-        const i64 st_ = t * b, bt = std::min(b, n - st_);
-        const double* d = w.dall + t * b;
-        const double* Vs = w.Vsall + t * b * b;
-        const double* Us = w.Usall + t * b * b;
-        RUTV_CHECK(set_diag_block(sS, bt, d, T + st_ + st_ * ldt, ldt));
-        RUTV_CHECK(right_mul_small(sS, xS, st_, bt, T + st_ * ldt, ldt, Vs));
-        RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_UV, t), 0));
-        if (wantV) RUTV_CHECK(right_mul_small(sS, xS, n, bt, V + st_ * ldv, ldv, Vs));
-        if (wantU) RUTV_CHECK(right_mul_small(sS, xS, m, bt, U + st_ * ldu, ldu, Us));
-      }
-      g0 = i + 1;
-    }
     s = e;
   }
+  RUTV_CHECK(uv_and_svd(nsteps - 1, false));
   // ---- join, then the deferred left factors: T(s:e, e:n) <- U_S^T T(s:e, e:n)
   RUTV_TRY(hipEventRecord(cx.ev_misc[0], sS));
   RUTV_TRY(hipEventRecord(cx.ev_misc[1], sUV));
