@@ -110,7 +110,7 @@ struct EventTimer final : LaunchTimer {
 // ---------------------------------------------------------------------------
 enum { ST_T = 0, ST_P, ST_UV, ST_S, NSTREAMS };
 constexpr int kEvRing = 4;  // events of a kind are reused every kEvRing steps
-enum { EV_V = 0, EV_COLS, EV_U, EV_UV, EV_PRE, EV_KINDS };
+enum { EV_V = 0, EV_COLS, EV_U, EV_UV, EV_PRE, EV_WV, EV_WU, EV_KINDS };
 
 struct Context {
   std::mutex mu;
@@ -189,7 +189,7 @@ struct StreamWS {
   double* splitk = nullptr;
   i64 splitk_elems = 0;
   double* Gram = nullptr;  // b x b
-  double* Tf = nullptr;    // b x b
+  double* X2 = nullptr;    // max(m, n) x b
   double* X = nullptr;     // max(m, n) x b
   PanelWork pw;
 };
@@ -198,8 +198,8 @@ constexpr int kSvdGroup = 8;  // SVDs per batched launch
 
 struct FactorWS {
   StreamWS sw[NSTREAMS];
-  double *G, *Y, *Zp, *tauV, *tauU, *X3;
-  double *WV[2], *ZV[2], *WU[2], *ZU[2];
+  double *G, *Y, *Zp, *tauV, *tauU, *X3, *X3t;
+  double *WV[2], *TV[2], *WU[2], *TU[2];  // reflectors and their block factors, by step parity
   double *Rall, *dall, *Usall, *Vsall, *jwork;
   int* status;  // [0] finite flag, [1] panel sync error, [2 + 3i ..] sweeps, converged, sync error
 };
@@ -247,8 +247,8 @@ static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wa
     x.splitk_elems = sk;
     x.splitk = c.take<double>(sk);
     x.Gram = c.take<double>(b * b);
-    x.Tf = c.take<double>(b * b);
     x.X = c.take<double>(mx * b);
+    x.X2 = c.take<double>(mx * b);
     x.pw.xch = c.take<unsigned long long>(panel_work_elems(mx));
   }
   w.G = c.take<double>(m * b);
@@ -257,11 +257,12 @@ static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wa
   w.tauV = c.take<double>(b);
   w.tauU = c.take<double>(b);
   w.X3 = c.take<double>(b * n);
+  w.X3t = c.take<double>(b * n);
   for (int t = 0; t < 2; ++t) {
     w.WV[t] = c.take<double>(n * b);
-    w.ZV[t] = c.take<double>(n * b);
+    w.TV[t] = c.take<double>(b * b);
     w.WU[t] = c.take<double>(m * b);
-    w.ZU[t] = c.take<double>(m * b);
+    w.TU[t] = c.take<double>(b * b);
   }
   w.Rall = c.take<double>(nsteps * b * b);
   w.dall = c.take<double>(nsteps * b);
@@ -278,22 +279,22 @@ static int gemm(hipStream_t st, const StreamWS& x, bool ta, bool tb, i64 M, i64 
   return dgemm(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, x.splitk, x.splitk_elems);
 }
 
-// compact-WY factor of the reflectors in P (rows x k, ld ldp): W explicit,
-// T from the Gram matrix, Z = W T^T
-static int wy_factor(hipStream_t st, const StreamWS& x, i64 rows, i64 k, double* P, i64 ldp,
-                     const double* tau, double* W, double* Z, double* R, i64 ldr, bool zero_panel) {
-  RUTV_CHECK(extract_reflectors(st, rows, k, P, ldp, W, rows, R, ldr, zero_panel));
+// block factor Tf (k x k, ld k) of the reflectors W (rows x k, unit lower
+// trapezoidal, ld rows): I - W Tf W^T = H_1 ... H_k, from the Gram matrix W^T W
+static int t_factor(hipStream_t st, const StreamWS& x, i64 rows, i64 k, const double* W,
+                    const double* tau, double* Tf) {
   RUTV_CHECK(gemm(st, x, true, false, k, k, rows, 1.0, W, rows, W, rows, 0.0, x.Gram, k));
-  RUTV_CHECK(larft_from_gram(st, k, x.Gram, k, tau, x.Tf, k));
-  RUTV_CHECK(gemm(st, x, false, true, rows, k, k, 1.0, W, rows, x.Tf, k, 0.0, Z, rows));
+  RUTV_CHECK(larft_from_gram(st, k, x.Gram, k, tau, Tf, k));
   return RANDUTV_OK;
 }
 
-// C(rows x cols, ld ldc) <- C (I - W T W^T) = C - (C W) Z^T, W/Z: cols x k (ld cols)
+// C(rows x cols, ld ldc) <- C (I - W Tf W^T) = C - ((C W) Tf) W^T, W: cols x k
+// (ld cols), Tf: k x k
 static int right_apply(hipStream_t st, const StreamWS& x, i64 rows, i64 cols, i64 k, double* C,
-                       i64 ldc, const double* W, const double* Z) {
+                       i64 ldc, const double* W, const double* Tf) {
   RUTV_CHECK(gemm(st, x, false, false, rows, k, cols, 1.0, C, ldc, W, cols, 0.0, x.X, rows));
-  RUTV_CHECK(gemm(st, x, false, true, rows, cols, k, -1.0, x.X, rows, Z, cols, 1.0, C, ldc));
+  RUTV_CHECK(gemm(st, x, false, false, rows, k, k, 1.0, x.X, rows, Tf, k, 0.0, x.X2, rows));
+  RUTV_CHECK(gemm(st, x, false, true, rows, cols, k, -1.0, x.X2, rows, W, cols, 1.0, C, ldc));
   return RANDUTV_OK;
 }
 
@@ -360,9 +361,9 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     const int bf = (int)(j & 1);
     if (wait_pre) RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_PRE, j + 1), 0));
     RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_V, j), 0));
-    if (wantV) RUTV_CHECK(right_apply(sUV, xUV, n, nj, bj, V + sj * ldv, ldv, w.WV[bf], w.ZV[bf]));
+    if (wantV) RUTV_CHECK(right_apply(sUV, xUV, n, nj, bj, V + sj * ldv, ldv, w.WV[bf], w.TV[bf]));
     RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_U, j), 0));
-    if (wantU) RUTV_CHECK(right_apply(sUV, xUV, m, mj, bj, U + sj * ldu, ldu, w.WU[bf], w.ZU[bf]));
+    if (wantU) RUTV_CHECK(right_apply(sUV, xUV, m, mj, bj, U + sj * ldu, ldu, w.WU[bf], w.TU[bf]));
     RUTV_TRY(hipEventRecord(ev(EV_UV, j), sUV));
     // stream S: b x b SVDs in groups, then their right factors
     const bool last = sj + bj >= n;
@@ -394,7 +395,7 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     const int buf = (int)(i & 1);
     double* Bm = T + s + s * ldt;
     // ---- stream T: sketch, power iteration, QR(Y), compact WY of V^
-    if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_UV, i - 2), 0));  // WV/ZV[buf] free
+    if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_UV, i - 2), 0));  // WV[buf] free
     RUTV_CHECK(sketch(sT, seed, (uint64_t)i, mi, bi, w.G, mi));
     RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.G, mi, 0.0, w.Y, ni));
     for (int it = 0; it < q; ++it) {
@@ -404,29 +405,42 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     RUTV_TRY(hipEventRecord(ev(EV_PRE, i), sT));
     if (i >= 1) RUTV_CHECK(uv_and_svd(i - 1, true));
     RUTV_CHECK(panel_qr(sT, ni, bi, w.Y, ni, w.tauV, xT.pw));
-    RUTV_CHECK(wy_factor(sT, xT, ni, bi, w.Y, ni, w.tauV, w.WV[buf], w.ZV[buf], nullptr, 0, false));
-    RUTV_TRY(hipEventRecord(ev(EV_V, i), sT));
-    // right transform of all m rows: first the current column block (it
-    // feeds the panel QR on stream P), then the rest
+    RUTV_CHECK(extract_reflectors(sT, ni, bi, w.Y, ni, w.WV[buf], ni, nullptr, 0, false));
+    RUTV_TRY(hipEventRecord(ev(EV_WV, i), sT));
+    // stream P: block factor of V^ while stream T forms X = T W
+    RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_WV, i), 0));
+    if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_UV, i - 2), 0));  // TV/WU/TU[buf] free
+    RUTV_CHECK(t_factor(sP, xP, ni, bi, w.WV[buf], w.tauV, w.TV[buf]));
+    RUTV_TRY(hipEventRecord(ev(EV_V, i), sP));
+    // right transform of all m rows, T <- T - ((T W) Tf) W^T: first the
+    // current column block (it feeds the panel QR on stream P), then the rest
     RUTV_CHECK(gemm(sT, xT, false, false, m, bi, ni, 1.0, T + s * ldt, ldt, w.WV[buf], ni, 0.0, xT.X, m));
-    RUTV_CHECK(gemm(sT, xT, false, true, m, bi, bi, -1.0, xT.X, m, w.ZV[buf], ni, 1.0, T + s * ldt, ldt));
+    RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_V, i), 0));
+    RUTV_CHECK(gemm(sT, xT, false, false, m, bi, bi, 1.0, xT.X, m, w.TV[buf], bi, 0.0, xT.X2, m));
+    RUTV_CHECK(gemm(sT, xT, false, true, m, bi, bi, -1.0, xT.X2, m, w.WV[buf], ni, 1.0, T + s * ldt, ldt));
     RUTV_TRY(hipEventRecord(ev(EV_COLS, i), sT));
     if (e < n)
-      RUTV_CHECK(gemm(sT, xT, false, true, m, ni - bi, bi, -1.0, xT.X, m, w.ZV[buf] + bi, ni, 1.0,
+      RUTV_CHECK(gemm(sT, xT, false, true, m, ni - bi, bi, -1.0, xT.X2, m, w.WV[buf] + bi, ni, 1.0,
                       T + e * ldt, ldt));
-    // ---- stream P: panel QR of the column block, compact WY of U^
+    // ---- stream P: panel QR of the column block, its reflectors, then their
+    // block factor while stream T forms W^T C
     RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_COLS, i), 0));
-    if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_UV, i - 2), 0));  // WU/ZU[buf] free
     RUTV_CHECK(panel_qr(sP, mi, bi, Bm, ldt, w.tauU, xP.pw));
-    RUTV_CHECK(wy_factor(sP, xP, mi, bi, Bm, ldt, w.tauU, w.WU[buf], w.ZU[buf], w.Rall + i * b * b, b,
-                         true));
+    RUTV_CHECK(extract_reflectors(sP, mi, bi, Bm, ldt, w.WU[buf], mi, w.Rall + i * b * b, b, true));
+    RUTV_TRY(hipEventRecord(ev(EV_WU, i), sP));
+    RUTV_CHECK(t_factor(sP, xP, mi, bi, w.WU[buf], w.tauU, w.TU[buf]));
     RUTV_TRY(hipEventRecord(ev(EV_U, i), sP));
-    // ---- stream T: left transform of the remaining columns
-    RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_U, i), 0));
+    // ---- stream T: left transform of the remaining columns,
+    // C <- C - W (Tf^T (W^T C))
+    RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_WU, i), 0));
     if (e < n) {
       double* C = T + s + e * ldt;
       RUTV_CHECK(gemm(sT, xT, true, false, bi, ni - bi, mi, 1.0, w.WU[buf], mi, C, ldt, 0.0, w.X3, bi));
-      RUTV_CHECK(gemm(sT, xT, false, false, mi, ni - bi, bi, -1.0, w.ZU[buf], mi, w.X3, bi, 1.0, C, ldt));
+      RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_U, i), 0));
+      RUTV_CHECK(gemm(sT, xT, true, false, bi, ni - bi, bi, 1.0, w.TU[buf], bi, w.X3, bi, 0.0, w.X3t, bi));
+      RUTV_CHECK(gemm(sT, xT, false, false, mi, ni - bi, bi, -1.0, w.WU[buf], mi, w.X3t, bi, 1.0, C, ldt));
+    } else {
+      RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_U, i), 0));
     }
     s = e;
   }
