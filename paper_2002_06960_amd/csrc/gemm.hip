@@ -4,8 +4,10 @@
 // products of the compact-WY updates and the rank-b updates A -= X Z^T) goes
 // through this kernel.  Tiles of BM x BN are staged through LDS in BK-deep
 // slices (double buffered, next slice prefetched into registers while the
-// current one feeds the matrix cores).  Four waves per workgroup each own a
-// (BM/2) x (BN/2) sub-tile built from 16x16 blocks of v_mfma_f64_16x16x4.
+// current one feeds the matrix cores).  Eight waves per workgroup, a 2 x 4 grid,
+// each own a (BM/2) x (BN/4) sub-tile built from 16x16 blocks of
+// v_mfma_f64_16x16x4; with two workgroups per CU every SIMD interleaves four
+// waves, which hides the LDS and barrier latency of the matrix-core work.
 //
 // The MFMA is issued with the operands swapped (op(B)^T block as the 16x4
 // operand, op(A)^T block as the 4x16 operand) so that the 16 lanes of a lane
@@ -22,7 +24,8 @@ namespace rutv {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGemmThreads = 256;
+constexpr int kWavesM = 2, kWavesN = 4;  // wave grid of a workgroup
+constexpr int kGemmThreads = 64 * kWavesM * kWavesN;
 
 // Global -> register loads of one operand slice.  An operand is either
 // contiguous along the tile edge ("edge-major": op(A) = A, op(B) = B^T) or
@@ -37,9 +40,9 @@ __device__ __forceinline__ double keep_or_zero(double x, bool keep) {
   return __longlong_as_double(__double_as_longlong(x) & m);
 }
 
-template <bool KMAJOR, int BE_, int BX, int BK>
+template <bool KMAJOR, int BE_, int BX, int BK, int NT>
 struct SliceLoader {
-  static constexpr int kStride = kGemmThreads / (KMAJOR ? BK : BX);  // tile-edge (or k) step per r
+  static constexpr int kStride = NT / (KMAJOR ? BK : BX);  // tile-edge (or k) step per r
   const double* base;  // matrix pointer
   i64 ld;
   int e0;              // this thread's first edge index (edge-major: fixed; k-major: + kStride r)
@@ -107,21 +110,22 @@ __device__ __forceinline__ void tile_of(int L, int tilesM, int tilesN, int split
   nt = t2 / gm;
 }
 
-template <bool TA, bool TB, int BM, int BN, int BK, int MINB = 2>
-__global__ __launch_bounds__(kGemmThreads, MINB) void dgemm_mfma_kernel(
+template <bool TA, bool TB, int BM, int BN, int BK, int MINB = 2, int WGM = 2, int WGN = 2>
+__global__ __launch_bounds__(64 * WGM * WGN, MINB) void dgemm_mfma_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, i64 lda,
     const double* __restrict__ B, i64 ldb, double beta, double* __restrict__ C, i64 ldc,
     int kchunk, double* __restrict__ part, int tilesM, int tilesN, int splits) {
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int NT = 64 * WGM * WGN;  // threads: a WGM x WGN grid of waves
+  constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int MI = WM / 16, NJ = WN / 16;
   constexpr int LDAS = BM + 1, LDBS = BN + 1;  // +1 double: conflict-free transposing stores
-  constexpr int AE = BM * BK / kGemmThreads, BE = BN * BK / kGemmThreads;
-  static_assert(AE * kGemmThreads == BM * BK && BE * kGemmThreads == BN * BK, "tile/threads");
+  constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
+  static_assert(AE * NT == BM * BK && BE * NT == BN * BK, "tile/threads");
   __shared__ double As[2][BK * LDAS];
   __shared__ double Bs[2][BK * LDBS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm0 = (wave & 1) * WM, wn0 = (wave >> 1) * WN;
+  const int wm0 = (wave % WGM) * WM, wn0 = (wave / WGM) * WN;
 
   int mt, nt, kz;
   tile_of(blockIdx.x, tilesM, tilesN, splits, mt, nt, kz);
@@ -129,8 +133,8 @@ __global__ __launch_bounds__(kGemmThreads, MINB) void dgemm_mfma_kernel(
   const int kbeg = kz * kchunk;
   const int kend = min(K, kbeg + kchunk);
 
-  SliceLoader<TA, AE, BM, BK> la;
-  SliceLoader<!TB, BE, BN, BK> lb;
+  SliceLoader<TA, AE, BM, BK, NT> la;
+  SliceLoader<!TB, BE, BN, BK, NT> lb;
   la.init(A, lda, tid, m0, M);
   lb.init(B, ldb, tid, n0, N);
   double ra[AE], rb[BE];
@@ -279,10 +283,10 @@ void launch_tile(hipStream_t st, int bm, int M, int N, int K, double alpha, cons
   const int tilesM = (int)cdiv(M, bm), tilesN = (int)cdiv(N, bm);
   const dim3 grid(tilesM * tilesN * splits);
   if (bm == 128)
-    dgemm_mfma_kernel<TA, TB, 128, 128, kBK><<<grid, kGemmThreads, 0, st>>>(
+    dgemm_mfma_kernel<TA, TB, 128, 128, kBK, 2, kWavesM, kWavesN><<<grid, kGemmThreads, 0, st>>>(
         M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, tilesN, splits);
   else
-    dgemm_mfma_kernel<TA, TB, 64, 64, kBK><<<grid, kGemmThreads, 0, st>>>(
+    dgemm_mfma_kernel<TA, TB, 64, 64, kBK, 2, kWavesM, kWavesN><<<grid, kGemmThreads, 0, st>>>(
         M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, tilesN, splits);
 }
 
