@@ -61,6 +61,26 @@ int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda,
                    double* U, double* T, double* V);
 
 /*
+ * randutv_factor_ex -- randutv_factor with a choice of arithmetic for the
+ * sketch and power-iteration products Y = (B^T B)^q B^T G of every step
+ * (Section 3.1; they only choose the subspace that V^ spans).
+ *   sketch_bits : RANDUTV_SKETCH_FP64 (64): FP64 matrix cores, as randutv_factor;
+ *                 RANDUTV_SKETCH_FP32 (32): operands rounded to FP32 and
+ *                 multiplied on the FP32 matrix cores (FP64 storage, FP32
+ *                 accumulation within a K split).
+ * Every transform applied to T, U and V (Householder vectors, block factors,
+ * updates, the b x b SVDs) stays FP64, so A = U T V^T holds to FP64 accuracy
+ * either way; with FP32 the subspaces (hence T, U, V themselves) differ from
+ * the FP64 ones by the perturbation of the sketch.  Errors as randutv_factor,
+ * plus -11 for an unknown sketch_bits.
+ */
+#define RANDUTV_SKETCH_FP64 64
+#define RANDUTV_SKETCH_FP32 32
+int randutv_factor_ex(int64_t m, int64_t n, const double* A, int64_t lda,
+                      int64_t b, int32_t q, uint64_t seed,
+                      double* U, double* T, double* V, int32_t sketch_bits);
+
+/*
  * randutv_truncate -- rank-k truncation A_k = U(:, 0:k) T(0:k, :) V^T
  * (Section 1.1).  U m x m (ld m), T m x n (ld m), V n x n (ld n), Ak m x n
  * (ld m), all device pointers from a previous randutv_factor.
@@ -91,6 +111,13 @@ int randutv_sketch(uint64_t seed, uint64_t step, int64_t rows, int64_t cols,
 int randutv_dgemm(char transa, char transb, int64_t M, int64_t N, int64_t K,
                   double alpha, const double* A, int64_t lda, const double* B,
                   int64_t ldb, double beta, double* C, int64_t ldc);
+
+/* Same operation and arguments as randutv_dgemm, FP64 operands and result,
+ * with the operands rounded to FP32 and multiplied on the FP32 matrix cores
+ * (the product used by randutv_factor_ex with RANDUTV_SKETCH_FP32). */
+int randutv_gemm_f32(char transa, char transb, int64_t M, int64_t N, int64_t K,
+                     double alpha, const double* A, int64_t lda, const double* B,
+                     int64_t ldb, double beta, double* C, int64_t ldc);
 
 /* Householder QR of the m x k matrix A (m >= k, k <= 256) in place, LAPACK
  * dgeqr2 conventions (Figure 2's "unpivoted QR"): on return R is in the upper

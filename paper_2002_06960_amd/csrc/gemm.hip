@@ -23,6 +23,29 @@
 namespace rutv {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// matrix-core step of one compute type: D(16 x 16) += A(16 x 4) B(4 x 16), lane
+// l supplying A[l % 16][l / 16] and B[l / 16][l % 16]; kRow(r, lane) is the
+// row of D that register r of the lane holds (its column is lane % 16)
+template <class CT>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using V4 = dbl4;
+  __device__ __forceinline__ static V4 mma(double a, double b, V4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int r, int lane) { return 4 * r + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+  using V4 = flt4;
+  __device__ __forceinline__ static V4 mma(float a, float b, V4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int r, int lane) { return 4 * (lane >> 4) + r; }
+};
 
 constexpr int kWavesM = 2, kWavesN = 4;  // wave grid of a workgroup
 constexpr int kGemmThreads = 64 * kWavesM * kWavesN;
@@ -110,7 +133,7 @@ __device__ __forceinline__ void tile_of(int L, int tilesM, int tilesN, int split
   nt = t2 / gm;
 }
 
-template <bool TA, bool TB, int BM, int BN, int BK, int MINB = 2, int WGM = 2, int WGN = 2>
+template <class CT, bool TA, bool TB, int BM, int BN, int BK, int MINB = 2, int WGM = 2, int WGN = 2>
 __global__ __launch_bounds__(64 * WGM * WGN, MINB) void dgemm_mfma_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, i64 lda,
     const double* __restrict__ B, i64 ldb, double beta, double* __restrict__ C, i64 ldc,
@@ -121,8 +144,10 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void dgemm_mfma_kernel(
   constexpr int LDAS = BM + 1, LDBS = BN + 1;  // +1 double: conflict-free transposing stores
   constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
   static_assert(AE * NT == BM * BK && BE * NT == BN * BK, "tile/threads");
-  __shared__ double As[2][BK * LDAS];
-  __shared__ double Bs[2][BK * LDBS];
+  using MT = Mfma<CT>;
+  using V4 = typename MT::V4;
+  __shared__ CT As[2][BK * LDAS];
+  __shared__ CT Bs[2][BK * LDBS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave % WGM) * WM, wn0 = (wave / WGM) * WN;
@@ -141,16 +166,18 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void dgemm_mfma_kernel(
   bool ka[AE], kb[BE];
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < AE; ++r) As[buf][la.lds_k(r) * LDAS + la.lds_e(r)] = keep_or_zero(ra[r], ka[r]);
+    for (int r = 0; r < AE; ++r)
+      As[buf][la.lds_k(r) * LDAS + la.lds_e(r)] = static_cast<CT>(keep_or_zero(ra[r], ka[r]));
 #pragma unroll
-    for (int r = 0; r < BE; ++r) Bs[buf][lb.lds_k(r) * LDBS + lb.lds_e(r)] = keep_or_zero(rb[r], kb[r]);
+    for (int r = 0; r < BE; ++r)
+      Bs[buf][lb.lds_k(r) * LDBS + lb.lds_e(r)] = static_cast<CT>(keep_or_zero(rb[r], kb[r]));
   };
 
-  dbl4 acc[MI][NJ];
+  V4 acc[MI][NJ];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   if (nk > 0) {
@@ -164,12 +191,12 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void dgemm_mfma_kernel(
         la.load(ra, ka, kbeg + (t + 1) * BK, kend);
         lb.load(rb, kb, kbeg + (t + 1) * BK, kend);
       }
-      const double* as = As[cur];
-      const double* bs = Bs[cur];
+      const CT* as = As[cur];
+      const CT* bs = Bs[cur];
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         const int kr = kk + (lane >> 4), cl = lane & 15;
-        double af[MI], bf[NJ];
+        CT af[MI], bf[NJ];
 #pragma unroll
         for (int i = 0; i < MI; ++i) af[i] = as[kr * LDAS + wm0 + 16 * i + cl];
 #pragma unroll
@@ -178,18 +205,19 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void dgemm_mfma_kernel(
         for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int j = 0; j < NJ; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);
+            acc[i][j] = MT::mma(bf[j], af[i], acc[i][j]);
       }
       if (t + 1 < nk) sstore(cur ^ 1);
       __syncthreads();
     }
   }
 
-  // v_mfma_f64_16x16x4 leaves D(4r + lane/16, lane%16) in register r; with the
-  // swapped operands D is the transposed C block, so the lane holds
-  // C[m0+wm0+16i+(lane&15)][n0+wn0+16j+4r+(lane>>4)], r = 0..3.  The C values
-  // of one row block are loaded together (clamped addresses), then stored.
-  const int cm = lane & 15, cn = lane >> 4;
+  // register r of a lane holds D(MT::row(r, lane), lane % 16); with the swapped
+  // operands D is the transposed C block, so the lane holds
+  // C[m0+wm0+16i+(lane&15)][n0+wn0+16j+MT::row(r, lane)], r = 0..3.  The C
+  // values of one row block are loaded together (clamped addresses), then
+  // stored.
+  const int cm = lane & 15;
 #pragma unroll
   for (int i = 0; i < MI; ++i) {
     const int gm = m0 + wm0 + 16 * i + cm;
@@ -200,14 +228,14 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void dgemm_mfma_kernel(
       if (!part && beta != 0.0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int gnc = min(n0 + wn0 + 16 * j + 4 * r + cn, N - 1);
+          const int gnc = min(n0 + wn0 + 16 * j + MT::row(r, lane), N - 1);
           cv[r] = C[gmc + (i64)gnc * ldc];
         }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gn = n0 + wn0 + 16 * j + 4 * r + cn;
-        double v = alpha * acc[i][j][r];
+        const int gn = n0 + wn0 + 16 * j + MT::row(r, lane);
+        double v = alpha * static_cast<double>(acc[i][j][r]);
         if (!part && beta != 0.0) v += beta * cv[r];
         if (gm < M && gn < N) {
           if (part)
@@ -276,17 +304,17 @@ Plan choose_plan(i64 M, i64 N, i64 K) {
   return p;
 }
 
-template <bool TA, bool TB>
+template <class CT, bool TA, bool TB>
 void launch_tile(hipStream_t st, int bm, int M, int N, int K, double alpha, const double* A,
                  i64 lda, const double* B, i64 ldb, double beta, double* C, i64 ldc, int kchunk,
                  int splits, double* part) {
   const int tilesM = (int)cdiv(M, bm), tilesN = (int)cdiv(N, bm);
   const dim3 grid(tilesM * tilesN * splits);
   if (bm == 128)
-    dgemm_mfma_kernel<TA, TB, 128, 128, kBK, 2, kWavesM, kWavesN><<<grid, kGemmThreads, 0, st>>>(
+    dgemm_mfma_kernel<CT, TA, TB, 128, 128, kBK, 2, kWavesM, kWavesN><<<grid, kGemmThreads, 0, st>>>(
         M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, tilesN, splits);
   else
-    dgemm_mfma_kernel<TA, TB, 64, 64, kBK, 2, kWavesM, kWavesN><<<grid, kGemmThreads, 0, st>>>(
+    dgemm_mfma_kernel<CT, TA, TB, 64, 64, kBK, 2, kWavesM, kWavesN><<<grid, kGemmThreads, 0, st>>>(
         M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, tilesN, splits);
 }
 
@@ -299,7 +327,7 @@ i64 dgemm_work_elems(i64 M, i64 N, i64 K) {
 
 int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha, const double* A,
           i64 lda, const double* B, i64 ldb, double beta, double* C, i64 ldc, double* work,
-          i64 work_elems) {
+          i64 work_elems, bool f32) {
   if (M <= 0 || N <= 0) return RANDUTV_OK;
   if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return RANDUTV_ERR_TOO_LARGE;
   Plan p = choose_plan(M, N, K);
@@ -320,18 +348,25 @@ int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha, c
   const int cls = ta ? (tb ? K_GEMM_TT : K_GEMM_TN) : (tb ? K_GEMM_NT : K_GEMM_NN);
   LaunchTimer* tm = launch_timer();
   if (tm) tm->begin(st, cls);
-  if (!ta && !tb)
-    launch_tile<false, false>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C,
-                              ldc, p.kchunk, p.splits, part);
-  else if (ta && !tb)
-    launch_tile<true, false>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C,
-                             ldc, p.kchunk, p.splits, part);
-  else if (!ta && tb)
-    launch_tile<false, true>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C,
-                             ldc, p.kchunk, p.splits, part);
+  auto go = [&](auto ct) {
+    using CT = decltype(ct);
+    if (!ta && !tb)
+      launch_tile<CT, false, false>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta,
+                                    C, ldc, p.kchunk, p.splits, part);
+    else if (ta && !tb)
+      launch_tile<CT, true, false>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta,
+                                   C, ldc, p.kchunk, p.splits, part);
+    else if (!ta && tb)
+      launch_tile<CT, false, true>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta,
+                                   C, ldc, p.kchunk, p.splits, part);
+    else
+      launch_tile<CT, true, true>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta,
+                                  C, ldc, p.kchunk, p.splits, part);
+  };
+  if (f32)
+    go(0.0f);
   else
-    launch_tile<true, true>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C,
-                            ldc, p.kchunk, p.splits, part);
+    go(0.0);
   RUTV_TRY(hipGetLastError());
   if (tm) tm->end(st, cls, 2.0 * (double)M * (double)N * (double)K);
   if (part) {

@@ -22,10 +22,12 @@ const char* kernel_class_name(int cls);
 
 // ---- GEMM (gemm.hip) ------------------------------------------------------
 // C = alpha op(A) op(B) + beta C.  'work' (work_elems doubles) holds split-K
-// partial tiles; the launcher picks fewer splits when it is too small.
+// partial tiles; the launcher picks fewer splits when it is too small.  f32:
+// FP64 operands and result, operands rounded to FP32 and multiplied on the
+// FP32 matrix cores (FP32 accumulation within a split).
 int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha,
           const double* A, i64 lda, const double* B, i64 ldb, double beta,
-          double* C, i64 ldc, double* work, i64 work_elems);
+          double* C, i64 ldc, double* work, i64 work_elems, bool f32 = false);
 // split-K partial buffer size (doubles) that lets dgemm use its preferred plan
 i64 dgemm_work_elems(i64 M, i64 N, i64 K);
 

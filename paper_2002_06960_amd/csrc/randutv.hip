@@ -275,8 +275,9 @@ static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wa
 
 static int gemm(hipStream_t st, const StreamWS& x, bool ta, bool tb, i64 M, i64 N, i64 K,
                 double alpha, const double* A, i64 lda, const double* B, i64 ldb, double beta,
-                double* C, i64 ldc) {
-  return dgemm(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, x.splitk, x.splitk_elems);
+                double* C, i64 ldc, bool f32 = false) {
+  return dgemm(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, x.splitk, x.splitk_elems,
+               f32);
 }
 
 // block factor Tf (k x k, ld k) of the reflectors W (rows x k, unit lower
@@ -307,8 +308,10 @@ static int right_mul_small(hipStream_t st, const StreamWS& x, i64 rows, i64 k, d
   return RANDUTV_OK;
 }
 
+// sketch32: the sketch and power-iteration products Y = (B^T B)^q B^T G on the
+// FP32 matrix cores (FP64 storage); every transform of T, U and V stays FP64
 static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uint64_t seed,
-                       double* U, double* T, double* V) {
+                       double* U, double* T, double* V, bool sketch32) {
   Context& cx = ctx();
   RUTV_CHECK(cx.init());
   hipStream_t sT = cx.streams[ST_T], sP = cx.streams[ST_P], sUV = cx.streams[ST_UV],
@@ -397,10 +400,10 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     // ---- stream T: sketch, power iteration, QR(Y), compact WY of V^
     if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_UV, i - 2), 0));  // WV[buf] free
     RUTV_CHECK(sketch(sT, seed, (uint64_t)i, mi, bi, w.G, mi));
-    RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.G, mi, 0.0, w.Y, ni));
+    RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.G, mi, 0.0, w.Y, ni, sketch32));
     for (int it = 0; it < q; ++it) {
-      RUTV_CHECK(gemm(sT, xT, false, false, mi, bi, ni, 1.0, Bm, ldt, w.Y, ni, 0.0, w.Zp, mi));
-      RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.Zp, mi, 0.0, w.Y, ni));
+      RUTV_CHECK(gemm(sT, xT, false, false, mi, bi, ni, 1.0, Bm, ldt, w.Y, ni, 0.0, w.Zp, mi, sketch32));
+      RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.Zp, mi, 0.0, w.Y, ni, sketch32));
     }
     RUTV_TRY(hipEventRecord(ev(EV_PRE, i), sT));
     if (i >= 1) RUTV_CHECK(uv_and_svd(i - 1, true));
@@ -485,6 +488,11 @@ extern "C" {
 
 int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
                    uint64_t seed, double* U, double* T, double* V) {
+  return randutv_factor_ex(m, n, A, lda, b, q, seed, U, T, V, RANDUTV_SKETCH_FP64);
+}
+
+int randutv_factor_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                      uint64_t seed, double* U, double* T, double* V, int32_t sketch_bits) {
   if (m < 0) return -1;
   if (n < 0 || n > m) return -2;
   if (m == 0 || n == 0) return RANDUTV_OK;
@@ -496,10 +504,11 @@ int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
   if (T == A && lda != m) return -9;
   if (U && (U == T || U == V)) return -8;
   if (V && V == T) return -10;
+  if (sketch_bits != RANDUTV_SKETCH_FP64 && sketch_bits != RANDUTV_SKETCH_FP32) return -11;
   if (std::min(b, n) > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
-  return factor_impl(m, n, A, lda, b, q, seed, U, T, V);
+  return factor_impl(m, n, A, lda, b, q, seed, U, T, V, sketch_bits == RANDUTV_SKETCH_FP32);
 }
 
 int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const double* T,
@@ -555,9 +564,9 @@ int randutv_sketch(uint64_t seed, uint64_t step, int64_t rows, int64_t cols, dou
   return RANDUTV_OK;
 }
 
-int randutv_dgemm(char transa, char transb, int64_t M, int64_t N, int64_t K, double alpha,
-                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
-                  double* C, int64_t ldc) {
+static int gemm_entry(char transa, char transb, int64_t M, int64_t N, int64_t K, double alpha,
+                      const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                      double* C, int64_t ldc, bool f32) {
   const bool ta = transa == 'T' || transa == 't', tb = transb == 'T' || transb == 't';
   if (!ta && transa != 'N' && transa != 'n') return -1;
   if (!tb && transb != 'N' && transb != 'n') return -2;
@@ -578,9 +587,21 @@ int randutv_dgemm(char transa, char transb, int64_t M, int64_t N, int64_t K, dou
   RUTV_CHECK(cx.reserve(sizeof(double) * std::max<i64>(sk, 1)));
   set_launch_timer(nullptr);
   RUTV_CHECK(dgemm(cx.st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                   reinterpret_cast<double*>(cx.ws), sk));
+                   reinterpret_cast<double*>(cx.ws), sk, f32));
   RUTV_TRY(hipStreamSynchronize(cx.st));
   return RANDUTV_OK;
+}
+
+int randutv_dgemm(char transa, char transb, int64_t M, int64_t N, int64_t K, double alpha,
+                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                  double* C, int64_t ldc) {
+  return gemm_entry(transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, false);
+}
+
+int randutv_gemm_f32(char transa, char transb, int64_t M, int64_t N, int64_t K, double alpha,
+                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                     double* C, int64_t ldc) {
+  return gemm_entry(transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, true);
 }
 
 int randutv_geqrf(int64_t m, int64_t k, double* A, int64_t lda, double* tau) {

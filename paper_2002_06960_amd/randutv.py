@@ -24,9 +24,11 @@ _I64, _I32, _U64, _D, _P, _C = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                                 ctypes.c_void_p, ctypes.c_char)
 SIGNATURES = {
     "randutv_factor": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P]),
+    "randutv_factor_ex": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P, _I32]),
     "randutv_truncate": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _P]),
     "randutv_sketch": (ctypes.c_int, [_U64, _U64, _I64, _I64, _P, _I64]),
     "randutv_dgemm": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
+    "randutv_gemm_f32": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
     "randutv_geqrf": (ctypes.c_int, [_I64, _I64, _P, _I64, _P]),
     "randutv_larft": (ctypes.c_int, [_I64, _I64, _P, _I64, _P, _P, _I64]),
     "randutv_gesvj": (ctypes.c_int, [_I64, _P, _I64, _P, _P, _P, ctypes.POINTER(_I32)]),
@@ -128,10 +130,13 @@ def _out(x, rows, cols, device):
 
 
 def randutv_factor(A, b: int, q: int, seed: int = 0, build_u: bool = True,
-                   build_v: bool = True, in_place: bool = False, U=None, T=None, V=None) -> Tuple:
+                   build_v: bool = True, in_place: bool = False, U=None, T=None, V=None,
+                   sketch_bits: int = 64) -> Tuple:
     """A = U T V^T.  Returns (U, T, V) column-major tensors (U/V None if not built).
 
-    U, T, V may be given as preallocated column-major outputs."""
+    U, T, V may be given as preallocated column-major outputs.  sketch_bits
+    32 runs the sketch and power-iteration products on the FP32 matrix cores
+    (randutv_factor_ex); 64 is the all-FP64 randutv_factor."""
     lib = load()
     A, lda = as_colmajor(A)
     m, n = A.shape
@@ -142,8 +147,13 @@ def randutv_factor(A, b: int, q: int, seed: int = 0, build_u: bool = True,
     U = _out(U, m, m, A.device) if build_u else None
     V = _out(V, n, n, A.device) if build_v else None
     _sync()
-    _check("randutv_factor", lib.randutv_factor(m, n, _ptr(A), lda, b, q, seed & (2**64 - 1),
-                                                _ptr(U), _ptr(T), _ptr(V)))
+    if sketch_bits == 64:
+        _check("randutv_factor", lib.randutv_factor(m, n, _ptr(A), lda, b, q, seed & (2**64 - 1),
+                                                    _ptr(U), _ptr(T), _ptr(V)))
+    else:
+        _check("randutv_factor_ex", lib.randutv_factor_ex(m, n, _ptr(A), lda, b, q,
+                                                          seed & (2**64 - 1), _ptr(U), _ptr(T),
+                                                          _ptr(V), sketch_bits))
     return U, T, V
 
 
@@ -169,8 +179,10 @@ def randutv_sketch(seed: int, step: int, rows: int, cols: int, device=None):
     return G
 
 
-def randutv_dgemm(transa: str, transb: str, alpha: float, A, B, beta: float = 0.0, C=None):
-    """C = alpha op(A) op(B) + beta C (FP64 MFMA kernels).  Returns C."""
+def randutv_dgemm(transa: str, transb: str, alpha: float, A, B, beta: float = 0.0, C=None,
+                  f32: bool = False):
+    """C = alpha op(A) op(B) + beta C (FP64 MFMA kernels; f32: FP64 operands and
+    result, FP32 matrix-core arithmetic).  Returns C."""
     lib = load()
     A, lda = as_colmajor(A)
     B, ldb = as_colmajor(B)
@@ -185,8 +197,9 @@ def randutv_dgemm(transa: str, transb: str, alpha: float, A, B, beta: float = 0.
             raise ValueError("C must be column-major")
         ldc = max(1, C.stride(1) if N > 1 else M)
     _sync()
-    _check("randutv_dgemm", lib.randutv_dgemm(transa.encode(), transb.encode(), M, N, K, alpha,
-                                              _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C), ldc))
+    fn = "randutv_gemm_f32" if f32 else "randutv_dgemm"
+    _check(fn, getattr(lib, fn)(transa.encode(), transb.encode(), M, N, K, alpha, _ptr(A), lda,
+                                _ptr(B), ldb, beta, _ptr(C), ldc))
     return C
 
 

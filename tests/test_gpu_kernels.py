@@ -147,3 +147,27 @@ def test_gesvj_rejects_nonfinite():
     with pytest.raises(pkg.RandUTVError) as e:
         pkg.randutv_gesvj(to_dev(R))
     assert e.value.code == 3
+
+
+@pytest.mark.parametrize("ta,tb", list(itertools.product("NT", "NT")))
+@pytest.mark.parametrize("M,N,K", [(37, 53, 29), (300, 257, 1000), (2500, 256, 3000), (700, 700, 256)])
+def test_gemm_f32_matches_numpy(ta, tb, M, N, K):
+    """FP64 operands rounded to FP32 and multiplied on the FP32 matrix cores:
+    each product carries two roundings of the operands and at most K + 1 of the
+    accumulation (2^-24 each), the FP64 epilogue adds beta C exactly enough."""
+    rng = np.random.default_rng(M * 5 + N * 7 + K)
+    A = rng.standard_normal((K, M) if ta == "T" else (M, K))
+    B = rng.standard_normal((N, K) if tb == "T" else (K, N))
+    C0 = rng.standard_normal((M, N))
+    opA = A.T if ta == "T" else A
+    opB = B.T if tb == "T" else B
+    for alpha, beta in ((1.0, 0.0), (-1.0, 1.0)):
+        C = pkg.randutv_dgemm(ta, tb, alpha, to_dev(A), to_dev(B), beta, to_dev(C0), f32=True)
+        ref = alpha * (opA @ opB) + beta * C0
+        bound = abs(alpha) * (np.abs(opA) @ np.abs(opB)) * (K + 4) * 2.0**-24 + abs(beta) * np.abs(C0) * 2.0**-50
+        err = np.abs(to_host(C) - ref)
+        assert np.all(err <= bound), (alpha, beta, (err / bound).max())
+        # and it is not the FP64 result: the operands really are rounded
+        if K >= 256:
+            C64 = to_host(pkg.randutv_dgemm(ta, tb, alpha, to_dev(A), to_dev(B), beta, to_dev(C0)))
+            assert np.abs(to_host(C) - C64).max() > 1e3 * 2.0**-52 * np.abs(ref).max()

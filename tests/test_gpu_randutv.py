@@ -188,3 +188,39 @@ def test_full_size_invariants_and_step0(m, n):
     assert np.all(np.diag(Th0) <= 0.99 ** np.arange(1, b + 1) * (1 + 1e-10))
     del U, T, V, A
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("m,n,b,q,kind,close", [(512, 512, 64, 2, "exp", True),
+                                                (300, 200, 32, 1, "iid", True),
+                                                (600, 600, 128, 2, "log8", False)])
+def test_fp32_sketch_keeps_the_fp64_factorization(m, n, b, q, kind, close):
+    """Sketch and power iteration on the FP32 matrix cores (randutv_factor_ex):
+    every transform of T, U and V is still FP64, so the invariants hold to the
+    FP64 bar.  T itself moves from the FP64 oracle's only through the subspace
+    the sketch selects: checked loosely where the powered spectrum within a
+    block stays inside FP32's range (exp, iid); for log8 with q = 2 the
+    columns of one block's sketch span ~40 decades, far beyond FP32, so the
+    trailing directions of a block are chosen by rounding and only the
+    invariants are asserted (the distances are printed)."""
+    A = make_matrix(kind, m, n, seed=2)
+    Ad = to_dev(A)
+    U, T, V = pkg.randutv_factor(Ad, b, q, 0, sketch_bits=32)
+    res, eu, ev, lower = invariants_dev(Ad, U, T, V)
+    assert res <= TOL_RES and eu <= TOL_ORTH and ev <= TOL_ORTH and lower == 0.0
+    assert diag_blocks_ok(to_host(T), b)
+    Uo, To, Vo = ro.randutv(A, b, q, 0)
+    nA = np.linalg.norm(A)
+    Th = to_host(T)
+    dd = np.abs(np.abs(np.diag(Th)) - np.abs(np.diag(To))).max() / nA
+    errs = []
+    for k in (b, min(n, 2 * b)):
+        Ak = to_host(pkg.randutv_truncate(U, T, V, k))
+        ek = np.linalg.norm(A - Ak) / nA
+        eko = np.linalg.norm(A - Uo[:, :k] @ To[:k, :] @ Vo.T) / nA
+        errs.append((k, ek, eko))
+    print(f"fp32 sketch {m}x{n} b={b} q={q} {kind}: max |d_fp32 - d_fp64| / |A| = {dd:.2e}; "
+          f"rank-k errors (k, fp32, fp64): {errs}")
+    if close:
+        assert dd <= 1e-4
+        for k, ek, eko in errs:
+            assert abs(ek - eko) <= 1e-4 * max(eko, 1e-12) + 1e-9, (k, ek, eko)
