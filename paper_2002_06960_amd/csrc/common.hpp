@@ -33,23 +33,29 @@ __device__ __forceinline__ double wave_max(double v) {
 // larger than a fraction of the chip).  The counter must be zero at launch;
 // the n-th barrier waits for n * gridDim.x arrivals.  The wait is bounded: on
 // expiry it records RANDUTV_ERR_SYNC in *err and returns, so every wave exits.
+//
+// Arrival is a release increment (one L2 write-back); the wait polls with
+// relaxed loads and ends with a single acquire fence.  An acquire load per
+// poll would invalidate the L2 of the XCD on every iteration, which starves
+// whatever else runs there (the GEMMs of the other streams).  Every increment
+// is a read-modify-write, so the value that ends the wait lies in the release
+// sequence of every arrival and the fence synchronizes with all of them.
 // ---------------------------------------------------------------------------
 constexpr unsigned kSpinLimit = 1u << 26;
 
 __device__ __forceinline__ void grid_barrier(unsigned* counter, unsigned target, int* err) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
     __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit) {
         __hip_atomic_store(err, RANDUTV_ERR_SYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
