@@ -140,7 +140,22 @@ struct Context {
       ws_bytes = 0;
     }
     device = dev;
-    for (auto& x : streams) RUTV_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    // Streams created with a CU mask (here: every CU) get a hardware queue of
+    // their own; pooled streams share the few queues a process has by default,
+    // and a long kernel (a batch of Jacobi SVDs) then holds up every kernel of
+    // the other streams queued behind it on the same queue.
+    {
+      hipDeviceProp_t prop;
+      RUTV_TRY(hipGetDeviceProperties(&prop, dev));
+      const int words = (prop.multiProcessorCount + 31) / 32;
+      std::vector<uint32_t> mask(words, 0xffffffffu);
+      if (prop.multiProcessorCount % 32) mask[words - 1] = (1u << (prop.multiProcessorCount % 32)) - 1u;
+      for (auto& x : streams)
+        if (hipExtStreamCreateWithCUMask(&x, (uint32_t)words, mask.data()) != hipSuccess) {
+          (void)hipGetLastError();
+          RUTV_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        }
+    }
     for (auto& kind : ev)
       for (auto& e : kind) RUTV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (auto& e : ev_misc) RUTV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -189,17 +204,21 @@ struct StreamWS {
   double* splitk = nullptr;
   i64 splitk_elems = 0;
   double* Gram = nullptr;  // b x b
-  double* X2 = nullptr;    // max(m, n) x b
+  double* Tf = nullptr;    // b x b block factor (stream P)
   double* X = nullptr;     // max(m, n) x b
   PanelWork pw;
 };
 
-constexpr int kSvdGroup = 8;  // SVDs per batched launch
+#ifndef RUTV_SVD_GROUP
+#define RUTV_SVD_GROUP 8
+#endif
+constexpr int kSvdGroup = RUTV_SVD_GROUP;  // SVDs per batched launch
 
 struct FactorWS {
   StreamWS sw[NSTREAMS];
-  double *G, *Y, *Zp, *tauV, *tauU, *X3, *X3t;
-  double *WV[2], *TV[2], *WU[2], *TU[2];  // reflectors and their block factors, by step parity
+  double *G, *Y, *Zp, *tauV, *tauU, *X3;
+  // reflectors W and Z = W Tf^T (Tf their block factor), by step parity
+  double *WV[2], *ZV[2], *WU[2], *ZU[2];
   double *Rall, *dall, *Usall, *Vsall, *jwork;
   int* status;  // [0] finite flag, [1] panel sync error, [2 + 3i ..] sweeps, converged, sync error
 };
@@ -248,7 +267,7 @@ static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wa
     x.splitk = c.take<double>(sk);
     x.Gram = c.take<double>(b * b);
     x.X = c.take<double>(mx * b);
-    x.X2 = c.take<double>(mx * b);
+    x.Tf = c.take<double>(b * b);
     x.pw.xch = c.take<unsigned long long>(panel_work_elems(mx));
   }
   w.G = c.take<double>(m * b);
@@ -257,12 +276,11 @@ static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wa
   w.tauV = c.take<double>(b);
   w.tauU = c.take<double>(b);
   w.X3 = c.take<double>(b * n);
-  w.X3t = c.take<double>(b * n);
   for (int t = 0; t < 2; ++t) {
     w.WV[t] = c.take<double>(n * b);
-    w.TV[t] = c.take<double>(b * b);
+    w.ZV[t] = c.take<double>(n * b);
     w.WU[t] = c.take<double>(m * b);
-    w.TU[t] = c.take<double>(b * b);
+    w.ZU[t] = c.take<double>(m * b);
   }
   w.Rall = c.take<double>(nsteps * b * b);
   w.dall = c.take<double>(nsteps * b);
@@ -280,22 +298,24 @@ static int gemm(hipStream_t st, const StreamWS& x, bool ta, bool tb, i64 M, i64 
                f32);
 }
 
-// block factor Tf (k x k, ld k) of the reflectors W (rows x k, unit lower
-// trapezoidal, ld rows): I - W Tf W^T = H_1 ... H_k, from the Gram matrix W^T W
+// Z (rows x k, ld rows) := W Tf^T, Tf the block factor of the reflectors W
+// (rows x k, unit lower trapezoidal, ld rows), formed from the Gram matrix
+// W^T W: H_1 ... H_k = I - W Tf W^T = I - W Z^T, and its transpose is
+// I - Z W^T.  Every later use of the block reflector needs Z only.
 static int t_factor(hipStream_t st, const StreamWS& x, i64 rows, i64 k, const double* W,
-                    const double* tau, double* Tf) {
+                    const double* tau, double* Z) {
   RUTV_CHECK(gemm(st, x, true, false, k, k, rows, 1.0, W, rows, W, rows, 0.0, x.Gram, k));
-  RUTV_CHECK(larft_from_gram(st, k, x.Gram, k, tau, Tf, k));
+  RUTV_CHECK(larft_from_gram(st, k, x.Gram, k, tau, x.Tf, k));
+  RUTV_CHECK(gemm(st, x, false, true, rows, k, k, 1.0, W, rows, x.Tf, k, 0.0, Z, rows));
   return RANDUTV_OK;
 }
 
-// C(rows x cols, ld ldc) <- C (I - W Tf W^T) = C - ((C W) Tf) W^T, W: cols x k
-// (ld cols), Tf: k x k
+// C(rows x cols, ld ldc) <- C (I - W Tf W^T) = C - (C W) Z^T, W and Z: cols x k
+// (ld cols)
 static int right_apply(hipStream_t st, const StreamWS& x, i64 rows, i64 cols, i64 k, double* C,
-                       i64 ldc, const double* W, const double* Tf) {
+                       i64 ldc, const double* W, const double* Z) {
   RUTV_CHECK(gemm(st, x, false, false, rows, k, cols, 1.0, C, ldc, W, cols, 0.0, x.X, rows));
-  RUTV_CHECK(gemm(st, x, false, false, rows, k, k, 1.0, x.X, rows, Tf, k, 0.0, x.X2, rows));
-  RUTV_CHECK(gemm(st, x, false, true, rows, cols, k, -1.0, x.X2, rows, W, cols, 1.0, C, ldc));
+  RUTV_CHECK(gemm(st, x, false, true, rows, cols, k, -1.0, x.X, rows, Z, cols, 1.0, C, ldc));
   return RANDUTV_OK;
 }
 
@@ -364,9 +384,9 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     const int bf = (int)(j & 1);
     if (wait_pre) RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_PRE, j + 1), 0));
     RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_V, j), 0));
-    if (wantV) RUTV_CHECK(right_apply(sUV, xUV, n, nj, bj, V + sj * ldv, ldv, w.WV[bf], w.TV[bf]));
+    if (wantV) RUTV_CHECK(right_apply(sUV, xUV, n, nj, bj, V + sj * ldv, ldv, w.WV[bf], w.ZV[bf]));
     RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_U, j), 0));
-    if (wantU) RUTV_CHECK(right_apply(sUV, xUV, m, mj, bj, U + sj * ldu, ldu, w.WU[bf], w.TU[bf]));
+    if (wantU) RUTV_CHECK(right_apply(sUV, xUV, m, mj, bj, U + sj * ldu, ldu, w.WU[bf], w.ZU[bf]));
     RUTV_TRY(hipEventRecord(ev(EV_UV, j), sUV));
     // stream S: b x b SVDs in groups, then their right factors
     const bool last = sj + bj >= n;
@@ -412,18 +432,17 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     RUTV_TRY(hipEventRecord(ev(EV_WV, i), sT));
     // stream P: block factor of V^ while stream T forms X = T W
     RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_WV, i), 0));
-    if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_UV, i - 2), 0));  // TV/WU/TU[buf] free
-    RUTV_CHECK(t_factor(sP, xP, ni, bi, w.WV[buf], w.tauV, w.TV[buf]));
+    if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_UV, i - 2), 0));  // ZV/WU/ZU[buf] free
+    RUTV_CHECK(t_factor(sP, xP, ni, bi, w.WV[buf], w.tauV, w.ZV[buf]));
     RUTV_TRY(hipEventRecord(ev(EV_V, i), sP));
-    // right transform of all m rows, T <- T - ((T W) Tf) W^T: first the
+    // right transform of all m rows, T <- T - (T W) Z^T: first the
     // current column block (it feeds the panel QR on stream P), then the rest
     RUTV_CHECK(gemm(sT, xT, false, false, m, bi, ni, 1.0, T + s * ldt, ldt, w.WV[buf], ni, 0.0, xT.X, m));
     RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_V, i), 0));
-    RUTV_CHECK(gemm(sT, xT, false, false, m, bi, bi, 1.0, xT.X, m, w.TV[buf], bi, 0.0, xT.X2, m));
-    RUTV_CHECK(gemm(sT, xT, false, true, m, bi, bi, -1.0, xT.X2, m, w.WV[buf], ni, 1.0, T + s * ldt, ldt));
+    RUTV_CHECK(gemm(sT, xT, false, true, m, bi, bi, -1.0, xT.X, m, w.ZV[buf], ni, 1.0, T + s * ldt, ldt));
     RUTV_TRY(hipEventRecord(ev(EV_COLS, i), sT));
     if (e < n)
-      RUTV_CHECK(gemm(sT, xT, false, true, m, ni - bi, bi, -1.0, xT.X2, m, w.WV[buf] + bi, ni, 1.0,
+      RUTV_CHECK(gemm(sT, xT, false, true, m, ni - bi, bi, -1.0, xT.X, m, w.ZV[buf] + bi, ni, 1.0,
                       T + e * ldt, ldt));
     // ---- stream P: panel QR of the column block, its reflectors, then their
     // block factor while stream T forms W^T C
@@ -431,17 +450,16 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     RUTV_CHECK(panel_qr(sP, mi, bi, Bm, ldt, w.tauU, xP.pw));
     RUTV_CHECK(extract_reflectors(sP, mi, bi, Bm, ldt, w.WU[buf], mi, w.Rall + i * b * b, b, true));
     RUTV_TRY(hipEventRecord(ev(EV_WU, i), sP));
-    RUTV_CHECK(t_factor(sP, xP, mi, bi, w.WU[buf], w.tauU, w.TU[buf]));
+    RUTV_CHECK(t_factor(sP, xP, mi, bi, w.WU[buf], w.tauU, w.ZU[buf]));
     RUTV_TRY(hipEventRecord(ev(EV_U, i), sP));
     // ---- stream T: left transform of the remaining columns,
-    // C <- C - W (Tf^T (W^T C))
+    // C <- C - Z (W^T C)
     RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_WU, i), 0));
     if (e < n) {
       double* C = T + s + e * ldt;
       RUTV_CHECK(gemm(sT, xT, true, false, bi, ni - bi, mi, 1.0, w.WU[buf], mi, C, ldt, 0.0, w.X3, bi));
       RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_U, i), 0));
-      RUTV_CHECK(gemm(sT, xT, true, false, bi, ni - bi, bi, 1.0, w.TU[buf], bi, w.X3, bi, 0.0, w.X3t, bi));
-      RUTV_CHECK(gemm(sT, xT, false, false, mi, ni - bi, bi, -1.0, w.WU[buf], mi, w.X3t, bi, 1.0, C, ldt));
+      RUTV_CHECK(gemm(sT, xT, false, false, mi, ni - bi, bi, -1.0, w.ZU[buf], mi, w.X3, bi, 1.0, C, ldt));
     } else {
       RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_U, i), 0));
     }
