@@ -9,11 +9,27 @@
 // Panel kernel layout: P workgroups of 8 waves each own a contiguous slab of
 // at most 512 rows.  The panel is processed in leaves of 16 columns whose rows
 // stay in the registers of waves 0-3 (two rows per thread); all 8 waves share
-// the matrix-core work of the trailing updates.  Within a leaf each column needs one sum over
-// all rows (squares below the diagonal plus the dot products with the leaf's
-// remaining columns, combined with the pivot row): every workgroup publishes
-// its partial sums, reads everybody's and adds them in the same order, so all
-// workgroups derive the bit-identical reflector and update their own rows.
+// the matrix-core work.
+//
+// A leaf's reflectors need sums over all rows.  Rather than one exchange
+// between the workgroups per column, a leaf takes one exchange per pass: the
+// workgroups publish the Gram matrix G = B^T B of their rows below the leaf's
+// 16 x 16 diagonal block (B), the owners publish that block (the top block),
+// and every workgroup then runs the column recurrence of the leaf on 16 x 16
+// data alone.  The bottom part of every current column stays B m_c for a
+// 16-vector m_c (M = I at the start of a pass), so its squared norm is
+// m_c^T G m_c and its dot products m_c^T G m_d; the top block is updated
+// explicitly.  A pass ends with the coefficient matrix K that maps the
+// pass-start rows of B to their new values (v_j = scale_j B m_j for a
+// finished column j, B m_c for a column still open), applied by every
+// workgroup to its own rows.  The Gram form loses accuracy when a column's
+// bottom part has cancelled against the earlier reflectors; the pass stops
+// at a column whose bound (sum_a |m_a| sqrt(G_aa))^2 exceeds kGramCap times
+// its squared norm, and the next pass starts there from a fresh Gram matrix
+// of the current rows (the first column of a pass always has M = I, so
+// every pass finishes at least one column).  In exact arithmetic the result
+// is the column-by-column factorization.
+//
 // After a leaf, the rest of the panel receives the leaf's block reflector
 // C <- (I - W Tl W^T)^T C, with the Gram matrix of the leaf vectors and W^T C
 // summed over the workgroups in two rounds (each workgroup reduces a share of
@@ -25,9 +41,10 @@
 // device-scope atomics.  A reader polls until every word it needs carries the
 // current round number; since each word validates itself, only per-location
 // coherence is needed.  Round numbers start at 1 in every launch, whose
-// exchange area is cleared before the launch.  Column rounds alternate
-// between two buffers: a workgroup can only be one round ahead of the
-// slowest reader.
+// exchange area is cleared before the launch.  Leaf passes alternate between
+// two buffers: a workgroup can only be one pass ahead of the slowest reader.
+// Every workgroup sums the exchanged values in the same order, so all of them
+// take the same decisions and derive bit-identical reflectors.
 #include <algorithm>
 #include <type_traits>
 
@@ -41,20 +58,21 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kPQThreads = 512;  // 8 waves (two per SIMD keep the FP64 matrix cores busy)
 constexpr int kPQWaves = kPQThreads / WAVE;
 constexpr int kPQLeafThreads = 256;  // waves 0-3 hold the leaf rows
-constexpr int kPQLeafWaves = kPQLeafThreads / WAVE;
 constexpr int kPQRpt = 2;            // leaf rows per thread
 constexpr int kPQMaxRows = kPQLeafThreads * kPQRpt;
 constexpr int kPQNB = 16;                  // leaf width
-constexpr int kPQLdW = kPQMaxRows + 1;     // padded leading dimension of the leaf's W in LDS
+constexpr int kPQLdW = kPQMaxRows + 1;     // padded leading dimension of the leaf in LDS
 constexpr int kPQMaxWG = 64;
 constexpr int kPQTrail = kPQNB * kPQNB + kPQNB * (kPanelMaxCols - kPQNB);  // Gram + W^T C entries
+constexpr int kPQGramE = kPQNB * (kPQNB + 1) / 2;  // packed upper triangle of a leaf Gram matrix
+constexpr double kGramCap = 16.0;  // tolerated cancellation of a Gram-derived squared norm
 constexpr unsigned kPQSpinLimit = 1u << 22;
 
 // exchange area (64-bit words; a double is a pair of words)
-constexpr i64 kXCol = 0;                                 // [2][kPQMaxWG][kPQNB][2] column partials
-constexpr i64 kXPiv = kXCol + 2 * kPQMaxWG * kPQNB * 2;  // [2][kPQNB][2] pivot row
-constexpr i64 kXTot = kXPiv + 2 * kPQNB * 2;             // [kPQTrail][2] reduced trailing sums
-constexpr i64 kXPart = kXTot + kPQTrail * 2;             // [P][kPQTrail][2] trailing partials
+constexpr i64 kXGram = 0;                                     // [2][kPQMaxWG][kPQGramE][2] leaf Gram partials
+constexpr i64 kXTop = kXGram + 2 * kPQMaxWG * kPQGramE * 2;   // [2][kPQNB][kPQNB][2] leaf top block
+constexpr i64 kXTot = kXTop + 2 * kPQNB * kPQNB * 2;          // [kPQTrail][2] reduced trailing sums
+constexpr i64 kXPart = kXTot + kPQTrail * 2;                  // [P][kPQTrail][2] trailing partials
 
 static int panel_grid(i64 m) {
   i64 P = std::max<i64>(cdiv(m, kPQMaxRows), std::min<i64>(32, cdiv(m, 128)));
@@ -78,34 +96,27 @@ __device__ __forceinline__ double xval(u64 lo, u64 hi) {
   return __longlong_as_double((long long)((lo & 0xffffffffull) | (hi << 32)));
 }
 
-// one halving step of a wave reduce-scatter of kPQNB values: lanes with bit
-// OFF set keep values N..2N-1, the others 0..N-1, each adding its partner's
-template <int N, int OFF>
-__device__ __forceinline__ void reduce_scatter_step(double (&v)[kPQNB], int lane) {
-  const bool up = (lane & OFF) != 0;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const double send = up ? v[i] : v[i + N];
-    const double keep = up ? v[i + N] : v[i];
-    v[i] = keep + __shfl_xor(send, OFF, WAVE);
-  }
+// value of lane l (a wave-uniform index) in every lane
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// calls f(integral_constant<int, J>) for J = J0, J0 + 1, ... while J < n
+// calls f(integral_constant<int, J>) for J = J0, J0 + 1, ..., kPQNB - 1
 template <int J0>
 struct ForColumns {
   template <class F>
-  __device__ __forceinline__ static void run(int n, F& f) {
-    if (J0 < n) {
-      f(std::integral_constant<int, J0>{});
-      ForColumns<J0 + 1>::run(n, f);
-    }
+  __device__ __forceinline__ static void run(F& f) {
+    f(std::integral_constant<int, J0>{});
+    ForColumns<J0 + 1>::run(f);
   }
 };
 template <>
 struct ForColumns<kPQNB> {
   template <class F>
-  __device__ __forceinline__ static void run(int, F&) {}
+  __device__ __forceinline__ static void run(F&) {}
 };
 
 __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, double* __restrict__ A,
@@ -115,15 +126,15 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
   const int P = gridDim.x, wg = blockIdx.x;
   const int r0 = (int)((i64)m * wg / P), r1 = (int)((i64)m * (wg + 1) / P), R = r1 - r0;
 
-  __shared__ double Wl[kPQNB * kPQLdW];        // explicit W of the finished leaf
-  __shared__ double S[kPQNB * kPanelMaxCols];  // X = W^T C, then Tl^T X
-  __shared__ double red[kPQLeafWaves * kPQNB]; // per-wave column sums
-  __shared__ double pivl[kPQNB];               // pivot row (its owner only)
-  __shared__ double tsum[kPQNB];               // column totals
-  __shared__ double pivs[kPQNB];               // the pivot row as read back
-  __shared__ double Gs[kPQNB * kPQNB];
+  __shared__ double Wl[kPQNB * kPQLdW];        // leaf rows during a pass, then the leaf's explicit W
+  __shared__ double S[kPQNB * kPanelMaxCols];  // per-wave Gram partials; X = W^T C, then Tl^T X
+  __shared__ double Gs[kPQNB * kPQNB];         // Gram matrix (pass: bottom rows; trailing: W^T W)
   __shared__ double Tl[kPQNB * kPQNB];
+  __shared__ double Tops[kPQNB * kPQNB];       // top block, row-major
+  __shared__ double Kl[kPQNB * kPQNB];         // pass coefficients K(a, c) at a * 16 + c
   __shared__ double taul[kPQNB];
+  __shared__ double dgs[kPQNB];                // sqrt of the Gram diagonal
+  __shared__ int jstop;
   __shared__ int dead;
   if (threadIdx.x == 0) dead = 0;
   __syncthreads();
@@ -149,8 +160,8 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
     asm volatile("" : "+s"(z), "+v"(tid));
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     double* const Ab = A + z;
-    u64* const xcol = xch + z + kXCol;
-    u64* const xpiv = xch + z + kXPiv;
+    u64* const xgram = xch + z + kXGram;
+    u64* const xtop = xch + z + kXTop;
     u64* const xtot = xch + z + kXTot;
     u64* const xpart = xch + z + kXPart;
     double row[kPQRpt][kPQNB];
@@ -166,147 +177,207 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
         row[i][c] = (own[i] && c < nbl) ? Ab[(i64)gr[i] + (i64)(c0 + c) * lda] : 0.0;
     }
 
-    // one column of the leaf; jj is a compile-time constant in each instance
-    auto column = [&](auto jc) {
-      constexpr int jj = decltype(jc)::value;
-      const int j = c0 + jj;
+    for (int j0 = 0; j0 < nbl;) {
       const unsigned tag = ++rnd;
-      int zc = 0;
-      asm volatile("" : "+s"(zc));
-      // column masks (constants: the loop is unrolled, so the leaf stays in registers)
-      double msk[kPQNB];
+      const int par = (int)(tag & 1);
+      u64* const xg = xgram + (i64)par * kPQMaxWG * kPQGramE * 2;
+      u64* const xt = xtop + (i64)par * kPQNB * kPQNB * 2;
+      // rows to LDS (X(r, c) at Wl[c * kPQLdW + r]); the owners of top-block
+      // rows publish them
+      if (tid < kPQLeafThreads) {
 #pragma unroll
-      for (int c = 0; c < kPQNB; ++c) msk[c] = c > jj ? 1.0 : 0.0;
-      double x[kPQRpt];
+        for (int i = 0; i < kPQRpt; ++i) {
+          const int r = tid + kPQLeafThreads * i;
 #pragma unroll
-      for (int i = 0; i < kPQRpt; ++i) {
-        double xj = 0.0;
+          for (int c = 0; c < kPQNB; ++c) Wl[c * kPQLdW + r] = row[i][c];
+          const int t = gr[i] - c0;
+          if (own[i] && t >= 0 && t < nbl)
 #pragma unroll
-        for (int c = 0; c < kPQNB; ++c) xj = c == jj ? row[i][c] : xj;
-        x[i] = (own[i] && gr[i] > j) ? xj : 0.0;
-      }
-      // slot 0: squares below the diagonal; slot c > jj: dot with column c
-      if (wave < kPQLeafWaves) {
-      double v[kPQNB];
-      v[0] = 0.0;
-#pragma unroll
-      for (int i = 0; i < kPQRpt; ++i) v[0] += x[i] * x[i];
-#pragma unroll
-      for (int c = 1; c < kPQNB; ++c) {
-        v[c] = 0.0;
-#pragma unroll
-        for (int i = 0; i < kPQRpt; ++i) v[c] += x[i] * row[i][c];
-        v[c] *= msk[c];
-      }
-      // wave reduce-scatter: afterwards lane l holds slot l / 4
-      reduce_scatter_step<8, 32>(v, lane);
-      reduce_scatter_step<4, 16>(v, lane);
-      reduce_scatter_step<2, 8>(v, lane);
-      reduce_scatter_step<1, 4>(v, lane);
-      v[0] += __shfl_xor(v[0], 2, WAVE);
-      v[0] += __shfl_xor(v[0], 1, WAVE);
-      if ((lane & 3) == 0) red[wave * kPQNB + (lane >> 2)] = v[0];
-      }
-#pragma unroll
-      for (int i = 0; i < kPQRpt; ++i)
-        if (own[i] && gr[i] == j)
-#pragma unroll
-          for (int c = 0; c < kPQNB; ++c) pivl[c] = row[i][c];
-      __syncthreads();
-
-      {
-        const int s = lane & 15, g = lane >> 4;
-        u64* const xc = xcol + zc + (i64)(tag & 1) * kPQMaxWG * kPQNB * 2;
-        u64* const xp = xpiv + zc + (i64)(tag & 1) * kPQNB * 2;
-        if (wave == 0) {
-          if (g == 0) {
-            double ts = red[s];
-#pragma unroll
-            for (int w = 1; w < kPQLeafWaves; ++w) ts += red[w * kPQNB + s];
-            xput(xc + ((i64)wg * kPQNB + s) * 2, ts, tag);
-          } else if (g == 1 && j >= r0 && j < r1) {
-            xput(xp + s * 2, pivl[s], tag);
-          }
+            for (int c = 0; c < kPQNB; ++c) xput(xt + (i64)(t * kPQNB + c) * 2, row[i][c], tag);
         }
-        // wave w < 4 gathers slots 4 w .. 4 w + 3: lane (s4, g) reads slot
-        // 4 w + s4 of workgroups g, g + 16, ...; lanes g = 0 also the pivot row
-        if (wave < kPQLeafWaves) {
-          constexpr int NG = kPQMaxWG / 16;
-          const int s4 = lane & 3, gq = lane >> 2, slot = 4 * wave + s4;
-          u64 lo[NG], hi[NG], plo, phi;
+      }
+      __syncthreads();
+      // Gram matrix of the rows below the top block on the matrix cores: wave
+      // w takes local rows 64 w .. 64 w + 63, four per step; lane l supplies
+      // X(r, l % 16) as both operands, D(a, b) = sum_r X(r, a) X(r, b)
+      {
+        dbl4 g = {0.0, 0.0, 0.0, 0.0};
+        const int c = lane & 15;
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4) {
+          const int r = 64 * wave + 4 * s4 + (lane >> 4);
+          const double x = Wl[c * kPQLdW + r];
+          g = __builtin_amdgcn_mfma_f64_16x16x4f64((r < R && r0 + r >= c0 + nbl) ? x : 0.0,
+                                                   (r < R && r0 + r >= c0 + nbl) ? x : 0.0, g, 0, 0, 0);
+        }
+        // register q of lane l holds D(4 q + l / 16, l % 16)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S[wave * 256 + (4 * q + (lane >> 4)) * kPQNB + c] = g[q];
+      }
+      __syncthreads();
+      // this workgroup's Gram entries (waves summed in order), packed upper
+      // triangle e = b (b + 1) / 2 + a for a <= b
+      if (tid < kPQNB * kPQNB) {
+        const int a = tid & 15, b = tid >> 4;
+        if (a <= b) {
+          double sv = S[tid];
+#pragma unroll
+          for (int w = 1; w < kPQWaves; ++w) sv += S[w * 256 + tid];
+          xput(xg + ((i64)wg * kPQGramE + b * (b + 1) / 2 + a) * 2, sv, tag);
+        }
+      }
+      // gather: threads 0..135 sum one Gram entry over the workgroups in
+      // order; threads 256..511 read the top block
+      if (tid < kPQGramE) {
+        constexpr int NB = 16;
+        double sv = 0.0;
+        for (int w0 = 0; w0 < P; w0 += NB) {
+          u64 lo[NB], hi[NB];
           unsigned spins = 0;
           while (true) {
-            // branch-free: every lane loads valid words (clamped indices), the
-            // masks decide what counts
 #pragma unroll
-            for (int i = 0; i < NG; ++i) {
-              const int w = min(gq + 16 * i, P - 1);
-              lo[i] = xget(xc + ((i64)w * kPQNB + slot) * 2);
-              hi[i] = xget(xc + ((i64)w * kPQNB + slot) * 2 + 1);
+            for (int i = 0; i < NB; ++i) {
+              u64* p = xg + ((i64)min(w0 + i, P - 1) * kPQGramE + tid) * 2;
+              lo[i] = xget(p);
+              hi[i] = xget(p + 1);
             }
-            plo = xget(xp + slot * 2);
-            phi = xget(xp + slot * 2 + 1);
-            int have = (gq != 0) | (xhas(plo, tag) & xhas(phi, tag));
+            int have = 1;
 #pragma unroll
-            for (int i = 0; i < NG; ++i)
-              have &= (gq + 16 * i >= P) | (xhas(lo[i], tag) & xhas(hi[i], tag));
-            if (__all(have)) break;
-            if (give_up(spins)) break;
+            for (int i = 0; i < NB; ++i) have &= (w0 + i >= P) | (xhas(lo[i], tag) & xhas(hi[i], tag));
+            if (have || give_up(spins)) break;
           }
-          double acc = 0.0;
 #pragma unroll
-          for (int i = 0; i < NG; ++i) acc += gq + 16 * i < P ? xval(lo[i], hi[i]) : 0.0;
-          acc += __shfl_xor(acc, 4, WAVE);
-          acc += __shfl_xor(acc, 8, WAVE);
-          acc += __shfl_xor(acc, 16, WAVE);
-          acc += __shfl_xor(acc, 32, WAVE);
-          if (gq == 0) {
-            tsum[slot] = acc;
-            pivs[slot] = xval(plo, phi);
-          }
+          for (int i = 0; i < NB; ++i) sv += w0 + i < P ? xval(lo[i], hi[i]) : 0.0;
         }
+        int b = 0;
+        while ((b + 1) * (b + 2) / 2 <= tid) ++b;
+        const int a = tid - b * (b + 1) / 2;
+        Gs[a * kPQNB + b] = sv;
+        Gs[b * kPQNB + a] = sv;
+      } else if (tid >= kPQThreads - kPQNB * kPQNB) {
+        const int e = tid - (kPQThreads - kPQNB * kPQNB), t = e >> 4;
+        double v = 0.0;
+        if (t < nbl) {
+          unsigned spins = 0;
+          u64 lo, hi;
+          while (true) {
+            lo = xget(xt + (i64)e * 2);
+            hi = xget(xt + (i64)e * 2 + 1);
+            if ((xhas(lo, tag) & xhas(hi, tag)) || give_up(spins)) break;
+          }
+          v = xval(lo, hi);
+        }
+        Tops[e] = v;
       }
       __syncthreads();
+      if (tid < kPQNB) dgs[tid] = sqrt(fmax(Gs[tid * (kPQNB + 1)], 0.0));
 
-      // every thread derives the reflector from the same totals
-      double t = 0.0, scale = 0.0, beta, wc[kPQNB];
-      {
-        double tot[kPQNB];
+      // the leaf's column recurrence from column j0 (wave 0; lane c % 16
+      // follows column c: its top-block column Tc, its bottom coefficients Mc)
+      if (wave == 0) {
+        const int c = lane & 15;
+        double Tc[kPQNB], Mc[kPQNB];
 #pragma unroll
-        for (int c = 0; c < kPQNB; ++c) tot[c] = tsum[c];
-        double alpha = 0.0;
-#pragma unroll
-        for (int c = 0; c < kPQNB; ++c) alpha = c == jj ? pivs[c] : alpha;
-        const double sq = tot[0];
-        beta = alpha;
-        if (sq != 0.0) {
-          const double nrm = sqrt(alpha * alpha + sq);
-          beta = alpha >= 0.0 ? -nrm : nrm;
-          t = (beta - alpha) / beta;
-          scale = 1.0 / (alpha - beta);
+        for (int a = 0; a < kPQNB; ++a) {
+          Tc[a] = Tops[a * kPQNB + c];
+          Mc[a] = a == c ? 1.0 : 0.0;
         }
+        int jf = nbl;
+        auto step = [&](auto jc) {
+          constexpr int jj = decltype(jc)::value;
+          if (jj < j0 || jj >= jf) return;
+          double mj[kPQNB], tj[kPQNB];
 #pragma unroll
-        for (int c = 0; c < kPQNB; ++c) wc[c] = (c < nbl) ? msk[c] * (pivs[c] + scale * tot[c]) : 0.0;
-        if (tid == 0) {
-          taul[jj] = t;
-          if (wg == 0) tau[j] = t;
+          for (int a = 0; a < kPQNB; ++a) mj[a] = a <= jj ? lane_value(Mc[a], jj) : 0.0;
+#pragma unroll
+          for (int t = jj; t < kPQNB; ++t) tj[t] = lane_value(Tc[t], jj);
+          // g = G m_j (lane c: g_c), then d_c = (top and bottom) column j . column c
+          double gcv = 0.0;
+#pragma unroll
+          for (int a = 0; a <= jj; ++a) gcv += Gs[c * kPQNB + a] * mj[a];
+          double dc = 0.0;
+#pragma unroll
+          for (int t = jj + 1; t < kPQNB; ++t) dc += tj[t] * Tc[t];
+#pragma unroll
+          for (int a = 0; a < kPQNB; ++a) dc += lane_value(gcv, a) * Mc[a];
+          const double sig2 = lane_value(dc, jj);  // squared norm below the diagonal
+          double eb = 0.0;
+#pragma unroll
+          for (int a = 0; a <= jj; ++a) eb += fabs(mj[a]) * dgs[a];
+          if (jj > j0 && eb * eb > kGramCap * sig2) {
+            jf = jj;
+            return;
+          }
+          const double alpha = tj[jj];
+          double t = 0.0, scale = 0.0, beta = alpha;
+          if (sig2 != 0.0) {
+            const double nrm = sqrt(alpha * alpha + sig2);
+            beta = alpha >= 0.0 ? -nrm : nrm;
+            t = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+          }
+          if (c > jj) {
+            const double w = Tc[jj] + scale * dc;
+            const double f = t * scale * w;
+            Tc[jj] -= t * w;
+#pragma unroll
+            for (int r = jj + 1; r < kPQNB; ++r) Tc[r] -= f * tj[r];
+#pragma unroll
+            for (int a = 0; a <= jj; ++a) Mc[a] -= f * mj[a];
+          } else if (c == jj) {
+#pragma unroll
+            for (int a = 0; a < kPQNB; ++a) Mc[a] = scale * mj[a];
+            Tc[jj] = beta;
+#pragma unroll
+            for (int r = jj + 1; r < kPQNB; ++r) Tc[r] = scale * tj[r];
+          }
+          if (lane == 0) {
+            taul[jj] = t;
+            if (wg == 0) tau[c0 + jj] = t;
+          }
+        };
+        ForColumns<0>::run(step);
+        // K(:, c): identity before j0, scale_c m_c for finished columns, m_c
+        // for the open ones
+        if (lane < kPQNB) {
+#pragma unroll
+          for (int a = 0; a < kPQNB; ++a) {
+            Kl[a * kPQNB + c] = c < j0 ? (a == c ? 1.0 : 0.0) : Mc[a];
+            Tops[a * kPQNB + c] = Tc[a];
+          }
+        }
+        if (lane == 0) jstop = jf;
+      }
+      __syncthreads();
+      // apply the pass to this workgroup's rows: top-block rows from the
+      // recurrence, rows below through K, rows above unchanged
+      if (tid < kPQLeafThreads) {
+#pragma unroll
+        for (int i = 0; i < kPQRpt; ++i) {
+          const int r = tid + kPQLeafThreads * i, t = gr[i] - c0;
+          double x[kPQNB];
+#pragma unroll
+          for (int a = 0; a < kPQNB; ++a) x[a] = Wl[a * kPQLdW + r];
+          if (t >= nbl) {
+#pragma unroll
+            for (int cc = 0; cc < kPQNB; ++cc) {
+              double sv = 0.0;
+#pragma unroll
+              for (int a = 0; a < kPQNB; ++a) sv += x[a] * Kl[a * kPQNB + cc];
+              row[i][cc] = sv;
+            }
+          } else if (t >= 0) {
+#pragma unroll
+            for (int cc = 0; cc < kPQNB; ++cc) row[i][cc] = Tops[t * kPQNB + cc];
+          } else {
+#pragma unroll
+            for (int cc = 0; cc < kPQNB; ++cc) row[i][cc] = x[cc];
+          }
         }
       }
-#pragma unroll
-      for (int i = 0; i < kPQRpt; ++i) {
-        if (wave >= kPQLeafWaves) break;
-        const bool live = own[i] && gr[i] >= j, below = gr[i] > j;
-        const double vr = below ? x[i] * scale : 1.0;
-        const double tv = live ? t * vr : 0.0;
-        const double nj = below ? vr : beta;
-#pragma unroll
-        for (int c = 0; c < kPQNB; ++c) {
-          row[i][c] -= tv * wc[c];
-          if (c == jj && live) row[i][c] = nj;
-        }
-      }
-    };
-    ForColumns<0>::run(nbl, column);
+      j0 = jstop;
+      __syncthreads();
+    }
 
     // leaf back to memory; Wl := explicit W of the leaf (1 on the diagonal
     // row, 0 above it, the reflector below it; zero past nbl and past the slab)
