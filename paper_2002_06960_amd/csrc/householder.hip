@@ -44,7 +44,12 @@
 // exchange area is cleared before the launch.  Leaf passes alternate between
 // two buffers: a workgroup can only be one pass ahead of the slowest reader.
 // Every workgroup sums the exchanged values in the same order, so all of them
-// take the same decisions and derive bit-identical reflectors.
+// take the same decisions and derive bit-identical reflectors.  Readers first
+// wait on a per-exchange arrival counter (one word, bumped by each workgroup
+// after it has published) and only then read the data: polling the data words
+// themselves would flood the memory system with atomic loads while the slower
+// workgroups are still computing.  The counter is a hint only; the round
+// numbers in the data words still decide.
 #include <algorithm>
 #include <type_traits>
 
@@ -69,7 +74,8 @@ constexpr double kGramCap = 16.0;  // tolerated cancellation of a Gram-derived s
 constexpr unsigned kPQSpinLimit = 1u << 22;
 
 // exchange area (64-bit words; a double is a pair of words)
-constexpr i64 kXGram = 0;                                     // [2][kPQMaxWG][kPQGramE][2] leaf Gram partials
+constexpr i64 kXCnt = 0;                                      // arrival counters, one per 128-byte line
+constexpr i64 kXGram = kXCnt + 3 * 16;                        // [2][kPQMaxWG][kPQGramE][2] leaf Gram partials
 constexpr i64 kXTop = kXGram + 2 * kPQMaxWG * kPQGramE * 2;   // [2][kPQNB][kPQNB][2] leaf top block
 constexpr i64 kXTot = kXTop + 2 * kPQNB * kPQNB * 2;          // [kPQTrail][2] reduced trailing sums
 constexpr i64 kXPart = kXTot + kPQTrail * 2;                  // [P][kPQTrail][2] trailing partials
@@ -152,6 +158,23 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
     return false;
   };
 
+  // publish-then-wait on counter ctr (every workgroup adds 1 per exchange;
+  // n-th exchange of that kind waits for n * P arrivals)
+  unsigned narr[3] = {0, 0, 0};
+  auto arrive_and_wait = [&](int ctr) {
+    __syncthreads();
+    ++narr[ctr];
+    if (threadIdx.x == 0) {
+      unsigned* cw = reinterpret_cast<unsigned*>(xch + kXCnt + 16 * ctr);
+      __hip_atomic_fetch_add(cw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned target = narr[ctr] * (unsigned)P;
+      unsigned spins = 0;
+      while (__hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+        if (give_up(spins)) break;
+    }
+    __syncthreads();
+  };
+
   for (int c0 = 0; c0 < k; c0 += kPQNB) {
     const int nbl = min(kPQNB, k - c0);
     // opaque zero and thread index: every address below is recomputed per leaf
@@ -226,6 +249,7 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
           xput(xg + ((i64)wg * kPQGramE + b * (b + 1) / 2 + a) * 2, sv, tag);
         }
       }
+      arrive_and_wait(0);
       // gather: threads 0..135 sum one Gram entry over the workgroups in
       // order; threads 256..511 read the top block
       if (tid < kPQGramE) {
@@ -461,6 +485,7 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
         if (gram) xput(mine + (i64)(a + lc * kPQNB) * 2, accg[qq], tag1);
       }
     }
+    arrive_and_wait(1);
     // round 1: workgroup wg sums entries [e0, e1) over all workgroups, in order
     {
       const int e0 = (int)((i64)E * wg / P), e1 = (int)((i64)E * (wg + 1) / P);
@@ -488,6 +513,7 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
         xput(xtot + (i64)e * 2, sv, tag2);
       }
     }
+    arrive_and_wait(2);
     // round 2: every workgroup reads all totals
     {
       constexpr int NE = kPQTrail / kPQThreads;
