@@ -63,11 +63,11 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kPQThreads = 512;  // 8 waves (two per SIMD keep the FP64 matrix cores busy)
 constexpr int kPQWaves = kPQThreads / WAVE;
 constexpr int kPQLeafThreads = 256;  // waves 0-3 hold the leaf rows
-constexpr int kPQRpt = 2;            // leaf rows per thread
+constexpr int kPQRpt = 1;            // leaf rows per thread
 constexpr int kPQMaxRows = kPQLeafThreads * kPQRpt;
 constexpr int kPQNB = 16;                  // leaf width
 constexpr int kPQLdW = kPQMaxRows + 1;     // padded leading dimension of the leaf in LDS
-constexpr int kPQMaxWG = 64;
+constexpr int kPQMaxWG = 128;
 constexpr int kPQTrail = kPQNB * kPQNB + kPQNB * (kPanelMaxCols - kPQNB);  // Gram + W^T C entries
 constexpr int kPQGramE = kPQNB * (kPQNB + 1) / 2;  // packed upper triangle of a leaf Gram matrix
 constexpr double kGramCap = 16.0;  // tolerated cancellation of a Gram-derived squared norm
@@ -81,7 +81,7 @@ constexpr i64 kXTot = kXTop + 2 * kPQNB * kPQNB * 2;          // [kPQTrail][2] r
 constexpr i64 kXPart = kXTot + kPQTrail * 2;                  // [P][kPQTrail][2] trailing partials
 
 static int panel_grid(i64 m) {
-  i64 P = std::max<i64>(cdiv(m, kPQMaxRows), std::min<i64>(32, cdiv(m, 128)));
+  i64 P = std::max<i64>(cdiv(m, kPQMaxRows), std::min<i64>(32, cdiv(m, 64)));
   return (int)std::max<i64>(P, 1);
 }
 
@@ -125,10 +125,13 @@ struct ForColumns<kPQNB> {
   __device__ __forceinline__ static void run(F&) {}
 };
 
-__global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, double* __restrict__ A,
-                                                              i64 lda, double* __restrict__ tau,
-                                                              u64* __restrict__ xch,
-                                                              int* __restrict__ err) {
+// kMinWaves = minimum waves per SIMD: 2 lets a workgroup use 256 registers
+// per lane and so take a CU for itself; 4 (128 registers) lets it share a CU
+// with one GEMM workgroup, so that it is placed while GEMMs keep the chip busy
+template <int kMinWaves>
+__global__ __launch_bounds__(kPQThreads, kMinWaves) void panel_qr_kernel(
+    int m, int k, double* __restrict__ A, i64 lda, double* __restrict__ tau, u64* __restrict__ xch,
+    int* __restrict__ err) {
   const int P = gridDim.x, wg = blockIdx.x;
   const int r0 = (int)((i64)m * wg / P), r1 = (int)((i64)m * (wg + 1) / P), R = r1 - r0;
 
@@ -221,14 +224,16 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
       }
       __syncthreads();
       // Gram matrix of the rows below the top block on the matrix cores: wave
-      // w takes local rows 64 w .. 64 w + 63, four per step; lane l supplies
-      // X(r, l % 16) as both operands, D(a, b) = sum_r X(r, a) X(r, b)
+      // w takes local rows kRowsPerWave w .. kRowsPerWave (w + 1) - 1, four
+      // per step; lane l supplies X(r, l % 16) as both operands,
+      // D(a, b) = sum_r X(r, a) X(r, b)
       {
         dbl4 g = {0.0, 0.0, 0.0, 0.0};
         const int c = lane & 15;
+        constexpr int kRowsPerWave = kPQMaxRows / kPQWaves;
 #pragma unroll
-        for (int s4 = 0; s4 < 16; ++s4) {
-          const int r = 64 * wave + 4 * s4 + (lane >> 4);
+        for (int s4 = 0; s4 < kRowsPerWave / 4; ++s4) {
+          const int r = kRowsPerWave * wave + 4 * s4 + (lane >> 4);
           const double x = Wl[c * kPQLdW + r];
           g = __builtin_amdgcn_mfma_f64_16x16x4f64((r < R && r0 + r >= c0 + nbl) ? x : 0.0,
                                                    (r < R && r0 + r >= c0 + nbl) ? x : 0.0, g, 0, 0, 0);
@@ -633,7 +638,8 @@ __global__ __launch_bounds__(kPQThreads) void panel_qr_kernel(int m, int k, doub
   }
 }
 
-int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau, const PanelWork& w) {
+int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau, const PanelWork& w,
+             bool shared_cus) {
   if (k <= 0 || m <= 0) return RANDUTV_OK;
   if (k > kPanelMaxCols || m < k) return RANDUTV_ERR_TOO_LARGE;
   const int P = panel_grid(m);
@@ -641,7 +647,10 @@ int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau, cons
   LaunchTimer* tm = launch_timer();
   RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(w.xch), 2 * panel_words(P)));
   if (tm) tm->begin(st, K_PANEL);
-  panel_qr_kernel<<<P, kPQThreads, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err);
+  if (shared_cus)
+    panel_qr_kernel<4><<<P, kPQThreads, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err);
+  else
+    panel_qr_kernel<2><<<P, kPQThreads, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err);
   RUTV_TRY(hipGetLastError());
   if (tm) tm->end(st, K_PANEL, 2.0 * m * k * k - 2.0 * k * k * k / 3.0);
   return RANDUTV_OK;

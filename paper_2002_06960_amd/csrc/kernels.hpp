@@ -39,8 +39,11 @@ struct PanelWork {
 };
 // size (64-bit words) of PanelWork::xch for panels of up to m rows
 i64 panel_work_elems(i64 m);
+// shared_cus: the kernel variant that fits beside a GEMM workgroup on a CU
+// (for a panel that runs while other streams keep the chip busy); otherwise
+// each workgroup takes a CU for itself
 int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau,
-             const PanelWork& w);
+             const PanelWork& w, bool shared_cus = false);
 // W (m x k, ld ldw) := explicit unit lower trapezoidal part of the factored
 // panel P; R (k x k, ld ldr, may be null) := its upper triangle; if zero_panel
 // the panel is overwritten with zeros afterwards.

@@ -447,7 +447,9 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     // ---- stream P: panel QR of the column block, its reflectors, then their
     // block factor while stream T forms W^T C
     RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_COLS, i), 0));
-    RUTV_CHECK(panel_qr(sP, mi, bi, Bm, ldt, w.tauU, xP.pw));
+    // (the trailing update on stream T and the U/V updates keep every CU busy
+    // meanwhile: this panel takes the variant that shares CUs with them)
+    RUTV_CHECK(panel_qr(sP, mi, bi, Bm, ldt, w.tauU, xP.pw, true));
     RUTV_CHECK(extract_reflectors(sP, mi, bi, Bm, ldt, w.WU[buf], mi, w.Rall + i * b * b, b, true));
     RUTV_TRY(hipEventRecord(ev(EV_WU, i), sP));
     RUTV_CHECK(t_factor(sP, xP, mi, bi, w.WU[buf], w.tauU, w.ZU[buf]));
