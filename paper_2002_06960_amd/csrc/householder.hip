@@ -435,9 +435,12 @@ __global__ __launch_bounds__(kPQThreads, kMinWaves) void panel_qr_kernel(
     {
       // wave w forms X(:, 16q:16q+16) = W_slab^T C_slab(:, 16q:16q+16) for the
       // chunks q = w, w + W, ... (W waves; ncr <= 240: at most 15 chunks); the
-      // last wave also forms the Gram W^T W.  Rows are taken 4 per MFMA; the
-      // C values of the next kPF row groups are in flight.
-      constexpr int kPF = 8, NQ = (kPanelMaxCols / 16 - 1 + kPQWaves - 1) / kPQWaves;
+      // last wave also forms the Gram W^T W.  Rows are taken 4 per MFMA, in
+      // groups of kPF row steps whose C values are loaded one group ahead into
+      // alternating register sets (a single set would have to wait for every
+      // load in flight before it is refilled).
+      constexpr int kPF = kMinWaves == 2 ? 8 : 4, NQ = (kPanelMaxCols / 16 - 1 + kPQWaves - 1) / kPQWaves;
+      static_assert(NQ == 2, "chunk dispatch below assumes two chunks per wave");
       const bool gram = wave == kPQWaves - 1;
       // live chunks of this wave (uniform); loads are unconditional at clamped
       // addresses: rows past the slab meet zero rows of Wl, columns past ncr
@@ -452,29 +455,47 @@ __global__ __launch_bounds__(kPQThreads, kMinWaves) void panel_qr_kernel(
         acc[qd] = dbl4{0.0, 0.0, 0.0, 0.0};
       }
       const int nst = (R + 3) / 4;
-      double pf[NQ][kPF];
+      // one sweep over the slab for NQC live chunks (and the Gram when G)
+      auto sweep = [&](auto nqc, auto gc) {
+        constexpr int NQC = decltype(nqc)::value;
+        constexpr bool G = decltype(gc)::value;
+        constexpr int NS = NQC > 0 ? NQC : 1;
+        double ca[NS][kPF], cb[NS][kPF];
+        auto fetch = [&](double (&dst)[NS][kPF], int st0) {
 #pragma unroll
-      for (int i = 0; i < kPF; ++i)
+          for (int i = 0; i < kPF; ++i)
 #pragma unroll
-        for (int qd = 0; qd < NQ; ++qd) pf[qd][i] = Ac[qd][min(4 * i + lr, R - 1)];
-      for (int st0 = 0; st0 < nst; st0 += kPF) {
-        double cv[NQ][kPF];
+            for (int qd = 0; qd < NQC; ++qd) dst[qd][i] = Ac[qd][min(4 * (st0 + i) + lr, R - 1)];
+        };
+        auto work = [&](double (&src)[NS][kPF], int st0) {
 #pragma unroll
-        for (int i = 0; i < kPF; ++i)
+          for (int i = 0; i < kPF; ++i) {
+            const int r = 4 * (st0 + i) + lr;
+            const double wa = r < kPQMaxRows ? Wl[lc * kPQLdW + min(r, kPQMaxRows - 1)] : 0.0;  // W(r, a = lc)
 #pragma unroll
-          for (int qd = 0; qd < NQ; ++qd) {
-            cv[qd][i] = pf[qd][i];
-            pf[qd][i] = Ac[qd][min(4 * (st0 + kPF + i) + lr, R - 1)];
+            for (int qd = 0; qd < NQC; ++qd)
+              acc[qd] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, src[qd][i], acc[qd], 0, 0, 0);
+            if (G) accg = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, wa, accg, 0, 0, 0);
           }
-#pragma unroll
-        for (int i = 0; i < kPF; ++i) {
-          const int r = 4 * (st0 + i) + lr;
-          const double wa = r < kPQMaxRows ? Wl[lc * kPQLdW + min(r, kPQMaxRows - 1)] : 0.0;  // W(r, a = lc)
-#pragma unroll
-          for (int qd = 0; qd < NQ; ++qd)
-            if (qd < nq) acc[qd] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, cv[qd][i], acc[qd], 0, 0, 0);
-          if (gram) accg = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, wa, accg, 0, 0, 0);
+        };
+        fetch(ca, 0);
+        for (int st0 = 0; st0 < nst; st0 += 2 * kPF) {
+          fetch(cb, st0 + kPF);
+          work(ca, st0);
+          fetch(ca, st0 + 2 * kPF);
+          work(cb, st0 + kPF);
         }
+      };
+      using I0 = std::integral_constant<int, 0>;
+      using I1 = std::integral_constant<int, 1>;
+      using I2 = std::integral_constant<int, 2>;
+      if (gram) {
+        if (nq == 2) sweep(I2{}, std::true_type{});
+        else if (nq == 1) sweep(I1{}, std::true_type{});
+        else sweep(I0{}, std::true_type{});
+      } else {
+        if (nq == 2) sweep(I2{}, std::false_type{});
+        else if (nq == 1) sweep(I1{}, std::false_type{});
       }
       // D(4qq + lr, lc): X[a = 4qq + lr][t], Gram[a][c = lc]
       u64* const mine = xpart + (i64)wg * kPQTrail * 2;
@@ -587,51 +608,59 @@ __global__ __launch_bounds__(kPQThreads, kMinWaves) void panel_qr_kernel(
     // update on the matrix cores: 16-row x 16-column blocks of C -= W Y with
     // Y = S (16 x ncr); the MFMA forms the block transposed, so a lane holds
     // 4 columns of one row: C[rb + lc][t0 + 4q + lr] (16 rows per column per
-    // store).  Blocks are dealt to the waves; the next blocks' C values are
-    // fetched while the current one is computed.
+    // store).  Blocks are dealt to the waves and taken kG at a time; the C
+    // values of the next group are loaded into the other register set before
+    // the current group is computed and stored (the wait for a load then
+    // never includes the stores issued after it).
     {
       const int nrb = (R + 15) / 16;
       const int nblocks = nrb * nchunk;
-      constexpr int kRing = 4;
-      double ring[kRing][4];
+      constexpr int kG = kMinWaves == 2 ? 4 : 2;
       // unconditional loads at clamped addresses (the stores are guarded)
-      auto fetch = [&](int bi, double (&dst)[4]) {
-        const int bc = min(bi, nblocks - 1);
-        const int rb = 16 * (bc % nrb), t0 = 16 * (bc / nrb);
-        const int r = min(rb + lc, R - 1);
+      auto fetch = [&](int g, double (&dst)[kG][4]) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int tc = min(t0 + 4 * q + lr, ncr - 1);
-          dst[q] = Ab[(i64)(r0 + r) + (i64)(c0 + nbl + tc) * lda];
-        }
-      };
+        for (int u = 0; u < kG; ++u) {
+          const int bc = min(wave + kPQWaves * (kG * g + u), nblocks - 1);
+          const int rb = 16 * (bc % nrb), t0 = 16 * (bc / nrb);
+          const int r = min(rb + lc, R - 1);
 #pragma unroll
-      for (int u = 0; u < kRing; ++u) fetch(wave + kPQWaves * u, ring[u]);
-      for (int b0 = wave; b0 < nblocks; b0 += kPQWaves * kRing) {
-#pragma unroll
-        for (int u = 0; u < kRing; ++u) {
-          const int bidx = b0 + kPQWaves * u;
-          double cc[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) cc[q] = ring[u][q];
-          fetch(bidx + kPQWaves * kRing, ring[u]);
-          if (bidx < nblocks) {
-            const int rb = 16 * (bidx % nrb), t0 = 16 * (bidx / nrb);
-            dbl4 d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int kk = 0; kk < kPQNB; kk += 4) {
-              const double yv = S[(kk + lr) * kPanelMaxCols + t0 + lc];  // Y^T(t0 + lc, kk + lr)
-              const double wv = Wl[(kk + lr) * kPQLdW + rb + lc];        // W^T(kk + lr, rb + lc)
-              d = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, wv, d, 0, 0, 0);
-            }
-            const int r = rb + lc;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int tc = t0 + 4 * q + lr;
-              if (r < R && tc < ncr) Ab[(i64)(r0 + r) + (i64)(c0 + nbl + tc) * lda] = cc[q] - d[q];
-            }
+          for (int q = 0; q < 4; ++q) {
+            const int tc = min(t0 + 4 * q + lr, ncr - 1);
+            dst[u][q] = Ab[(i64)(r0 + r) + (i64)(c0 + nbl + tc) * lda];
           }
         }
+      };
+      auto finish = [&](int g, double (&src)[kG][4]) {
+#pragma unroll
+        for (int u = 0; u < kG; ++u) {
+          const int bidx = wave + kPQWaves * (kG * g + u);
+          const int bc = min(bidx, nblocks - 1);
+          const int rb = 16 * (bc % nrb), t0 = 16 * (bc / nrb);
+          dbl4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int kk = 0; kk < kPQNB; kk += 4) {
+            const double yv = S[(kk + lr) * kPanelMaxCols + t0 + lc];  // Y^T(t0 + lc, kk + lr)
+            const double wv = Wl[(kk + lr) * kPQLdW + rb + lc];        // W^T(kk + lr, rb + lc)
+            d = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, wv, d, 0, 0, 0);
+          }
+          const int r = rb + lc;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int tc = t0 + 4 * q + lr;
+            if (bidx < nblocks && r < R && tc < ncr)
+              Ab[(i64)(r0 + r) + (i64)(c0 + nbl + tc) * lda] = src[u][q] - d[q];
+          }
+        }
+      };
+      const int nbw = (nblocks - wave + kPQWaves - 1) / kPQWaves;  // this wave's blocks
+      const int ngroups = nbw > 0 ? (nbw + kG - 1) / kG : 0;
+      double ga[kG][4], gb[kG][4];
+      if (ngroups > 0) fetch(0, ga);
+      for (int g = 0; g < ngroups; g += 2) {
+        fetch(g + 1, gb);
+        finish(g, ga);
+        fetch(g + 2, ga);
+        finish(g + 1, gb);
       }
     }
     __syncthreads();
