@@ -716,103 +716,89 @@ int extract_reflectors(hipStream_t st, i64 m, i64 k, double* P, i64 ldp, double*
 // ---------------------------------------------------------------------------
 // Compact-WY factor from the Gram matrix G = W^T W (dlarft, forward,
 // column-wise): T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).
-// Blocked in 32 x 32 blocks: diagonal blocks by the column recurrence, then
-// T(I, K) = -(sum_{L=I}^{K-1} T(I, L) G(L, K)) T(K, K), block rows in parallel.
+// Row i of T depends only on row i itself: T(i, j) = -tau_j sum_{l=i}^{j-1}
+// T(i, l) G(l, j).  One workgroup owns a block of 32 rows and keeps them in
+// LDS; it walks the 32-column blocks K of its rows: the part of the sum over
+// the earlier column blocks is one product P = T(rows, o:oK) G(o:oK, K) on
+// the matrix cores, the rest is the recurrence inside block K, one row per
+// lane.  The workgroups do not depend on each other.
 // ---------------------------------------------------------------------------
 constexpr int kTB = 32;
+constexpr int kTLd = kPanelMaxCols + 1;  // padded row length of the block row in LDS
 
-__global__ __launch_bounds__(256) void larft_diag_kernel(int k, const double* __restrict__ G, i64 ldg,
-                                                         const double* __restrict__ tau,
+__global__ __launch_bounds__(256) void larft_rows_kernel(int k, const double* __restrict__ G,
+                                                         i64 ldg, const double* __restrict__ tau,
                                                          double* __restrict__ Tf, i64 ldt) {
-  const int I = blockIdx.x, tid = threadIdx.x;
-  const int o = I * kTB, nb = min(kTB, k - o);
-  __shared__ double Gd[kTB * kTB];
-  __shared__ double Td[kTB * kTB];
-  __shared__ double ta[kTB];
-  for (int e = tid; e < kTB * kTB; e += 256) {
-    const int r = e % kTB, c = e / kTB;
-    Gd[e] = (r < nb && c < nb) ? G[(o + r) + (i64)(o + c) * ldg] : 0.0;
-    Td[e] = 0.0;
-  }
-  if (tid < kTB) ta[tid] = tid < nb ? tau[o + tid] : 0.0;
-  __syncthreads();
-  for (int c = 0; c < nb; ++c) {
-    if (tid < c) {
-      double s = 0.0;
-      for (int l = tid; l < c; ++l) s += Td[tid + l * kTB] * Gd[l + c * kTB];
-      Td[tid + c * kTB] = -ta[c] * s;
-    }
-    if (tid == c) Td[c + c * kTB] = ta[c];
-    __syncthreads();
-  }
-  // diagonal block and the zero blocks below it
-  for (int e = tid; e < (k - o) * nb; e += 256) {
-    const int r = e % (k - o), c = e / (k - o);
-    Tf[(o + r) + (i64)(o + c) * ldt] = r < nb ? Td[r + c * kTB] : 0.0;
-  }
-}
-
-__global__ __launch_bounds__(256) void larft_offdiag_kernel(int k, const double* __restrict__ G,
-                                                            i64 ldg, double* __restrict__ Tf,
-                                                            i64 ldt) {
-  const int I = blockIdx.x, tid = threadIdx.x;
-  const int nblk = (k + kTB - 1) / kTB;
-  const int oi = I * kTB, ni = min(kTB, k - oi);
-  __shared__ double Ta[kTB * (kTB + 1)];
-  __shared__ double Gb[kTB * (kTB + 1)];
-  __shared__ double S[kTB * (kTB + 1)];
-  const int r = tid % kTB, c0 = (tid / kTB) * 4;  // each thread: row r, columns c0..c0+3
-  for (int K = I + 1; K < nblk; ++K) {
+  const int I = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int o = I * kTB, nblk = (k + kTB - 1) / kTB;
+  __shared__ double Tr[kTB * kTLd];        // T(o + i, c) at i * kTLd + c
+  __shared__ double Pb[kTB * (kTB + 1)];   // P(i, jj) at i * (kTB + 1) + jj
+  __shared__ double Gd[kTB * (kTB + 1)];   // G(oK + l, oK + jj) at l * (kTB + 1) + jj
+  __shared__ double tk[kTB];
+  for (int e = tid; e < kTB * kTLd; e += 256) Tr[e] = 0.0;
+  for (int K = I; K < nblk; ++K) {
     const int ok = K * kTB, nk = min(kTB, k - ok);
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int Lb = I; Lb < K; ++Lb) {
-      const int ol = Lb * kTB, nl = min(kTB, k - ol);
-      __syncthreads();
-      for (int e = tid; e < kTB * kTB; e += 256) {
-        const int rr = e % kTB, cc = e / kTB;
-        Ta[rr + cc * (kTB + 1)] = (rr < ni && cc < nl) ? Tf[(oi + rr) + (i64)(ol + cc) * ldt] : 0.0;
-        Gb[rr + cc * (kTB + 1)] = (rr < nl && cc < nk) ? G[(ol + rr) + (i64)(ok + cc) * ldg] : 0.0;
+    // P = T(o:o+32, o:ok) G(o:ok, ok:ok+32): wave w forms the 16 x 16 tile
+    // (rows 16 (w & 1), columns 16 (w >> 1)); lane l supplies
+    // T(row l % 16, col 4 s + l / 16) and G(row 4 s + l / 16, col l % 16)
+    {
+      const int ti = 16 * (wave & 1), tj = 16 * (wave >> 1);
+      dbl4 d = {0.0, 0.0, 0.0, 0.0};
+      const int gc = min(ok + tj + (lane & 15), k - 1);
+      for (int s4 = 0; s4 < (ok - o) / 4; ++s4) {
+        const int l = o + 4 * s4 + (lane >> 4);
+        const double a = Tr[(ti + (lane & 15)) * kTLd + l];
+        const double g = G[l + (i64)gc * ldg];
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, g, d, 0, 0, 0);
       }
-      __syncthreads();
-      for (int l = 0; l < kTB; ++l) {
-        const double a = Ta[r + l * (kTB + 1)];
+      // register r of lane l holds D(4 r + l / 16, l % 16)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] += a * Gb[l + (c0 + q) * (kTB + 1)];
-      }
+      for (int r = 0; r < 4; ++r) Pb[(ti + 4 * r + (lane >> 4)) * (kTB + 1) + tj + (lane & 15)] = d[r];
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) S[r + (c0 + q) * (kTB + 1)] = s[q];
     for (int e = tid; e < kTB * kTB; e += 256) {
-      const int rr = e % kTB, cc = e / kTB;
-      Gb[rr + cc * (kTB + 1)] = (rr < nk && cc < nk) ? Tf[(ok + rr) + (i64)(ok + cc) * ldt] : 0.0;
+      const int l = e % kTB, jj = e / kTB;
+      Gd[l * (kTB + 1) + jj] = (l < nk && jj < nk) ? G[(ok + l) + (i64)(ok + jj) * ldg] : 0.0;
+    }
+    if (tid < kTB) tk[tid] = tid < nk ? tau[ok + tid] : 0.0;
+    __syncthreads();
+    // recurrence inside block K, lane i = row o + i (rows past k stay zero)
+    if (wave == 0 && lane < kTB && o + lane < k) {
+      const int i = lane;
+      double row[kTB];
+#pragma unroll
+      for (int jj = 0; jj < kTB; ++jj) row[jj] = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < kTB; ++jj) {
+        if (jj < nk) {
+          double sv = Pb[i * (kTB + 1) + jj];
+#pragma unroll
+          for (int l = 0; l < jj; ++l) sv += row[l] * Gd[l * (kTB + 1) + jj];
+          const int j = ok + jj;
+          row[jj] = j < o + i ? 0.0 : (j == o + i ? tk[jj] : -tk[jj] * sv);
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < kTB; ++jj)
+        if (jj < nk) Tr[i * kTLd + ok + jj] = row[jj];
     }
     __syncthreads();
-    double o4[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int l = 0; l < kTB; ++l) {
-      const double a = S[r + l * (kTB + 1)];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) o4[q] += a * Gb[l + (c0 + q) * (kTB + 1)];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (r < ni && c0 + q < nk) Tf[(oi + r) + (i64)(ok + c0 + q) * ldt] = -o4[q];
-    __syncthreads();
+  }
+  // the block row to memory (zeros left of the diagonal block)
+  for (int e = tid; e < kTB * k; e += 256) {
+    const int i = e % kTB, c = e / kTB;
+    if (o + i < k) Tf[(o + i) + (i64)c * ldt] = Tr[i * kTLd + c];
   }
 }
 
 int larft_from_gram(hipStream_t st, i64 k, const double* G, i64 ldg, const double* tau, double* Tf,
                     i64 ldt) {
   if (k <= 0) return RANDUTV_OK;
+  if (k > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
   const int nblk = (int)cdiv(k, kTB);
   LaunchTimer* tm = launch_timer();
   if (tm) tm->begin(st, K_LARFT);
-  larft_diag_kernel<<<nblk, 256, 0, st>>>((int)k, G, ldg, tau, Tf, ldt);
+  larft_rows_kernel<<<nblk, 256, 0, st>>>((int)k, G, ldg, tau, Tf, ldt);
   RUTV_TRY(hipGetLastError());
-  if (nblk > 1) {
-    larft_offdiag_kernel<<<nblk - 1, 256, 0, st>>>((int)k, G, ldg, Tf, ldt);
-    RUTV_TRY(hipGetLastError());
-  }
   if (tm) tm->end(st, K_LARFT, (double)k * k * k / 3.0);
   return RANDUTV_OK;
 }
