@@ -133,8 +133,10 @@ __device__ __forceinline__ void tile_of(int L, int tilesM, int tilesN, int split
   nt = t2 / gm;
 }
 
+// MINB: workgroups that must fit on a CU at once (the launch bound counts
+// waves per SIMD, four SIMDs per CU)
 template <class CT, bool TA, bool TB, int BM, int BN, int BK, int MINB = 2, int WGM = 2, int WGN = 2>
-__global__ __launch_bounds__(64 * WGM * WGN, MINB) void dgemm_mfma_kernel(
+__global__ __launch_bounds__(64 * WGM * WGN, MINB * WGM * WGN / 4) void dgemm_mfma_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, i64 lda,
     const double* __restrict__ B, i64 ldb, double beta, double* __restrict__ C, i64 ldc,
     int kchunk, double* __restrict__ part, int tilesM, int tilesN, int splits) {
@@ -215,28 +217,31 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void dgemm_mfma_kernel(
   // register r of a lane holds D(MT::row(r, lane), lane % 16); with the swapped
   // operands D is the transposed C block, so the lane holds
   // C[m0+wm0+16i+(lane&15)][n0+wn0+16j+MT::row(r, lane)], r = 0..3.  The C
-  // values of one row block are loaded together (clamped addresses), then
-  // stored.
+  // values of row block i + 1 are loaded (clamped addresses) before the
+  // results of row block i are stored, into alternating register sets, so
+  // that the wait for a load never includes the stores issued after it.
   const int cm = lane & 15;
+  const bool read_c = !part && beta != 0.0;
+  double cva[NJ][4], cvb[NJ][4];
+  auto load_c = [&](int i, double (&cv)[NJ][4]) {
+    const int gmc = min(m0 + wm0 + 16 * i + cm, M - 1);
 #pragma unroll
-  for (int i = 0; i < MI; ++i) {
-    const int gm = m0 + wm0 + 16 * i + cm;
-    const int gmc = min(gm, M - 1);
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      double cv[4];
-      if (!part && beta != 0.0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int gnc = min(n0 + wn0 + 16 * j + MT::row(r, lane), N - 1);
-          cv[r] = C[gmc + (i64)gnc * ldc];
-        }
+      for (int r = 0; r < 4; ++r) {
+        const int gnc = min(n0 + wn0 + 16 * j + MT::row(r, lane), N - 1);
+        cv[j][r] = C[gmc + (i64)gnc * ldc];
       }
+  };
+  auto store_c = [&](int i, const double (&cv)[NJ][4]) {
+    const int gm = m0 + wm0 + 16 * i + cm;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gn = n0 + wn0 + 16 * j + MT::row(r, lane);
         double v = alpha * static_cast<double>(acc[i][j][r]);
-        if (!part && beta != 0.0) v += beta * cv[r];
+        if (read_c) v += beta * cv[j][r];
         if (gm < M && gn < N) {
           if (part)
             part[(i64)kz * M * N + gm + (i64)gn * M] = v;
@@ -244,6 +249,16 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void dgemm_mfma_kernel(
             C[gm + (i64)gn * ldc] = v;
         }
       }
+  };
+  if (read_c) load_c(0, cva);
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+    if (i % 2 == 0) {
+      if (read_c && i + 1 < MI) load_c(i + 1, cvb);
+      store_c(i, cva);
+    } else {
+      if (read_c && i + 1 < MI) load_c(i + 1, cva);
+      store_c(i, cvb);
     }
   }
 }
