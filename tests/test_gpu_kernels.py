@@ -83,6 +83,38 @@ def test_geqrf_degenerate_columns():
     np.testing.assert_allclose(_reflectors(to_host(F))[1], Ro, atol=0)
 
 
+def _restart_case(kind):
+    rng = np.random.default_rng(7)
+    m, k = 2000, 256
+    if kind == "rank100":
+        return rng.standard_normal((m, 100)) @ rng.standard_normal((100, k))
+    if kind == "near_parallel":
+        A = rng.standard_normal((m, k))
+        for j in range(1, k, 2):
+            A[:, j] = A[:, j - 1] + 1e-6 * rng.standard_normal(m)
+        return A
+    return rng.standard_normal((m, k)) * np.logspace(0, -12, k)  # graded column scales
+
+
+@pytest.mark.parametrize("kind,rtol_r", [("rank100", 1e-12), ("near_parallel", 1e-8), ("graded", 1e-12)])
+def test_geqrf_cancelling_columns(kind, rtol_r):
+    """Panels whose columns cancel against the earlier reflectors: the leaf
+    passes must stop at such columns and restart from a fresh Gram matrix.
+    The factorization must stay exact (A = QR, Q orthogonal); R is compared
+    with the oracle where it is well determined by the data."""
+    A = _restart_case(kind)
+    m, k = A.shape
+    F, tau = pkg.randutv_geqrf(to_dev(A))
+    Wg, Rg = _reflectors(to_host(F))
+    taug = to_host(tau)
+    T = ro.block_reflector_T(Wg, taug)
+    Q = np.eye(m)[:, :k] - Wg @ (T @ Wg[:k, :].T)
+    assert np.linalg.norm(A - Q @ Rg) <= 1e-13 * np.linalg.norm(A)
+    assert np.abs(Q.T @ Q - np.eye(k)).max() <= 1e-13
+    Wo, tauo, Ro = ro.householder_qr(A)
+    np.testing.assert_allclose(Rg, Ro, rtol=0, atol=rtol_r * np.abs(Ro).max())
+
+
 @pytest.mark.parametrize("m,k", [(500, 64), (12000, 256), (4000, 100), (40, 33)])
 def test_larft_matches_oracle(m, k):
     rng = np.random.default_rng(k)
