@@ -17,15 +17,23 @@
 // u_j = w_j / d_j (Gram-Schmidt completion over e_1, e_2, ... where d_j = 0),
 // and (u_j, v_j) negated when the largest-magnitude entry of v_j (lowest
 // index on ties) is negative.
+//
+// Inside a workgroup (4 waves) the 16 disjoint pairs of a step are handled by
+// 16-lane groups, each lane holding 16 rows; the dot products are summed
+// across the group by DPP butterflies, which leave the bit-identical total in
+// all 16 lanes (every lane of a group takes the same rotation decision).
 #include <algorithm>
 
 #include "kernels.hpp"
 
 namespace rutv {
 
-constexpr int kJThreads = 1024;
+constexpr int kJThreads = 256;
 constexpr int kJWaves = kJThreads / WAVE;
-constexpr int kJRows = kJacobiMaxN / WAVE;  // rows per lane
+constexpr int kJRows = kJacobiMaxN / WAVE;  // rows per lane (a wave per column)
+constexpr int kJG = 16;                     // lanes per column pair
+constexpr int kJRowsG = kJacobiMaxN / kJG;  // rows per lane (a 16-lane group per pair)
+constexpr int kJU = 8;                      // block loads in flight per thread
 constexpr int kJBW = 16;                    // columns per block
 constexpr int kJMaxWG = kJacobiMaxN / (2 * kJBW);
 
@@ -72,6 +80,61 @@ __device__ __forceinline__ int jacobi_pair(int k, int lane, double tol, double* 
 #pragma unroll
   for (int e = 0; e < kJRows; ++e) {
     const int r = lane + WAVE * e;
+    if (r < k) {
+      wx[r] = cs * xj[e] - sn * xq[e];
+      wy[r] = sn * xj[e] + cs * xq[e];
+      const double yj = vx[r], yq = vy[r];
+      vx[r] = cs * yj - sn * yq;
+      vy[r] = sn * yj + cs * yq;
+    }
+  }
+  return 1;
+}
+
+// one butterfly step across lanes l and l ^ mask inside a 16-lane row (DPP):
+// both lanes form the same sum, so the row total is bit-identical in all 16
+template <int kCtrl>
+__device__ __forceinline__ double dpp_swap(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), kCtrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_swap<0xB1>(v);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+  v += dpp_swap<0x4E>(v);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+  v += dpp_swap<0x141>(v);  // row_half_mirror: lane ^ 7 within 8
+  v += dpp_swap<0x140>(v);  // row_mirror: lane ^ 15 within 16
+  return v;
+}
+
+// the same rotation for a pair handled by a 16-lane group: lane l16 holds
+// rows l16 + 16 e (e = 0..15); returns 1 if rotated
+__device__ __forceinline__ int jacobi_pair16(int k, int l16, double tol, double* wx, double* wy,
+                                             double* vx, double* vy) {
+  double xj[kJRowsG], xq[kJRowsG];
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int e = 0; e < kJRowsG; ++e) {
+    const int r = l16 + kJG * e;
+    xj[e] = r < k ? wx[r] : 0.0;
+    xq[e] = r < k ? wy[r] : 0.0;
+    al += xj[e] * xj[e];
+    be += xq[e] * xq[e];
+    ga += xj[e] * xq[e];
+  }
+  al = row16_sum(al);
+  be = row16_sum(be);
+  ga = row16_sum(ga);
+  if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) return 0;
+  const double zeta = (be - al) / (2.0 * ga);
+  double tn = 1.0;
+  if (zeta != 0.0) tn = (zeta > 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + tn * tn);
+  const double sn = cs * tn;
+#pragma unroll
+  for (int e = 0; e < kJRowsG; ++e) {
+    const int r = l16 + kJG * e;
     if (r < k) {
       wx[r] = cs * xj[e] - sn * xq[e];
       wy[r] = sn * xj[e] + cs * xq[e];
@@ -137,41 +200,66 @@ __global__ __launch_bounds__(kJThreads) void jacobi_block_kernel(int kfull, int 
       const int pa = rr_player(wg, round, nblk), pb = rr_player(nblk - 1 - wg, round, nblk);
       const int ba = min(pa, pb), bb = max(pa, pb);
       const int blk[2] = {ba, bb};
-      // load both blocks (column c of block x is global column x*16 + c)
-      for (int e = tid; e < 2 * kJBW * k; e += kJThreads) {
-        const int r = e % k, cc = e / k, x = cc / kJBW, c = cc % kJBW;
-        const int gc = blk[x] * kJBW + c;
-        Wl[x][c][r] = gc < k ? W[r + (i64)gc * k] : 0.0;
-        Vl[x][c][r] = gc < k ? V[r + (i64)gc * k] : 0.0;
+      // load both blocks (column c of block x is global column x*16 + c),
+      // kJU elements per thread in flight at a time
+      {
+        const int ne = 2 * kJBW * k;
+        for (int e0 = tid; e0 < ne; e0 += kJThreads * kJU) {
+          double wv[kJU], vv[kJU];
+#pragma unroll
+          for (int u = 0; u < kJU; ++u) {
+            const int e = min(e0 + kJThreads * u, ne - 1);
+            const int r = e % k, cc = e / k, x = cc / kJBW, c = cc % kJBW;
+            const int gc = min(blk[x] * kJBW + c, k - 1);
+            wv[u] = W[r + (i64)gc * k];
+            vv[u] = V[r + (i64)gc * k];
+          }
+#pragma unroll
+          for (int u = 0; u < kJU; ++u) {
+            const int e = e0 + kJThreads * u;
+            if (e < ne) {
+              const int r = e % k, cc = e / k, x = cc / kJBW, c = cc % kJBW;
+              const bool in = blk[x] * kJBW + c < k;
+              Wl[x][c][r] = in ? wv[u] : 0.0;
+              Vl[x][c][r] = in ? vv[u] : 0.0;
+            }
+          }
+        }
       }
       __syncthreads();
       int myrot = 0;
+      // 16 disjoint pairs at a time, one per 16-lane group (pg = 0..15)
+      const int pg = wave * (WAVE / kJG) + (lane >> 4), l16 = lane & (kJG - 1);
       if (round == 0) {
         // pairs inside each block: 15 inner rounds of 8 pairs per block
-        const int x = wave / 8, p = wave % 8;
+        const int x = pg / 8, p = pg % 8;
         for (int ir = 0; ir < kJBW - 1; ++ir) {
           const int c1 = rr_player(p, ir, kJBW), c2 = rr_player(kJBW - 1 - p, ir, kJBW);
           const int cj = min(c1, c2), cq = max(c1, c2);
           if (blk[x] * kJBW + cq < k)
-            myrot += jacobi_pair(k, lane, tol, Wl[x][cj], Wl[x][cq], Vl[x][cj], Vl[x][cq]);
+            myrot += jacobi_pair16(k, l16, tol, Wl[x][cj], Wl[x][cq], Vl[x][cj], Vl[x][cq]);
           __syncthreads();
         }
       }
       // pairs across the two blocks: 16 inner steps of 16 disjoint pairs
       for (int t = 0; t < kJBW; ++t) {
-        const int i = wave, j2 = (wave + t) % kJBW;
+        const int i = pg, j2 = (pg + t) % kJBW;
         if (ba != bb && ba * kJBW + i < k && bb * kJBW + j2 < k)
-          myrot += jacobi_pair(k, lane, tol, Wl[0][i], Wl[1][j2], Vl[0][i], Vl[1][j2]);
+          myrot += jacobi_pair16(k, l16, tol, Wl[0][i], Wl[1][j2], Vl[0][i], Vl[1][j2]);
         __syncthreads();
       }
-      if (lane == 0 && myrot) atomicAdd(&lrot, myrot);
+      if (l16 == 0 && myrot) atomicAdd(&lrot, myrot);  // one count per pair group
       // blocks back to global memory
-      for (int e = tid; e < 2 * kJBW * k; e += kJThreads) {
-        const int r = e % k, cc = e / k, x = cc / kJBW, c = cc % kJBW;
-        const int gc = blk[x] * kJBW + c;
-        if (gc < k) {
-          W[r + (i64)gc * k] = Wl[x][c][r];
-          V[r + (i64)gc * k] = Vl[x][c][r];
+      {
+        const int ne = 2 * kJBW * k;
+#pragma unroll 4
+        for (int e = tid; e < ne; e += kJThreads) {
+          const int r = e % k, cc = e / k, x = cc / kJBW, c = cc % kJBW;
+          const int gc = blk[x] * kJBW + c;
+          if (gc < k) {
+            W[r + (i64)gc * k] = Wl[x][c][r];
+            V[r + (i64)gc * k] = Vl[x][c][r];
+          }
         }
       }
       const bool last = (round == nblk - 2) || nblk == 2;
