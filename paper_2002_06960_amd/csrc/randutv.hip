@@ -209,6 +209,12 @@ struct StreamWS {
   PanelWork pw;
 };
 
+// the column-block panel takes the CU-sharing kernel variant while the
+// trailing update beside it is at least this wide (below that the GEMMs leave
+// CUs free and the faster exclusive variant gets them)
+#ifndef RUTV_SHARED_PANEL_MIN_COLS
+#define RUTV_SHARED_PANEL_MIN_COLS 3000
+#endif
 #ifndef RUTV_SVD_GROUP
 #define RUTV_SVD_GROUP 8
 #endif
@@ -448,8 +454,9 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     // block factor while stream T forms W^T C
     RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_COLS, i), 0));
     // (the trailing update on stream T and the U/V updates keep every CU busy
-    // meanwhile: this panel takes the variant that shares CUs with them)
-    RUTV_CHECK(panel_qr(sP, mi, bi, Bm, ldt, w.tauU, xP.pw, true));
+    // meanwhile: while that update is wide, this panel takes the variant that
+    // shares CUs with them)
+    RUTV_CHECK(panel_qr(sP, mi, bi, Bm, ldt, w.tauU, xP.pw, ni - bi >= RUTV_SHARED_PANEL_MIN_COLS));
     RUTV_CHECK(extract_reflectors(sP, mi, bi, Bm, ldt, w.WU[buf], mi, w.Rall + i * b * b, b, true));
     RUTV_TRY(hipEventRecord(ev(EV_WU, i), sP));
     RUTV_CHECK(t_factor(sP, xP, mi, bi, w.WU[buf], w.tauU, w.ZU[buf]));
