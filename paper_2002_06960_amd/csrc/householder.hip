@@ -60,8 +60,6 @@ namespace rutv {
 typedef unsigned long long u64;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int kPQThreads = 512;  // 8 waves (two per SIMD keep the FP64 matrix cores busy)
-constexpr int kPQWaves = kPQThreads / WAVE;
 constexpr int kPQLeafThreads = 256;  // waves 0-3 hold the leaf rows
 constexpr int kPQRpt = 1;            // leaf rows per thread
 constexpr int kPQMaxRows = kPQLeafThreads * kPQRpt;
@@ -125,13 +123,16 @@ struct ForColumns<kPQNB> {
   __device__ __forceinline__ static void run(F&) {}
 };
 
-// kMinWaves = minimum waves per SIMD: 2 lets a workgroup use 256 registers
-// per lane and so take a CU for itself; 4 (128 registers) lets it share a CU
-// with one GEMM workgroup, so that it is placed while GEMMs keep the chip busy
-template <int kMinWaves>
-__global__ __launch_bounds__(kPQThreads, kMinWaves) void panel_qr_kernel(
+// kPQThreads = 512: 8 waves, two per SIMD (256 registers each), a CU to itself;
+// 256: 4 waves, one per SIMD, which fit beside one GEMM workgroup (2 waves of
+// 128 registers per SIMD), so the workgroup is placed while GEMMs keep the chip
+// busy.  Waves 0-3 hold the leaf rows in both; the matrix-core work is shared
+// by all waves.
+template <int kPQThreads>
+__global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
     int m, int k, double* __restrict__ A, i64 lda, double* __restrict__ tau, u64* __restrict__ xch,
     int* __restrict__ err) {
+  constexpr int kPQWaves = kPQThreads / WAVE;
   const int P = gridDim.x, wg = blockIdx.x;
   const int r0 = (int)((i64)m * wg / P), r1 = (int)((i64)m * (wg + 1) / P), R = r1 - r0;
 
@@ -283,8 +284,12 @@ __global__ __launch_bounds__(kPQThreads, kMinWaves) void panel_qr_kernel(
         const int a = tid - b * (b + 1) / 2;
         Gs[a * kPQNB + b] = sv;
         Gs[b * kPQNB + a] = sv;
-      } else if (tid >= kPQThreads - kPQNB * kPQNB) {
-        const int e = tid - (kPQThreads - kPQNB * kPQNB), t = e >> 4;
+      }
+      // the top block: with 512 threads by threads 256..511 (beside the Gram
+      // readers), with 256 by every thread after its Gram entry
+      for (int e = tid - (kPQThreads - kPQNB * kPQNB); e < kPQNB * kPQNB; e += kPQThreads) {
+        if (e < 0) continue;
+        const int t = e >> 4;
         double v = 0.0;
         if (t < nbl) {
           unsigned spins = 0;
@@ -439,8 +444,8 @@ __global__ __launch_bounds__(kPQThreads, kMinWaves) void panel_qr_kernel(
       // groups of kPF row steps whose C values are loaded one group ahead into
       // alternating register sets (a single set would have to wait for every
       // load in flight before it is refilled).
-      constexpr int kPF = kMinWaves == 2 ? 8 : 4, NQ = (kPanelMaxCols / 16 - 1 + kPQWaves - 1) / kPQWaves;
-      static_assert(NQ == 2, "chunk dispatch below assumes two chunks per wave");
+      constexpr int kPF = 8, NQ = (kPanelMaxCols / 16 - 1 + kPQWaves - 1) / kPQWaves;
+      static_assert(NQ <= 4, "chunk dispatch below handles up to four chunks per wave");
       const bool gram = wave == kPQWaves - 1;
       // live chunks of this wave (uniform); loads are unconditional at clamped
       // addresses: rows past the slab meet zero rows of Wl, columns past ncr
@@ -489,14 +494,17 @@ __global__ __launch_bounds__(kPQThreads, kMinWaves) void panel_qr_kernel(
       using I0 = std::integral_constant<int, 0>;
       using I1 = std::integral_constant<int, 1>;
       using I2 = std::integral_constant<int, 2>;
-      if (gram) {
-        if (nq == 2) sweep(I2{}, std::true_type{});
-        else if (nq == 1) sweep(I1{}, std::true_type{});
-        else sweep(I0{}, std::true_type{});
-      } else {
-        if (nq == 2) sweep(I2{}, std::false_type{});
-        else if (nq == 1) sweep(I1{}, std::false_type{});
-      }
+      using I3 = std::integral_constant<int, NQ >= 3 ? 3 : NQ>;
+      using I4 = std::integral_constant<int, NQ >= 4 ? 4 : NQ>;
+      auto dispatch = [&](auto gc) {
+        if (nq >= 4) sweep(I4{}, gc);
+        else if (nq == 3) sweep(I3{}, gc);
+        else if (nq == 2) sweep(I2{}, gc);
+        else if (nq == 1) sweep(I1{}, gc);
+        else if (decltype(gc)::value) sweep(I0{}, gc);
+      };
+      if (gram) dispatch(std::true_type{});
+      else dispatch(std::false_type{});
       // D(4qq + lr, lc): X[a = 4qq + lr][t], Gram[a][c = lc]
       u64* const mine = xpart + (i64)wg * kPQTrail * 2;
 #pragma unroll
@@ -615,7 +623,7 @@ __global__ __launch_bounds__(kPQThreads, kMinWaves) void panel_qr_kernel(
     {
       const int nrb = (R + 15) / 16;
       const int nblocks = nrb * nchunk;
-      constexpr int kG = kMinWaves == 2 ? 4 : 2;
+      constexpr int kG = 4;
       // unconditional loads at clamped addresses (the stores are guarded)
       auto fetch = [&](int g, double (&dst)[kG][4]) {
 #pragma unroll
@@ -677,9 +685,9 @@ int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau, cons
   RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(w.xch), 2 * panel_words(P)));
   if (tm) tm->begin(st, K_PANEL);
   if (shared_cus)
-    panel_qr_kernel<4><<<P, kPQThreads, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err);
+    panel_qr_kernel<256><<<P, 256, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err);
   else
-    panel_qr_kernel<2><<<P, kPQThreads, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err);
+    panel_qr_kernel<512><<<P, 512, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err);
   RUTV_TRY(hipGetLastError());
   if (tm) tm->end(st, K_PANEL, 2.0 * m * k * k - 2.0 * k * k * k / 3.0);
   return RANDUTV_OK;
