@@ -46,8 +46,10 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="block steps of the same problem timed for the CPU oracle baseline (0: skip)")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--mixed-modes", default="fp32,bf16x3,bf16",
+                    help="reduced-precision sketch modes timed beside the FP64 run")
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the run with the sketch and power iteration on the FP32 matrix cores")
+                    help="skip the runs with the sketch and power iteration in reduced precision")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the residual/orthogonality check of the timed output (profiler runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -143,38 +145,47 @@ def main():
         orth_v = (V.T @ V - eye_n).abs().max().item()
         del eye_n
 
-    # the same factorization with the sketch and power-iteration products on the
-    # FP32 matrix cores (every transform of T, U, V still FP64)
+    # the same factorization with the sketch and power-iteration products in
+    # reduced precision (every transform of T, U, V still FP64): FP32 matrix
+    # cores, three BF16 products of split operands, one BF16 product
     mixed = None
     if not args.no_mixed:
+        mixed = {}
         U2 = pkg.colmajor_empty(m, m, dev)
         T2 = pkg.colmajor_empty(m, n, dev)
         V2 = pkg.colmajor_empty(n, n, dev)
-        pkg.randutv_factor(A, b, q, 0, U=U2, T=T2, V=V2, sketch_bits=32)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            pkg.randutv_factor(A, b, q, 0, U=U2, T=T2, V=V2, sketch_bits=32)
-        torch.cuda.synchronize()
-        ms_mixed = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
-        print(f"# fp32-sketch: {ms_mixed:.2f} ms/step", file=sys.stderr, flush=True)
-        mixed = {"sketch": "fp32 matrix cores (FP64 storage); all transforms FP64",
-                 "ms_per_step": round(ms_mixed, 3),
-                 "value": round(F / (ms_mixed * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
-                 "frac_of_fp64_peak": round(F / (ms_mixed * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
-        if not args.no_check:
-            nA = torch.linalg.norm(A)
-            mixed["residual"] = (torch.linalg.norm(A - U2 @ T2 @ V2.T) / nA).item()
-            ranks = {}
-            for k in (64, 256, 1024):
-                Ak = pkg.randutv_truncate(U, T, V, k)
-                Ak2 = pkg.randutv_truncate(U2, T2, V2, k)
-                ranks[str(k)] = {"fp64_trunc_err": (torch.linalg.norm(A - Ak) / nA).item(),
-                                 "mixed_trunc_err": (torch.linalg.norm(A - Ak2) / nA).item(),
-                                 "mixed_vs_fp64": (torch.linalg.norm(Ak2 - Ak) / nA).item()}
-                del Ak, Ak2
-            mixed["rank_k"] = ranks
-            mixed["T_vs_fp64"] = (torch.linalg.norm(T2 - T) / nA).item()
+        modes = {"fp32": (32, "fp32 matrix cores (FP64 storage); all transforms FP64"),
+                 "bf16x3": (48, "bf16 matrix cores, operands split x = hi + lo, hi*hi + hi*lo + lo*hi, "
+                                "fp32 accumulation (FP64 storage); all transforms FP64"),
+                 "bf16": (16, "bf16 matrix cores, operands rounded to bf16, fp32 accumulation "
+                              "(FP64 storage); all transforms FP64")}
+        for name in args.mixed_modes.split(","):
+            bits, what = modes[name]
+            pkg.randutv_factor(A, b, q, 0, U=U2, T=T2, V=V2, sketch_bits=bits)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                pkg.randutv_factor(A, b, q, 0, U=U2, T=T2, V=V2, sketch_bits=bits)
+            torch.cuda.synchronize()
+            ms_mixed = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
+            print(f"# {name}-sketch: {ms_mixed:.2f} ms/step", file=sys.stderr, flush=True)
+            rec = {"sketch": what, "ms_per_step": round(ms_mixed, 3),
+                   "value": round(F / (ms_mixed * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+                   "frac_of_fp64_peak": round(F / (ms_mixed * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
+            if not args.no_check:
+                nA = torch.linalg.norm(A)
+                rec["residual"] = (torch.linalg.norm(A - U2 @ T2 @ V2.T) / nA).item()
+                ranks = {}
+                for k in (64, 256, 1024):
+                    Ak = pkg.randutv_truncate(U, T, V, k)
+                    Ak2 = pkg.randutv_truncate(U2, T2, V2, k)
+                    ranks[str(k)] = {"fp64_trunc_err": (torch.linalg.norm(A - Ak) / nA).item(),
+                                     "mixed_trunc_err": (torch.linalg.norm(A - Ak2) / nA).item(),
+                                     "mixed_vs_fp64": (torch.linalg.norm(Ak2 - Ak) / nA).item()}
+                    del Ak, Ak2
+                rec["rank_k"] = ranks
+                rec["T_vs_fp64"] = (torch.linalg.norm(T2 - T) / nA).item()
+            mixed[name] = rec
         del U2, T2, V2
 
     roofline = None

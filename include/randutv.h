@@ -67,15 +67,23 @@ int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda,
  *   sketch_bits : RANDUTV_SKETCH_FP64 (64): FP64 matrix cores, as randutv_factor;
  *                 RANDUTV_SKETCH_FP32 (32): operands rounded to FP32 and
  *                 multiplied on the FP32 matrix cores (FP64 storage, FP32
- *                 accumulation within a K split).
+ *                 accumulation within a K split);
+ *                 RANDUTV_SKETCH_BF16 (16): operands rounded to BF16 (via
+ *                 FP32), BF16 matrix cores, FP32 accumulation;
+ *                 RANDUTV_SKETCH_BF16X3 (48): each operand split into two
+ *                 BF16 parts x = hi + lo and the product formed as
+ *                 hi*hi + hi*lo + lo*hi on the BF16 matrix cores (about 16
+ *                 significant bits per operand), FP32 accumulation.
  * Every transform applied to T, U and V (Householder vectors, block factors,
  * updates, the b x b SVDs) stays FP64, so A = U T V^T holds to FP64 accuracy
- * either way; with FP32 the subspaces (hence T, U, V themselves) differ from
- * the FP64 ones by the perturbation of the sketch.  Errors as randutv_factor,
- * plus -11 for an unknown sketch_bits.
+ * in every mode; with a reduced-precision sketch the subspaces (hence T, U, V
+ * themselves) differ from the FP64 ones by the perturbation of the sketch.
+ * Errors as randutv_factor, plus -11 for an unknown sketch_bits.
  */
 #define RANDUTV_SKETCH_FP64 64
 #define RANDUTV_SKETCH_FP32 32
+#define RANDUTV_SKETCH_BF16 16
+#define RANDUTV_SKETCH_BF16X3 48
 int randutv_factor_ex(int64_t m, int64_t n, const double* A, int64_t lda,
                       int64_t b, int32_t q, uint64_t seed,
                       double* U, double* T, double* V, int32_t sketch_bits);
@@ -118,6 +126,17 @@ int randutv_dgemm(char transa, char transb, int64_t M, int64_t N, int64_t K,
 int randutv_gemm_f32(char transa, char transb, int64_t M, int64_t N, int64_t K,
                      double alpha, const double* A, int64_t lda, const double* B,
                      int64_t ldb, double beta, double* C, int64_t ldc);
+
+/* Same operation and arguments as randutv_dgemm, FP64 operands and result,
+ * on the BF16 matrix cores with FP32 accumulation (the products used by
+ * randutv_factor_ex with RANDUTV_SKETCH_BF16 / RANDUTV_SKETCH_BF16X3):
+ * terms = 1 rounds each operand to BF16 (via FP32); terms = 3 splits each
+ * operand x (rounded to FP32) into BF16 parts hi + lo and forms
+ * hi*hi + hi*lo + lo*hi.  Errors as randutv_dgemm, plus -14 for terms other
+ * than 1 or 3. */
+int randutv_gemm_bf16(char transa, char transb, int64_t M, int64_t N, int64_t K,
+                      double alpha, const double* A, int64_t lda, const double* B,
+                      int64_t ldb, double beta, double* C, int64_t ldc, int32_t terms);
 
 /* Householder QR of the m x k matrix A (m >= k, k <= 256) in place, LAPACK
  * dgeqr2 conventions (Figure 2's "unpivoted QR"): on return R is in the upper

@@ -18,6 +18,8 @@
 // Skinny products (an n x b output with K in the thousands) split K; each
 // split writes alpha * partial to a buffer and a second kernel sums the splits
 // in a fixed order (deterministic).
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace rutv {
@@ -279,6 +281,203 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(int M, int N, int S,
   }
 }
 
+// ---- BF16 products --------------------------------------------------------
+// The sketch and power-iteration products only choose a subspace, so they may
+// run on the BF16 matrix cores.  An FP64 operand value x is rounded to FP32
+// (f) and then to BF16 (hi); with kTerms = 3 the remainder f - hi, exact in
+// FP32, is rounded to BF16 as well (lo), and the product is formed as
+// hi*hi + hi*lo + lo*hi (about 16 significant bits per operand instead of 8;
+// lo*lo is below that).  Each 16x16x32 MFMA accumulates in FP32.
+//
+// Tiles are 128 x 128 with 32-deep slices, eight waves in a 2 x 4 grid as in
+// the FP64 kernel.  LDS holds each slice k-contiguous ([edge][k], 40 values a
+// row): a lane's 8 consecutive k of one row or column are one 16-byte read,
+// and the 80-byte row pitch spreads the 16 rows of a lane group over
+// distinct banks.  The conversion to BF16 happens once per element, when the
+// slice is written to LDS.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBfBK = 32;         // k per slice: one 16x16x32 MFMA step
+constexpr int kBfLd = kBfBK + 8;  // LDS row pitch (BF16 values)
+constexpr int kBfThreads = 512;
+
+// Global loads of one 128 x 32 slice of an operand, 8 values per thread.
+// edge-major (contiguous along the tile edge): edge tid % 128, k 8*(tid/128)+r;
+// k-major (contiguous along k): k tid % 32, edge tid/32 + 16 r.  Addresses are
+// clamped into the matrix, out-of-range values masked to zero at the LDS
+// store (as in SliceLoader).
+template <bool KMAJOR>
+struct BfLoader {
+  const double* base;
+  i64 ld;
+  int tile0, edge_total;
+  __device__ __forceinline__ int e_of(int tid, int r) const {
+    return KMAJOR ? tid / kBfBK + 16 * r : tid % 128;
+  }
+  __device__ __forceinline__ int k_of(int tid, int r) const {
+    return KMAJOR ? tid % kBfBK : 8 * (tid / 128) + r;
+  }
+  __device__ __forceinline__ void load(double (&v)[8], bool (&keep)[8], int tid, int k0,
+                                       int kend) const {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tile0 + e_of(tid, r), k = k0 + k_of(tid, r);
+      const i64 ec = min(e, edge_total - 1), kc = min(k, kend - 1);
+      v[r] = KMAJOR ? base[kc + ec * ld] : base[ec + kc * ld];
+      keep[r] = e < edge_total && k < kend;
+    }
+  }
+};
+
+struct BfPair {
+  __bf16 hi, lo;
+};
+__device__ __forceinline__ BfPair bf_split(double x) {
+  const float f = static_cast<float>(x);
+  const __bf16 hi = static_cast<__bf16>(f);
+  return {hi, static_cast<__bf16>(f - static_cast<float>(hi))};
+}
+
+template <bool TA, bool TB, int kTerms>
+__global__ __launch_bounds__(kBfThreads, 4) void gemm_bf16_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, i64 lda,
+    const double* __restrict__ B, i64 ldb, double beta, double* __restrict__ C, i64 ldc,
+    int kchunk, double* __restrict__ part, int tilesM, int tilesN, int splits) {
+  static_assert(kTerms == 1 || kTerms == 3, "one or three BF16 products");
+  constexpr int kPlanes = kTerms == 3 ? 2 : 1;  // hi (and lo) parts
+  constexpr int BM = 128, BN = 128, WM = BM / kWavesM, WN = BN / kWavesN;
+  constexpr int MI = WM / 16, NJ = WN / 16;
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][kPlanes][BM * kBfLd];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][kPlanes][BN * kBfLd];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave % kWavesM) * WM, wn0 = (wave / kWavesM) * WN;
+  int mt, nt, kz;
+  tile_of(blockIdx.x, tilesM, tilesN, splits, mt, nt, kz);
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int kbeg = kz * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+
+  const BfLoader<TA> la{A, lda, m0, M};
+  const BfLoader<!TB> lb{B, ldb, n0, N};
+  double ra[8], rb[8];
+  bool ka[8], kb[8];
+  auto sstore = [&](int buf) {
+    if (TA) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const BfPair p = bf_split(keep_or_zero(ra[r], ka[r]));
+        const int o = la.e_of(tid, r) * kBfLd + la.k_of(tid, r);
+        As[buf][0][o] = p.hi;
+        if (kTerms == 3) As[buf][kPlanes - 1][o] = p.lo;
+      }
+    } else {
+      bf16x8 h, l;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const BfPair p = bf_split(keep_or_zero(ra[r], ka[r]));
+        h[r] = p.hi;
+        l[r] = p.lo;
+      }
+      const int o = la.e_of(tid, 0) * kBfLd + la.k_of(tid, 0);
+      *reinterpret_cast<bf16x8*>(&As[buf][0][o]) = h;
+      if (kTerms == 3) *reinterpret_cast<bf16x8*>(&As[buf][kPlanes - 1][o]) = l;
+    }
+    if (!TB) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const BfPair p = bf_split(keep_or_zero(rb[r], kb[r]));
+        const int o = lb.e_of(tid, r) * kBfLd + lb.k_of(tid, r);
+        Bs[buf][0][o] = p.hi;
+        if (kTerms == 3) Bs[buf][kPlanes - 1][o] = p.lo;
+      }
+    } else {
+      bf16x8 h, l;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const BfPair p = bf_split(keep_or_zero(rb[r], kb[r]));
+        h[r] = p.hi;
+        l[r] = p.lo;
+      }
+      const int o = lb.e_of(tid, 0) * kBfLd + lb.k_of(tid, 0);
+      *reinterpret_cast<bf16x8*>(&Bs[buf][0][o]) = h;
+      if (kTerms == 3) *reinterpret_cast<bf16x8*>(&Bs[buf][kPlanes - 1][o]) = l;
+    }
+  };
+
+  flt4 acc[MI][NJ];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[i][j] = flt4{0, 0, 0, 0};
+
+  const int nk = kend > kbeg ? (kend - kbeg + kBfBK - 1) / kBfBK : 0;
+  if (nk > 0) {
+    la.load(ra, ka, tid, kbeg, kend);
+    lb.load(rb, kb, tid, kbeg, kend);
+    sstore(0);
+    __syncthreads();
+    // lane group g = lane / 16 supplies k = 8g .. 8g+7 of both operands (the
+    // same k for the same operand slot, so the pairing is consistent)
+    const int kq = 8 * (lane >> 4), cl = lane & 15;
+    for (int t = 0; t < nk; ++t) {
+      const int cur = t & 1;
+      if (t + 1 < nk) {
+        la.load(ra, ka, tid, kbeg + (t + 1) * kBfBK, kend);
+        lb.load(rb, kb, tid, kbeg + (t + 1) * kBfBK, kend);
+      }
+      bf16x8 bh[NJ], bl[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int o = (wn0 + 16 * j + cl) * kBfLd + kq;
+        bh[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][0][o]);
+        if (kTerms == 3) bl[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][kPlanes - 1][o]);
+      }
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const int o = (wm0 + 16 * i + cl) * kBfLd + kq;
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&As[cur][0][o]);
+        bf16x8 al;
+        if (kTerms == 3) al = *reinterpret_cast<const bf16x8*>(&As[cur][kPlanes - 1][o]);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          // swapped operands, as in the FP64 kernel: D is the transposed C block
+          if (kTerms == 3) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], ah, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], al, acc[i][j], 0, 0, 0);
+          }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], ah, acc[i][j], 0, 0, 0);
+        }
+      }
+      if (t + 1 < nk) sstore(cur ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // register r of a lane holds C[m0+wm0+16i+(lane&15)][n0+wn0+16j+4(lane>>4)+r]
+  const int gm0 = m0 + wm0 + (lane & 15);
+  const bool read_c = !part && beta != 0.0;
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+    const int gm = gm0 + 16 * i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gn = n0 + wn0 + 16 * j + 4 * (lane >> 4) + r;
+        if (gn >= N) continue;
+        double v = alpha * static_cast<double>(acc[i][j][r]);
+        if (part) {
+          part[(i64)kz * M * N + gm + (i64)gn * M] = v;
+        } else {
+          if (read_c) v += beta * C[gm + (i64)gn * ldc];
+          C[gm + (i64)gn * ldc] = v;
+        }
+      }
+  }
+}
+
 namespace {
 
 struct Plan {
@@ -288,7 +487,10 @@ struct Plan {
 };
 
 constexpr int kBK = 16;
-constexpr i64 kResident = 512;  // workgroups resident at once (two per CU)
+#ifndef RUTV_SPLITK_RESIDENT
+#define RUTV_SPLITK_RESIDENT 768
+#endif
+constexpr i64 kResident = RUTV_SPLITK_RESIDENT;  // workgroups resident at once (two per CU)
 
 Plan choose_plan(i64 M, i64 N, i64 K) {
   const i64 t128 = cdiv(M, 128) * cdiv(N, 128);
@@ -333,6 +535,22 @@ void launch_tile(hipStream_t st, int bm, int M, int N, int K, double alpha, cons
         M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, tilesN, splits);
 }
 
+template <bool TA, bool TB>
+void launch_bf16(hipStream_t st, int terms, int M, int N, int K, double alpha, const double* A,
+                 i64 lda, const double* B, i64 ldb, double beta, double* C, i64 ldc, int kchunk,
+                 int splits, double* part) {
+  const int tilesM = (int)cdiv(M, 128), tilesN = (int)cdiv(N, 128);
+  const dim3 grid(tilesM * tilesN * splits);
+  if (terms == 3)
+    gemm_bf16_kernel<TA, TB, 3><<<grid, kBfThreads, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta,
+                                                              C, ldc, kchunk, part, tilesM, tilesN,
+                                                              splits);
+  else
+    gemm_bf16_kernel<TA, TB, 1><<<grid, kBfThreads, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta,
+                                                              C, ldc, kchunk, part, tilesM, tilesN,
+                                                              splits);
+}
+
 }  // namespace
 
 i64 dgemm_work_elems(i64 M, i64 N, i64 K) {
@@ -342,7 +560,7 @@ i64 dgemm_work_elems(i64 M, i64 N, i64 K) {
 
 int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha, const double* A,
           i64 lda, const double* B, i64 ldb, double beta, double* C, i64 ldc, double* work,
-          i64 work_elems, bool f32) {
+          i64 work_elems, int prec) {
   if (M <= 0 || N <= 0) return RANDUTV_OK;
   if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return RANDUTV_ERR_TOO_LARGE;
   Plan p = choose_plan(M, N, K);
@@ -358,6 +576,8 @@ int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha, c
       p.kchunk = (int)chunk;
     }
   }
+  const bool bf16 = prec == PREC_BF16 || prec == PREC_BF16X3;
+  if (bf16) p.bm = 128;  // one tile shape for the BF16 kernel
   if (cdiv(M, p.bm) * cdiv(N, p.bm) * p.splits > INT32_MAX) return RANDUTV_ERR_TOO_LARGE;
   double* part = p.splits > 1 ? work : nullptr;
   const int cls = ta ? (tb ? K_GEMM_TT : K_GEMM_TN) : (tb ? K_GEMM_NT : K_GEMM_NN);
@@ -378,10 +598,28 @@ int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha, c
       launch_tile<CT, true, true>(st, p.bm, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta,
                                   C, ldc, p.kchunk, p.splits, part);
   };
-  if (f32)
+  if (bf16) {
+    const int terms = prec == PREC_BF16X3 ? 3 : 1;
+    auto go16 = [&](auto ta_, auto tb_) {
+      launch_bf16<decltype(ta_)::value, decltype(tb_)::value>(
+          st, terms, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C, ldc, p.kchunk,
+          p.splits, part);
+    };
+    using F = std::false_type;
+    using T = std::true_type;
+    if (!ta && !tb)
+      go16(F{}, F{});
+    else if (ta && !tb)
+      go16(T{}, F{});
+    else if (!ta && tb)
+      go16(F{}, T{});
+    else
+      go16(T{}, T{});
+  } else if (prec == PREC_F32) {
     go(0.0f);
-  else
+  } else {
     go(0.0);
+  }
   RUTV_TRY(hipGetLastError());
   if (tm) tm->end(st, cls, 2.0 * (double)M * (double)N * (double)K);
   if (part) {

@@ -21,13 +21,19 @@ enum KernelClass : int {
 const char* kernel_class_name(int cls);
 
 // ---- GEMM (gemm.hip) ------------------------------------------------------
+// Arithmetic of a product (operands and result are FP64 in memory):
+//   PREC_F64    FP64 matrix cores;
+//   PREC_F32    operands rounded to FP32, FP32 matrix cores;
+//   PREC_BF16   operands rounded to BF16 (via FP32), BF16 matrix cores;
+//   PREC_BF16X3 each operand split into two BF16 parts x = hi + lo, product
+//               hi*hi + hi*lo + lo*hi on the BF16 matrix cores.
+// The reduced-precision forms accumulate in FP32 within a K split.
+enum GemmPrec : int { PREC_F64 = 0, PREC_F32, PREC_BF16, PREC_BF16X3 };
 // C = alpha op(A) op(B) + beta C.  'work' (work_elems doubles) holds split-K
-// partial tiles; the launcher picks fewer splits when it is too small.  f32:
-// FP64 operands and result, operands rounded to FP32 and multiplied on the
-// FP32 matrix cores (FP32 accumulation within a split).
+// partial tiles; the launcher picks fewer splits when it is too small.
 int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha,
           const double* A, i64 lda, const double* B, i64 ldb, double beta,
-          double* C, i64 ldc, double* work, i64 work_elems, bool f32 = false);
+          double* C, i64 ldc, double* work, i64 work_elems, int prec = PREC_F64);
 // split-K partial buffer size (doubles) that lets dgemm use its preferred plan
 i64 dgemm_work_elems(i64 M, i64 N, i64 K);
 

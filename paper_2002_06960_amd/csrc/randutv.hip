@@ -110,6 +110,13 @@ struct EventTimer final : LaunchTimer {
 // ---------------------------------------------------------------------------
 enum { ST_T = 0, ST_P, ST_UV, ST_S, NSTREAMS };
 constexpr int kEvRing = 4;  // events of a kind are reused every kEvRing steps
+// reflector buffers (W, Z of V^ and of U^) by step: stream T may run this many
+// steps ahead of the U/V updates that read them
+#ifndef RUTV_WY_BUFFERS
+#define RUTV_WY_BUFFERS 2
+#endif
+constexpr int kWyBuf = RUTV_WY_BUFFERS;
+static_assert(kWyBuf >= 2 && kWyBuf - 2 < kEvRing, "an awaited event must not be re-recorded first");
 enum { EV_V = 0, EV_COLS, EV_U, EV_UV, EV_PRE, EV_WV, EV_WU, EV_KINDS };
 
 struct Context {
@@ -223,8 +230,9 @@ constexpr int kSvdGroup = RUTV_SVD_GROUP;  // SVDs per batched launch
 struct FactorWS {
   StreamWS sw[NSTREAMS];
   double *G, *Y, *Zp, *tauV, *tauU, *X3;
-  // reflectors W and Z = W Tf^T (Tf their block factor), by step parity
-  double *WV[2], *ZV[2], *WU[2], *ZU[2];
+  // reflectors W and Z = W Tf^T (Tf their block factor), one set per step in
+  // turn (kWyBuf sets)
+  double *WV[kWyBuf], *ZV[kWyBuf], *WU[kWyBuf], *ZU[kWyBuf];
   double *Rall, *dall, *Usall, *Vsall, *jwork;
   int* status;  // [0] finite flag, [1] panel sync error, [2 + 3i ..] sweeps, converged, sync error
 };
@@ -282,7 +290,7 @@ static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wa
   w.tauV = c.take<double>(b);
   w.tauU = c.take<double>(b);
   w.X3 = c.take<double>(b * n);
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < kWyBuf; ++t) {
     w.WV[t] = c.take<double>(n * b);
     w.ZV[t] = c.take<double>(n * b);
     w.WU[t] = c.take<double>(m * b);
@@ -299,9 +307,9 @@ static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wa
 
 static int gemm(hipStream_t st, const StreamWS& x, bool ta, bool tb, i64 M, i64 N, i64 K,
                 double alpha, const double* A, i64 lda, const double* B, i64 ldb, double beta,
-                double* C, i64 ldc, bool f32 = false) {
+                double* C, i64 ldc, int prec = PREC_F64) {
   return dgemm(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, x.splitk, x.splitk_elems,
-               f32);
+               prec);
 }
 
 // Z (rows x k, ld rows) := W Tf^T, Tf the block factor of the reflectors W
@@ -334,10 +342,11 @@ static int right_mul_small(hipStream_t st, const StreamWS& x, i64 rows, i64 k, d
   return RANDUTV_OK;
 }
 
-// sketch32: the sketch and power-iteration products Y = (B^T B)^q B^T G on the
-// FP32 matrix cores (FP64 storage); every transform of T, U and V stays FP64
+// sketch_prec: arithmetic of the sketch and power-iteration products
+// Y = (B^T B)^q B^T G (a GemmPrec; FP64 storage either way); every transform
+// of T, U and V stays FP64
 static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uint64_t seed,
-                       double* U, double* T, double* V, bool sketch32) {
+                       double* U, double* T, double* V, int sketch_prec) {
   Context& cx = ctx();
   RUTV_CHECK(cx.init());
   hipStream_t sT = cx.streams[ST_T], sP = cx.streams[ST_P], sUV = cx.streams[ST_UV],
@@ -387,7 +396,7 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
   i64 g0 = 0;
   auto uv_and_svd = [&](i64 j, bool wait_pre) -> int {
     const i64 sj = j * b, bj = std::min(b, n - sj), mj = m - sj, nj = n - sj;
-    const int bf = (int)(j & 1);
+    const int bf = (int)(j % kWyBuf);
     if (wait_pre) RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_PRE, j + 1), 0));
     RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_V, j), 0));
     if (wantV) RUTV_CHECK(right_apply(sUV, xUV, n, nj, bj, V + sj * ldv, ldv, w.WV[bf], w.ZV[bf]));
@@ -421,15 +430,15 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
   i64 s = 0;
   for (i64 i = 0; s < n; ++i) {
     const i64 bi = std::min(b, n - s), e = s + bi, mi = m - s, ni = n - s;
-    const int buf = (int)(i & 1);
+    const int buf = (int)(i % kWyBuf);
     double* Bm = T + s + s * ldt;
     // ---- stream T: sketch, power iteration, QR(Y), compact WY of V^
-    if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_UV, i - 2), 0));  // WV[buf] free
+    if (i >= kWyBuf) RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_UV, i - kWyBuf), 0));  // WV[buf] free
     RUTV_CHECK(sketch(sT, seed, (uint64_t)i, mi, bi, w.G, mi));
-    RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.G, mi, 0.0, w.Y, ni, sketch32));
+    RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.G, mi, 0.0, w.Y, ni, sketch_prec));
     for (int it = 0; it < q; ++it) {
-      RUTV_CHECK(gemm(sT, xT, false, false, mi, bi, ni, 1.0, Bm, ldt, w.Y, ni, 0.0, w.Zp, mi, sketch32));
-      RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.Zp, mi, 0.0, w.Y, ni, sketch32));
+      RUTV_CHECK(gemm(sT, xT, false, false, mi, bi, ni, 1.0, Bm, ldt, w.Y, ni, 0.0, w.Zp, mi, sketch_prec));
+      RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.Zp, mi, 0.0, w.Y, ni, sketch_prec));
     }
     RUTV_TRY(hipEventRecord(ev(EV_PRE, i), sT));
     if (i >= 1) RUTV_CHECK(uv_and_svd(i - 1, true));
@@ -438,7 +447,7 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     RUTV_TRY(hipEventRecord(ev(EV_WV, i), sT));
     // stream P: block factor of V^ while stream T forms X = T W
     RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_WV, i), 0));
-    if (i >= 2) RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_UV, i - 2), 0));  // ZV/WU/ZU[buf] free
+    if (i >= kWyBuf) RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_UV, i - kWyBuf), 0));  // ZV/WU/ZU[buf] free
     RUTV_CHECK(t_factor(sP, xP, ni, bi, w.WV[buf], w.tauV, w.ZV[buf]));
     RUTV_TRY(hipEventRecord(ev(EV_V, i), sP));
     // right transform of all m rows, T <- T - (T W) Z^T: first the
@@ -531,11 +540,18 @@ int randutv_factor_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_
   if (T == A && lda != m) return -9;
   if (U && (U == T || U == V)) return -8;
   if (V && V == T) return -10;
-  if (sketch_bits != RANDUTV_SKETCH_FP64 && sketch_bits != RANDUTV_SKETCH_FP32) return -11;
+  int prec;
+  switch (sketch_bits) {
+    case RANDUTV_SKETCH_FP64: prec = PREC_F64; break;
+    case RANDUTV_SKETCH_FP32: prec = PREC_F32; break;
+    case RANDUTV_SKETCH_BF16: prec = PREC_BF16; break;
+    case RANDUTV_SKETCH_BF16X3: prec = PREC_BF16X3; break;
+    default: return -11;
+  }
   if (std::min(b, n) > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
-  return factor_impl(m, n, A, lda, b, q, seed, U, T, V, sketch_bits == RANDUTV_SKETCH_FP32);
+  return factor_impl(m, n, A, lda, b, q, seed, U, T, V, prec);
 }
 
 int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const double* T,
@@ -593,7 +609,7 @@ int randutv_sketch(uint64_t seed, uint64_t step, int64_t rows, int64_t cols, dou
 
 static int gemm_entry(char transa, char transb, int64_t M, int64_t N, int64_t K, double alpha,
                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
-                      double* C, int64_t ldc, bool f32) {
+                      double* C, int64_t ldc, int prec) {
   const bool ta = transa == 'T' || transa == 't', tb = transb == 'T' || transb == 't';
   if (!ta && transa != 'N' && transa != 'n') return -1;
   if (!tb && transb != 'N' && transb != 'n') return -2;
@@ -614,7 +630,7 @@ static int gemm_entry(char transa, char transb, int64_t M, int64_t N, int64_t K,
   RUTV_CHECK(cx.reserve(sizeof(double) * std::max<i64>(sk, 1)));
   set_launch_timer(nullptr);
   RUTV_CHECK(dgemm(cx.st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                   reinterpret_cast<double*>(cx.ws), sk, f32));
+                   reinterpret_cast<double*>(cx.ws), sk, prec));
   RUTV_TRY(hipStreamSynchronize(cx.st));
   return RANDUTV_OK;
 }
@@ -622,13 +638,21 @@ static int gemm_entry(char transa, char transb, int64_t M, int64_t N, int64_t K,
 int randutv_dgemm(char transa, char transb, int64_t M, int64_t N, int64_t K, double alpha,
                   const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                   double* C, int64_t ldc) {
-  return gemm_entry(transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, false);
+  return gemm_entry(transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, PREC_F64);
 }
 
 int randutv_gemm_f32(char transa, char transb, int64_t M, int64_t N, int64_t K, double alpha,
                      const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                      double* C, int64_t ldc) {
-  return gemm_entry(transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, true);
+  return gemm_entry(transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, PREC_F32);
+}
+
+int randutv_gemm_bf16(char transa, char transb, int64_t M, int64_t N, int64_t K, double alpha,
+                      const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                      double* C, int64_t ldc, int32_t terms) {
+  if (terms != 1 && terms != 3) return -14;
+  return gemm_entry(transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                    terms == 3 ? PREC_BF16X3 : PREC_BF16);
 }
 
 int randutv_geqrf(int64_t m, int64_t k, double* A, int64_t lda, double* tau) {

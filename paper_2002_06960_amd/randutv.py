@@ -29,6 +29,8 @@ SIGNATURES = {
     "randutv_sketch": (ctypes.c_int, [_U64, _U64, _I64, _I64, _P, _I64]),
     "randutv_dgemm": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
     "randutv_gemm_f32": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
+    "randutv_gemm_bf16": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64,
+                                         _I32]),
     "randutv_geqrf": (ctypes.c_int, [_I64, _I64, _P, _I64, _P]),
     "randutv_larft": (ctypes.c_int, [_I64, _I64, _P, _I64, _P, _P, _I64]),
     "randutv_gesvj": (ctypes.c_int, [_I64, _P, _I64, _P, _P, _P, ctypes.POINTER(_I32)]),
@@ -135,8 +137,10 @@ def randutv_factor(A, b: int, q: int, seed: int = 0, build_u: bool = True,
     """A = U T V^T.  Returns (U, T, V) column-major tensors (U/V None if not built).
 
     U, T, V may be given as preallocated column-major outputs.  sketch_bits
-    32 runs the sketch and power-iteration products on the FP32 matrix cores
-    (randutv_factor_ex); 64 is the all-FP64 randutv_factor."""
+    selects the arithmetic of the sketch and power-iteration products
+    (randutv_factor_ex): 32 the FP32 matrix cores, 16 the BF16 matrix cores,
+    48 three BF16 products of split operands; 64 is the all-FP64
+    randutv_factor."""
     lib = load()
     A, lda = as_colmajor(A)
     m, n = A.shape
@@ -180,9 +184,11 @@ def randutv_sketch(seed: int, step: int, rows: int, cols: int, device=None):
 
 
 def randutv_dgemm(transa: str, transb: str, alpha: float, A, B, beta: float = 0.0, C=None,
-                  f32: bool = False):
+                  f32: bool = False, bf16_terms: int = 0):
     """C = alpha op(A) op(B) + beta C (FP64 MFMA kernels; f32: FP64 operands and
-    result, FP32 matrix-core arithmetic).  Returns C."""
+    result, FP32 matrix-core arithmetic; bf16_terms 1 or 3: BF16 matrix-core
+    arithmetic with one product of rounded operands or three of split ones).
+    Returns C."""
     lib = load()
     A, lda = as_colmajor(A)
     B, ldb = as_colmajor(B)
@@ -197,9 +203,13 @@ def randutv_dgemm(transa: str, transb: str, alpha: float, A, B, beta: float = 0.
             raise ValueError("C must be column-major")
         ldc = max(1, C.stride(1) if N > 1 else M)
     _sync()
-    fn = "randutv_gemm_f32" if f32 else "randutv_dgemm"
-    _check(fn, getattr(lib, fn)(transa.encode(), transb.encode(), M, N, K, alpha, _ptr(A), lda,
-                                _ptr(B), ldb, beta, _ptr(C), ldc))
+    args = (transa.encode(), transb.encode(), M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta,
+            _ptr(C), ldc)
+    if bf16_terms:
+        _check("randutv_gemm_bf16", lib.randutv_gemm_bf16(*args, bf16_terms))
+    else:
+        fn = "randutv_gemm_f32" if f32 else "randutv_dgemm"
+        _check(fn, getattr(lib, fn)(*args))
     return C
 
 

@@ -67,11 +67,15 @@ def test_argument_validation_without_device_work():
     assert lib.randutv_sketch(0, 0, 4, 3, P, 2) == -6
     assert lib.randutv_larft(5, 6, P, 5, P, P, 6) == -2
     fx = lib.randutv_factor_ex
-    assert fx(5, 3, P, 5, 2, 0, 0, None, P, None, 16) == -11     # unknown sketch precision
+    assert fx(5, 3, P, 5, 2, 0, 0, None, P, None, 8) == -11      # unknown sketch precision
     assert fx(5, 3, P, 4, 2, 0, 0, None, P, None, 32) == -4
     g32 = lib.randutv_gemm_f32
     assert g32(b"N", b"Q", 1, 1, 1, 1.0, P, 1, P, 1, 0.0, P, 1) == -2
     assert g32(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 3) == -13
+    g16 = lib.randutv_gemm_bf16
+    assert g16(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 4, 2) == -14   # one or three terms
+    assert g16(b"X", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 4, 3) == -1
+    assert g16(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 3, 1) == -13
 
 
 def test_b_above_kernel_limit_is_reported():

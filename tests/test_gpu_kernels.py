@@ -203,3 +203,39 @@ def test_gemm_f32_matches_numpy(ta, tb, M, N, K):
         if K >= 256:
             C64 = to_host(pkg.randutv_dgemm(ta, tb, alpha, to_dev(A), to_dev(B), beta, to_dev(C0)))
             assert np.abs(to_host(C) - C64).max() > 1e3 * 2.0**-52 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("terms", [1, 3])
+@pytest.mark.parametrize("ta,tb", list(itertools.product("NT", "NT")))
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (37, 53, 29), (300, 257, 1000), (129, 65, 17),
+                                   (2500, 256, 3000), (700, 700, 256), (64, 64, 0)])
+def test_gemm_bf16_matches_numpy(terms, ta, tb, M, N, K):
+    """FP64 operands on the BF16 matrix cores.  An operand x goes to FP32 (f,
+    relative error 2^-24) and to BF16 (hi, 2^-8); with three terms the
+    remainder f - hi (exact in FP32) is rounded to BF16 too (lo), and
+    hi*hi + hi*lo + lo*hi misses r_a f_b + f_a r_b + lo_a lo_b with
+    |r| <= 2^-16 |f|.  BF16 x BF16 products are exact in FP32; each MFMA adds
+    into an FP32 accumulator, at most terms*K + 4 roundings of 2^-24."""
+    rng = np.random.default_rng(M * 11 + N * 5 + K + terms)
+    A = rng.standard_normal((K, M) if ta == "T" else (M, K))
+    B = rng.standard_normal((N, K) if tb == "T" else (K, N))
+    C0 = rng.standard_normal((M, N))
+    opA = A.T if ta == "T" else A
+    opB = B.T if tb == "T" else B
+    absAB = np.abs(opA) @ np.abs(opB)
+    rel = (2 * (2.0**-8 + 2.0**-24) + 2.0**-16) if terms == 1 else (3.1 * 2.0**-16 + 3 * 2.0**-24)
+    for alpha, beta in ((1.0, 0.0), (-1.0, 1.0), (0.5, -2.0)):
+        C = pkg.randutv_dgemm(ta, tb, alpha, to_dev(A), to_dev(B), beta, to_dev(C0), bf16_terms=terms)
+        ref = alpha * (opA @ opB) + beta * C0
+        bound = abs(alpha) * absAB * (rel + (terms * K + 4) * 2.0**-24) + abs(beta) * np.abs(C0) * 2.0**-50
+        err = np.abs(to_host(C) - ref)
+        assert np.all(err <= bound), (alpha, beta, (err / np.maximum(bound, 1e-300)).max())
+        if K >= 256 and alpha == 1.0:
+            rms = np.sqrt(np.mean(err**2)) / np.sqrt(np.mean(absAB**2))
+            # the operands really are rounded: far from FP64, and the split form
+            # is far closer than one BF16 product (about 2^-8 / sqrt(K) vs 2^-16)
+            assert rms > 1e-9
+            if terms == 1:
+                assert rms > 1e-5
+            else:
+                assert rms < 1e-5

@@ -224,3 +224,36 @@ def test_fp32_sketch_keeps_the_fp64_factorization(m, n, b, q, kind, close):
         assert dd <= 1e-4
         for k, ek, eko in errs:
             assert abs(ek - eko) <= 1e-4 * max(eko, 1e-12) + 1e-9, (k, ek, eko)
+
+
+@pytest.mark.parametrize("bits", [48, 16])
+@pytest.mark.parametrize("m,n,b,q,kind", [(512, 512, 64, 2, "exp"), (300, 200, 32, 1, "iid"),
+                                          (1100, 1000, 128, 2, "exp")])
+def test_bf16_sketch_keeps_the_fp64_factorization(bits, m, n, b, q, kind):
+    """Sketch and power iteration on the BF16 matrix cores (randutv_factor_ex
+    with RANDUTV_SKETCH_BF16X3 = 48 or RANDUTV_SKETCH_BF16 = 16).  The
+    transforms stay FP64, so the invariants hold to the FP64 bar; the
+    rank-k truncation errors stay close to the FP64 ones: the perturbation of
+    the sketch (relative 2^-16 per operand with three split products, 2^-8
+    with one) only tilts the chosen subspaces inside slowly decaying spectra."""
+    A = make_matrix(kind, m, n, seed=2)
+    Ad = to_dev(A)
+    U, T, V = pkg.randutv_factor(Ad, b, q, 0, sketch_bits=bits)
+    res, eu, ev, lower = invariants_dev(Ad, U, T, V)
+    assert res <= TOL_RES and eu <= TOL_ORTH and ev <= TOL_ORTH and lower == 0.0
+    assert diag_blocks_ok(to_host(T), b)
+    Uo, To, Vo = ro.randutv(A, b, q, 0)
+    nA = np.linalg.norm(A)
+    Th = to_host(T)
+    dd = np.abs(np.abs(np.diag(Th)) - np.abs(np.diag(To))).max() / nA
+    errs = []
+    for k in (b, min(n, 2 * b)):
+        Ak = to_host(pkg.randutv_truncate(U, T, V, k))
+        ek = np.linalg.norm(A - Ak) / nA
+        eko = np.linalg.norm(A - Uo[:, :k] @ To[:k, :] @ Vo.T) / nA
+        errs.append((k, ek, eko))
+    print(f"sketch_bits={bits} {m}x{n} b={b} q={q} {kind}: max |d - d_fp64| / |A| = {dd:.2e}; "
+          f"rank-k errors (k, reduced, fp64): {errs}")
+    close = 1e-3 if bits == 48 else 3e-2
+    for k, ek, eko in errs:
+        assert abs(ek - eko) <= close * eko + 1e-9, (k, ek, eko)
