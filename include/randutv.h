@@ -166,7 +166,9 @@ int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d,
 
 /* Per-kernel timing.  randutv_set_timing(1) clears the counters and makes
  * every later randutv_factor call record a HIP event pair around each kernel
- * launch on the stream it is launched on; randutv_set_timing(0) stops it.
+ * launch on the stream it is launched on; randutv_set_timing(2) does the same
+ * for the GEMM launches only (half the event records); randutv_set_timing(0)
+ * stops it.  Other values return -1.
  * randutv_kernel_stats writes, per kernel class, the number of launches, the
  * summed device time in ms and the algorithmic FP64 flops accumulated since
  * timing was enabled.  Returns the number of classes written (at most cap);

@@ -57,6 +57,7 @@ struct EventTimer final : LaunchTimer {
   size_t used = 0;
   std::vector<Rec> recs;
   std::vector<hipEvent_t> open;  // begin events awaiting their end (one per class nesting level)
+  bool gemm_only = false;  // time the GEMM launches alone (fewer event records)
   int64_t launches[K_NUM_CLASSES] = {};
   double ms[K_NUM_CLASSES] = {};
   double flops[K_NUM_CLASSES] = {};
@@ -77,15 +78,16 @@ struct EventTimer final : LaunchTimer {
   void clear_counts() {
     for (int c = 0; c < K_NUM_CLASSES; ++c) launches[c] = 0, ms[c] = 0.0, flops[c] = 0.0;
   }
-  void begin(hipStream_t st, int) override {
-    hipEvent_t e = take();
+  static bool is_gemm(int cls) { return cls >= K_GEMM_NN && cls <= K_GEMM_TT; }
+  void begin(hipStream_t st, int cls) override {
+    hipEvent_t e = gemm_only && !is_gemm(cls) ? nullptr : take();
     if (e) (void)hipEventRecord(e, st);
     open.push_back(e);
   }
   void end(hipStream_t st, int cls, double f) override {
     hipEvent_t a = open.empty() ? nullptr : open.back();
     if (!open.empty()) open.pop_back();
-    hipEvent_t b = take();
+    hipEvent_t b = a ? take() : nullptr;
     if (a && b) {
       (void)hipEventRecord(b, st);
       recs.push_back({a, b, cls, f});
@@ -758,7 +760,9 @@ int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d, double* Us
 int randutv_set_timing(int32_t enable) {
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
+  if (enable < 0 || enable > 2) return -1;
   cx.timing = enable != 0;
+  cx.timer.gemm_only = enable == 2;
   cx.timer.clear_counts();
   return RANDUTV_OK;
 }

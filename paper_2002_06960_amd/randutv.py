@@ -252,8 +252,11 @@ def randutv_gesvj(R):
     return Us, d, Vs, sw.value
 
 
-def randutv_set_timing(enable: bool):
-    _check("randutv_set_timing", load().randutv_set_timing(1 if enable else 0))
+def randutv_set_timing(enable, gemm_only: bool = False):
+    """Per-launch HIP-event timing of later randutv_factor calls (all kernel
+    classes, or the GEMM launches only)."""
+    mode = (2 if gemm_only else 1) if enable else 0
+    _check("randutv_set_timing", load().randutv_set_timing(mode))
 
 
 def randutv_kernel_stats():
