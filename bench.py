@@ -84,8 +84,8 @@ def traffic_entry(kernel: str):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
-                                   "not part of this build (--gpus 1)"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the factorization has "
+                                   "no multi-GPU path (use --gpus 1)"}))
         sys.exit(2)
     import numpy as np
     import torch

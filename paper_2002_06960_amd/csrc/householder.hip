@@ -520,7 +520,7 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
       }
     }
     arrive_and_wait(1);
-    // round 1: workgroup wg sums entries [e0, e1) over all workgroups, in order
+    // first exchange: workgroup wg sums entries [e0, e1) over all workgroups, in order
     {
       const int e0 = (int)((i64)E * wg / P), e1 = (int)((i64)E * (wg + 1) / P);
       constexpr int NB = 16;
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
       }
     }
     arrive_and_wait(2);
-    // round 2: every workgroup reads all totals
+    // second exchange: every workgroup reads all totals
     {
       constexpr int NE = kPQTrail / kPQThreads;
       u64 lo[NE], hi[NE];

@@ -72,6 +72,8 @@ def test_argument_validation_without_device_work():
     g32 = lib.randutv_gemm_f32
     assert g32(b"N", b"Q", 1, 1, 1, 1.0, P, 1, P, 1, 0.0, P, 1) == -2
     assert g32(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 3) == -13
+    assert lib.randutv_set_timing(3) == -1
+    assert lib.randutv_set_timing(0) == 0
     g16 = lib.randutv_gemm_bf16
     assert g16(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 4, 2) == -14   # one or three terms
     assert g16(b"X", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 4, 3) == -1
