@@ -1,0 +1,64 @@
+"""Pins of the first-block truncation derivative reference (CPU, FP64)."""
+import numpy as np
+import pytest
+
+from oracle import randutv_oracle as ro
+from oracle import truncation_grad as tg
+
+
+def _matrix(m, n, seed, decay=0.9):
+    rng = np.random.default_rng(seed)
+    P = np.linalg.qr(rng.standard_normal((m, m)))[0]
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    s = decay ** np.arange(min(m, n))
+    return (P[:, :n] * s) @ Q.T
+
+
+def _algorithm_truncation(A, b, q, seed):
+    U, T, V = ro.randutv(A, b, q, seed)
+    return ro.truncate(U, T, V, min(b, A.shape[1]))
+
+
+@pytest.mark.parametrize("m,n,b,q", [(60, 40, 8, 1), (50, 50, 10, 2), (45, 30, 6, 0), (30, 20, 25, 1)])
+def test_closed_form_is_the_algorithms_first_block(m, n, b, q):
+    """A_k of the step loop (U_k T_k V^T) equals Q Q^T A with Q = orth((A A^T)^(q+1) G(0))."""
+    A = _matrix(m, n, seed=m + n)
+    ref = _algorithm_truncation(A, b, q, 3)
+    got = tg.first_block_truncation(A, b, q, 3)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(A).max()
+    if b >= n:  # one step: the truncation at k = n is A itself
+        assert np.abs(got - A).max() <= 1e-12 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("m,n,b,q", [(40, 30, 8, 1), (36, 36, 6, 2), (30, 24, 5, 0)])
+def test_gradient_matches_finite_differences_of_the_algorithm(m, n, b, q):
+    """<dL/dA, E> against central differences of L(A) = <Gbar, A_k(A)>, with
+    A_k taken from the oracle's full randUTV step loop (not the closed form)."""
+    A = _matrix(m, n, seed=7 * m + n, decay=0.8)
+    rng = np.random.default_rng(11)
+    Gbar = rng.standard_normal((m, n))
+    grad = tg.first_block_truncation_grad(A, b, q, 5, Gbar)
+    # central differences: error ~h^2 f''' (large here: the power iteration
+    # amplifies curvature) plus ~eps |f| / h of rounding; h = 1e-6 keeps both
+    # near 1e-8 relative
+    h = 1e-6
+    for t in range(3):
+        E = rng.standard_normal((m, n))
+        fp = np.sum(Gbar * _algorithm_truncation(A + h * E, b, q, 5))
+        fm = np.sum(Gbar * _algorithm_truncation(A - h * E, b, q, 5))
+        fd = (fp - fm) / (2 * h)
+        an = np.sum(grad * E)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (t, fd, an)
+
+
+def test_gradient_has_the_subspace_term():
+    """The derivative of the projector matters: dropping it (P Gbar alone) is
+    far from the reference, so the pins above would catch that mistake."""
+    A = _matrix(40, 30, seed=1, decay=0.8)
+    rng = np.random.default_rng(2)
+    Gbar = rng.standard_normal((40, 30))
+    grad = tg.first_block_truncation_grad(A, 8, 1, 5, Gbar)
+    Ak = tg.first_block_truncation(A, 8, 1, 5)
+    Q = np.linalg.qr(Ak)[0][:, :8]
+    naive = Q @ (Q.T @ Gbar)
+    assert np.linalg.norm(grad - naive) > 0.1 * np.linalg.norm(grad)
