@@ -52,7 +52,10 @@ def parse():
     ap.add_argument("--mixed-modes", default="fp32,bf16x3,bf16",
                     help="reduced-precision sketch modes timed beside the FP64 run")
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the runs with the sketch and power iteration in reduced precision")
+                    help="skip the runs beside the FP64 headline: the reduced-precision sketches "
+                         "and the differentiable truncation")
+    ap.add_argument("--grad-batch", type=int, default=16,
+                    help="matrices of the differentiable-truncation run (2048 x 2048, b=128; 0: skip)")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the residual/orthogonality check of the timed output (profiler runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -190,7 +193,7 @@ def main():
                 nA = torch.linalg.norm(A)
                 rec["residual"] = (torch.linalg.norm(A - U2 @ T2 @ V2.T) / nA).item()
                 ranks = {}
-                for k in (64, 256, 1024):
+                for k in (kk for kk in (64, 256, 1024) if kk <= n):
                     Ak = pkg.randutv_truncate(U, T, V, k)
                     Ak2 = pkg.randutv_truncate(U2, T2, V2, k)
                     ranks[str(k)] = {"fp64_trunc_err": (torch.linalg.norm(A - Ak) / nA).item(),
@@ -201,6 +204,45 @@ def main():
                 rec["T_vs_fp64"] = (torch.linalg.norm(T2 - T) / nA).item()
             mixed[name] = rec
         del U2, T2, V2
+
+    # differentiable first-block truncation: a batch of 2048 x 2048 matrices
+    # (s_i = 0.98^i), b = 128, q = 2, k = 128; loss ||A_k - B||_F^2 for a
+    # seeded Gaussian B; forward (randutv_factor + randutv_truncate) and
+    # reverse pass (randutv_truncate_grad) timed separately
+    trunc_grad = None
+    if args.grad_batch > 0 and not args.no_mixed:
+        gm, gb, gq = 2048, 128, 2
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(77)
+        As = [make_matrix_device("exp98", gm, gm, seed=100 + i, device=dev) for i in range(args.grad_batch)]
+        Bs = [torch.randn(gm, gm, dtype=torch.float64, device=dev, generator=gen) for _ in As]
+
+        def fwd_bwd(Ai, Bi):
+            X = Ai.detach().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Ak = pkg.first_block_truncation(X, gb, gq, 0)
+            loss = ((Ak - Bi) ** 2).sum()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            loss.backward()
+            torch.cuda.synchronize()
+            return t1 - t0, time.perf_counter() - t1
+
+        fwd_bwd(As[0], Bs[0])
+        tf = tb = 0.0
+        for Ai, Bi in zip(As, Bs):
+            a, c = fwd_bwd(Ai, Bi)
+            tf += a
+            tb += c
+        trunc_grad = {"workload": f"{args.grad_batch} x {gm}x{gm}, s_i = 0.98^i, b={gb}, q={gq}, k={gb}, FP64, "
+                                  "loss ||A_k - B||_F^2",
+                      "ms_forward_per_matrix": round(1e3 * tf / len(As), 3),
+                      "ms_backward_per_matrix": round(1e3 * tb / len(As), 3),
+                      "ms_batch": round(1e3 * (tf + tb), 3)}
+        print(f"# truncation grad batch: forward {1e3 * tf / len(As):.2f} ms, backward "
+              f"{1e3 * tb / len(As):.2f} ms per matrix", file=sys.stderr, flush=True)
+        del As, Bs
 
     roofline = None
     kern = {}
@@ -271,6 +313,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "truncation_grad": trunc_grad,
         "kernels": kern,
     }
     print(json.dumps(out), flush=True)

@@ -34,6 +34,7 @@ extern "C" {
 #define RANDUTV_ERR_NOCONV 4       /* a b x b Jacobi SVD exceeded its sweep cap */
 #define RANDUTV_ERR_SYNC 5         /* a multi-workgroup kernel's bounded wait expired */
 #define RANDUTV_ERR_TOO_LARGE 6    /* a dimension exceeds a documented kernel limit */
+#define RANDUTV_ERR_RANK 7         /* the first block's sketch is rank deficient */
 
 /*
  * randutv_factor -- A = U T V^T (Section 3.1, Figure 2).
@@ -97,6 +98,27 @@ int randutv_factor_ex(int64_t m, int64_t n, const double* A, int64_t lda,
  */
 int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U,
                      const double* T, const double* V, double* Ak);
+
+/*
+ * randutv_truncate_grad -- reverse pass (vector-Jacobian product) of the
+ * first-block truncation A_k, k = min(b, n), of randutv_factor(m, n, A, lda,
+ * b, q, seed, ...) with the sketch G(0) held fixed (Section 3.1 for the first
+ * step; A_k as in randutv_truncate, Section 1.1).
+ * Since T(0:k, :) V^T = U_k^T A, A_k = U_k U_k^T A, and step 0 makes range(U_k)
+ * the range of M = (A A^T)^(q+1) G(0); A_k is the projection of A onto it.
+ *   Gbar : m x n (ld ldg), dL/dA_k of some scalar L.
+ *   Abar : m x n (ld ldab) output, dL/dA; must not alias A or Gbar.
+ * All device pointers, column-major FP64; the call is synchronous.  The
+ * sketch and power products are recomputed (nothing is kept from the
+ * forward call).  Errors: -1 m, -2 n (n < 0 or n > m), -3 A, -4 lda, -5 b,
+ * -6 q, -8 Gbar, -9 ldg, -10 Abar (NULL or aliasing), -11 ldab,
+ * RANDUTV_ERR_TOO_LARGE for min(b, n) > 256, RANDUTV_ERR_NONFINITE for NaN/Inf
+ * in A or Gbar, RANDUTV_ERR_RANK when M has a zero pivot (the projector is
+ * not differentiable there).
+ */
+int randutv_truncate_grad(int64_t m, int64_t n, const double* A, int64_t lda,
+                          int64_t b, int32_t q, uint64_t seed, const double* Gbar,
+                          int64_t ldg, double* Abar, int64_t ldab);
 
 /*
  * randutv_sketch -- write the sketch G(step) (rows x cols, ld = ldg) that

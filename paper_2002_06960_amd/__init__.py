@@ -7,6 +7,7 @@ from .randutv import (  # noqa: F401
     RandUTVError,
     as_colmajor,
     colmajor_empty,
+    first_block_truncation,
     load,
     randutv_dgemm,
     randutv_factor,
@@ -19,6 +20,7 @@ from .randutv import (  # noqa: F401
     randutv_sketch,
     randutv_strerror,
     randutv_truncate,
+    randutv_truncate_grad,
 )
 
 

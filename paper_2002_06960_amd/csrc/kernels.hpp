@@ -77,6 +77,11 @@ int jacobi_svd_batched(hipStream_t st, int count, i64 k, i64 k_last, const doubl
 int sketch(hipStream_t st, uint64_t seed, uint64_t step, i64 rows, i64 cols, double* G,
            i64 ldg);
 int set_identity(hipStream_t st, i64 n, double* X, i64 ldx);
+// X (rows x cols, ld ldx) := the first cols columns of the rows x rows identity
+int set_eye(hipStream_t st, i64 rows, i64 cols, double* X, i64 ldx);
+// X (k x k, ld ldx) := R^{-1} for the upper triangular R (k x k, ld ldr);
+// flag[0] |= 1 if a diagonal entry is zero or the result is not finite
+int tri_inverse(hipStream_t st, i64 k, const double* R, i64 ldr, double* X, i64 ldx, int* flag);
 // B := A (m x n) and flag[0] |= 1 if A holds a non-finite value (flag may be null)
 int copy_check(hipStream_t st, i64 m, i64 n, const double* A, i64 lda, double* B, i64 ldb,
                int* flag);

@@ -17,6 +17,7 @@
 // right factors commute, so the result is the same while the SVD stays off
 // the path that feeds the next step.
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -593,6 +594,133 @@ int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const dou
   return RANDUTV_OK;
 }
 
+// Reverse pass of the first-block truncation A_k = U_k U_k^T A, k = min(b, n)
+// (T(0:k, :) V^T = U_k^T A since T = U^T A V).  Step 0 of the method makes
+// range(U_k) = range(M), M = (A A^T)^(q+1) G(0) (Section 3.1: the sketch and
+// power iteration choose V's first block, A times that block spans range(M),
+// and the panel QR and the b x b SVD only rotate within it).  With
+// P = Q Q^T the projector onto range(M) and M = Q R:
+//   dP = (I - P) dM M^+ + (M^+)^T dM^T (I - P),  M^+ = R^{-1} Q^T,
+// so for L(A_k) with Gbar = dL/dA_k and W = Gbar A^T:
+//   dL/dA = P Gbar + [chain of M] applied to Mbar = (I - P)(W + W^T) Q R^{-T}.
+// The chain M_{j+1} = A (A^T M_j), M_0 = G(0), is recomputed and reversed:
+//   Abar += Mbar_{j+1} Z_j^T + M_j (A^T Mbar_{j+1})^T,  Mbar_j = A A^T Mbar_{j+1}.
+int randutv_truncate_grad(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                          int32_t q, uint64_t seed, const double* Gbar, int64_t ldg,
+                          double* Abar, int64_t ldab) {
+  if (m < 0) return -1;
+  if (n < 0 || n > m) return -2;
+  if (m == 0 || n == 0) return RANDUTV_OK;
+  if (!A) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (b < 1) return -5;
+  if (q < 0) return -6;
+  if (!Gbar) return -8;
+  if (ldg < std::max<int64_t>(1, m)) return -9;
+  if (!Abar || Abar == A || Abar == Gbar) return -10;
+  if (ldab < std::max<int64_t>(1, m)) return -11;
+  const i64 k = std::min<i64>(b, n);
+  if (k > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  RUTV_CHECK(cx.init());
+  hipStream_t st = cx.st;
+  i64 sk = 0;
+  for (auto s3 : {std::array<i64, 3>{n, k, m}, {m, k, n}, {k, k, m}, {k, k, k}, {m, k, k},
+                  {k, n, m}, {m, n, k}})
+    sk = std::max(sk, dgemm_work_elems(s3[0], s3[1], s3[2]));
+  auto layout_grad = [&](Carver& c, double** Mj, double** Zj, double** F, double** tau,
+                         double** Wr, double** Rk, double** Gram, double** Tf, double** X,
+                         double** Q, double** Rinv, double** Qt, double** T1, double** S,
+                         double** Ck, double** Cn, double** Zb, double** wk, int** status,
+                         unsigned long long** xch) {
+    for (int j = 0; j < q + 2; ++j) Mj[j] = c.take<double>(m * k);
+    for (int j = 0; j < q + 1; ++j) Zj[j] = c.take<double>(n * k);
+    *F = c.take<double>(m * k);
+    *tau = c.take<double>(k);
+    *Wr = c.take<double>(m * k);
+    *Rk = c.take<double>(k * k);
+    *Gram = c.take<double>(k * k);
+    *Tf = c.take<double>(k * k);
+    *X = c.take<double>(k * k);
+    *Q = c.take<double>(m * k);
+    *Rinv = c.take<double>(k * k);
+    *Qt = c.take<double>(m * k);
+    *T1 = c.take<double>(n * k);
+    *S = c.take<double>(m * k);
+    *Ck = c.take<double>(k * k);
+    *Cn = c.take<double>(k * n);
+    *Zb = c.take<double>(n * k);
+    *wk = c.take<double>(sk);
+    *status = c.take<int>(4);
+    *xch = c.take<unsigned long long>(panel_work_elems(m));
+  };
+  std::vector<double*> Mj(q + 2), Zj(q + 1);
+  double *F, *tau, *Wr, *Rk, *Gram, *Tf, *X, *Q, *Rinv, *Qt, *T1, *S, *Ck, *Cn, *Zb, *wk;
+  int* status;
+  unsigned long long* xch;
+  Carver probe;
+  layout_grad(probe, Mj.data(), Zj.data(), &F, &tau, &Wr, &Rk, &Gram, &Tf, &X, &Q, &Rinv, &Qt,
+              &T1, &S, &Ck, &Cn, &Zb, &wk, &status, &xch);
+  RUTV_CHECK(cx.reserve(probe.off));
+  Carver real;
+  real.base = cx.ws;
+  layout_grad(real, Mj.data(), Zj.data(), &F, &tau, &Wr, &Rk, &Gram, &Tf, &X, &Q, &Rinv, &Qt,
+              &T1, &S, &Ck, &Cn, &Zb, &wk, &status, &xch);
+  set_launch_timer(nullptr);
+  auto mm = [&](bool ta, bool tb, i64 M_, i64 N_, i64 K_, double alpha, const double* A_, i64 la,
+                const double* B_, i64 lb, double beta, double* C_, i64 lc) {
+    return dgemm(st, ta, tb, M_, N_, K_, alpha, A_, la, B_, lb, beta, C_, lc, wk, sk);
+  };
+  RUTV_TRY(hipMemsetAsync(status, 0, 4 * sizeof(int), st));
+  RUTV_CHECK(check_finite(st, m, n, A, lda, &status[0]));
+  RUTV_CHECK(check_finite(st, m, n, Gbar, ldg, &status[0]));
+  // M_0 = G(0); Z_j = A^T M_j; M_{j+1} = A Z_j
+  RUTV_CHECK(sketch(st, seed, 0, m, k, Mj[0], m));
+  for (int j = 0; j <= q; ++j) {
+    RUTV_CHECK(mm(true, false, n, k, m, 1.0, A, lda, Mj[j], m, 0.0, Zj[j], n));
+    RUTV_CHECK(mm(false, false, m, k, n, 1.0, A, lda, Zj[j], n, 0.0, Mj[j + 1], m));
+  }
+  // M = Q R: Householder QR, Q = (I - W Tf W^T) [I; 0] = [I; 0] - W (Tf W_1^T)
+  RUTV_CHECK(copy_matrix(st, m, k, Mj[q + 1], m, F, m));
+  PanelWork pw;
+  pw.xch = xch;
+  pw.err = &status[1];
+  RUTV_CHECK(panel_qr(st, m, k, F, m, tau, pw));
+  RUTV_CHECK(extract_reflectors(st, m, k, F, m, Wr, m, Rk, k, false));
+  RUTV_CHECK(mm(true, false, k, k, m, 1.0, Wr, m, Wr, m, 0.0, Gram, k));
+  RUTV_CHECK(larft_from_gram(st, k, Gram, k, tau, Tf, k));
+  RUTV_CHECK(mm(false, true, k, k, k, 1.0, Tf, k, Wr, m, 0.0, X, k));
+  RUTV_CHECK(set_eye(st, m, k, Q, m));
+  RUTV_CHECK(mm(false, false, m, k, k, -1.0, Wr, m, X, k, 1.0, Q, m));
+  // Qt = Q R^{-T} = (M^+)^T
+  RUTV_CHECK(tri_inverse(st, k, Rk, k, Rinv, k, &status[2]));
+  RUTV_CHECK(mm(false, true, m, k, k, 1.0, Q, m, Rinv, k, 0.0, Qt, m));
+  // S = (W + W^T) Qt = Gbar (A^T Qt) + A (Gbar^T Qt); Mbar = S - Q (Q^T S)
+  RUTV_CHECK(mm(true, false, n, k, m, 1.0, A, lda, Qt, m, 0.0, T1, n));
+  RUTV_CHECK(mm(false, false, m, k, n, 1.0, Gbar, ldg, T1, n, 0.0, S, m));
+  RUTV_CHECK(mm(true, false, n, k, m, 1.0, Gbar, ldg, Qt, m, 0.0, T1, n));
+  RUTV_CHECK(mm(false, false, m, k, n, 1.0, A, lda, T1, n, 1.0, S, m));
+  RUTV_CHECK(mm(true, false, k, k, m, 1.0, Q, m, S, m, 0.0, Ck, k));
+  RUTV_CHECK(mm(false, false, m, k, k, -1.0, Q, m, Ck, k, 1.0, S, m));
+  // Abar = P Gbar, then the chain of M in reverse
+  RUTV_CHECK(mm(true, false, k, n, m, 1.0, Q, m, Gbar, ldg, 0.0, Cn, k));
+  RUTV_CHECK(mm(false, false, m, n, k, 1.0, Q, m, Cn, k, 0.0, Abar, ldab));
+  for (int j = q; j >= 0; --j) {
+    RUTV_CHECK(mm(false, true, m, n, k, 1.0, S, m, Zj[j], n, 1.0, Abar, ldab));
+    RUTV_CHECK(mm(true, false, n, k, m, 1.0, A, lda, S, m, 0.0, Zb, n));
+    RUTV_CHECK(mm(false, true, m, n, k, 1.0, Mj[j], m, Zb, n, 1.0, Abar, ldab));
+    if (j > 0) RUTV_CHECK(mm(false, false, m, k, n, 1.0, A, lda, Zb, n, 0.0, S, m));
+  }
+  int flags[4] = {0, 0, 0, 0};
+  RUTV_TRY(hipMemcpyAsync(flags, status, sizeof(flags), hipMemcpyDeviceToHost, st));
+  RUTV_TRY(hipStreamSynchronize(st));
+  if (flags[0]) return RANDUTV_ERR_NONFINITE;
+  if (flags[1]) return RANDUTV_ERR_SYNC;
+  if (flags[2]) return RANDUTV_ERR_RANK;
+  return RANDUTV_OK;
+}
+
 int randutv_sketch(uint64_t seed, uint64_t step, int64_t rows, int64_t cols, double* G,
                    int64_t ldg) {
   if (rows < 0) return -3;
@@ -801,6 +929,7 @@ const char* randutv_strerror(int code) {
     case RANDUTV_ERR_NOCONV: return "Jacobi SVD did not converge within 30 sweeps";
     case RANDUTV_ERR_SYNC: return "multi-workgroup kernel wait expired";
     case RANDUTV_ERR_TOO_LARGE: return "dimension exceeds a kernel limit";
+    case RANDUTV_ERR_RANK: return "the first block's sketch is rank deficient (no derivative)";
     default: return code < 0 ? "invalid argument" : "unknown error";
   }
 }

@@ -78,18 +78,50 @@ int sketch(hipStream_t st, uint64_t seed, uint64_t step, i64 rows, i64 cols, dou
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void identity_kernel(i64 n, double* __restrict__ X, i64 ldx) {
-  const i64 total = n * n;
+__global__ __launch_bounds__(256) void identity_kernel(i64 rows, i64 cols, double* __restrict__ X,
+                                                      i64 ldx) {
+  const i64 total = rows * cols;
   for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
-    const i64 r = e % n, c = e / n;
+    const i64 r = e % rows, c = e / rows;
     X[r + c * ldx] = r == c ? 1.0 : 0.0;
   }
 }
 
-int set_identity(hipStream_t st, i64 n, double* X, i64 ldx) {
-  if (n <= 0) return RANDUTV_OK;
-  const int blocks = (int)std::min<i64>(cdiv(n * n, 256), 16384);
-  identity_kernel<<<blocks, 256, 0, st>>>(n, X, ldx);
+int set_eye(hipStream_t st, i64 rows, i64 cols, double* X, i64 ldx) {
+  if (rows <= 0 || cols <= 0) return RANDUTV_OK;
+  const int blocks = (int)std::min<i64>(cdiv(rows * cols, 256), 16384);
+  identity_kernel<<<blocks, 256, 0, st>>>(rows, cols, X, ldx);
+  RUTV_TRY(hipGetLastError());
+  return RANDUTV_OK;
+}
+
+int set_identity(hipStream_t st, i64 n, double* X, i64 ldx) { return set_eye(st, n, n, X, ldx); }
+
+// inverse of the k x k upper triangular R by back substitution, one column of
+// the inverse per thread (R^{-1} e_j needs rows 0..j of column j only); the
+// lower triangle is written as zeros
+__global__ __launch_bounds__(64) void tri_inverse_kernel(int k, const double* __restrict__ R,
+                                                         i64 ldr, double* __restrict__ X, i64 ldx,
+                                                         int* __restrict__ flag) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= k) return;
+  double* x = X + (i64)j * ldx;
+  bool bad = false;
+  for (int i = k - 1; i > j; --i) x[i] = 0.0;
+  for (int i = j; i >= 0; --i) {
+    double s = i == j ? 1.0 : 0.0;
+    for (int l = i + 1; l <= j; ++l) s -= R[i + (i64)l * ldr] * x[l];
+    const double r = R[i + (i64)i * ldr];
+    const double v = s / r;
+    bad |= r == 0.0 || !isfinite(v);
+    x[i] = v;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+int tri_inverse(hipStream_t st, i64 k, const double* R, i64 ldr, double* X, i64 ldx, int* flag) {
+  if (k <= 0) return RANDUTV_OK;
+  tri_inverse_kernel<<<(int)cdiv(k, 64), 64, 0, st>>>((int)k, R, ldr, X, ldx, flag);
   RUTV_TRY(hipGetLastError());
   return RANDUTV_OK;
 }

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librandutv.so")
 
 RANDUTV_OK = 0
-ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONV, ERR_SYNC, ERR_TOO_LARGE = 1, 2, 3, 4, 5, 6
+ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONV, ERR_SYNC, ERR_TOO_LARGE, ERR_RANK = 1, 2, 3, 4, 5, 6, 7
 
 # name -> (restype, argtypes)
 _I64, _I32, _U64, _D, _P, _C = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double,
@@ -26,6 +26,7 @@ SIGNATURES = {
     "randutv_factor": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P]),
     "randutv_factor_ex": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P, _I32]),
     "randutv_truncate": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _P]),
+    "randutv_truncate_grad": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64, _P, _I64]),
     "randutv_sketch": (ctypes.c_int, [_U64, _U64, _I64, _I64, _P, _I64]),
     "randutv_dgemm": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
     "randutv_gemm_f32": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
@@ -172,6 +173,59 @@ def randutv_truncate(U, T, V, k: int):
     _sync()
     _check("randutv_truncate", lib.randutv_truncate(m, n, k, _ptr(U), _ptr(T), _ptr(V), _ptr(Ak)))
     return Ak
+
+
+def randutv_truncate_grad(A, b: int, q: int, seed: int, Gbar):
+    """dL/dA for the first-block truncation A_k (k = min(b, n)) of
+    randutv_factor(A, b, q, seed), given Gbar = dL/dA_k (sketch held fixed)."""
+    lib = load()
+    A, lda = as_colmajor(A)
+    Gbar, ldg = as_colmajor(Gbar)
+    m, n = A.shape
+    if tuple(Gbar.shape) != (m, n):
+        raise ValueError("Gbar must have the shape of A")
+    Abar = colmajor_empty(m, n, A.device)
+    _sync()
+    _check("randutv_truncate_grad", lib.randutv_truncate_grad(m, n, _ptr(A), lda, b, q,
+                                                              seed & (2**64 - 1), _ptr(Gbar), ldg,
+                                                              _ptr(Abar), max(1, m)))
+    return Abar
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class FirstBlockTruncation(torch.autograd.Function):
+        """A -> A_k, k = min(b, n): randutv_factor then randutv_truncate on the
+        forward pass, randutv_truncate_grad on the reverse pass."""
+
+        @staticmethod
+        def forward(ctx, A, b, q, seed):
+            U, T, V = randutv_factor(A, b, q, seed)
+            Ak = randutv_truncate(U, T, V, min(b, A.shape[1]))
+            ctx.save_for_backward(A)
+            ctx.b, ctx.q, ctx.seed = b, q, seed
+            return Ak
+
+        @staticmethod
+        def backward(ctx, gout):
+            (A,) = ctx.saved_tensors
+            return randutv_truncate_grad(A, ctx.b, ctx.q, ctx.seed, gout), None, None, None
+
+    return FirstBlockTruncation
+
+
+_first_block_fn = None
+
+
+def first_block_truncation(A, b: int, q: int, seed: int = 0):
+    """Differentiable rank-k truncation of randUTV at k = min(b, n), the
+    sketch G(0) held fixed: returns A_k = U_k T_k V^T as a tensor that
+    torch.autograd differentiates through randutv_truncate_grad."""
+    global _first_block_fn
+    if _first_block_fn is None:
+        _first_block_fn = _autograd_function()
+    return _first_block_fn.apply(A, b, q, seed)
 
 
 def randutv_sketch(seed: int, step: int, rows: int, cols: int, device=None):

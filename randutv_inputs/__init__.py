@@ -15,6 +15,7 @@ parity check generates it from the counter-based generator's definition).
 Spectra (1-based index i, n singular values):
     "log8": s_i = 10^(-8 (i-1)/(n-1))            (eight decades, smooth decay)
     "exp":  s_i = 0.99^i                            (exponential decay)
+    "exp98": s_i = 0.98^i                           (faster exponential decay)
     "step": s_i = 1 for i <= 400, 1e-6 otherwise, plus 1e-10 * N(0,1) noise on A
     "iid":  A itself has i.i.d. N(0,1) entries (no P, Q)
 """
@@ -22,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-SPECTRA = ("log8", "exp", "step", "iid")
+SPECTRA = ("log8", "exp", "exp98", "step", "iid")
 
 # seed offsets for the independent random streams of one test matrix
 _SEED_P, _SEED_Q, _SEED_NOISE, _SEED_IID = 1, 2, 3, 4
@@ -37,6 +38,8 @@ def spectrum(kind: str, n: int) -> np.ndarray:
         return 10.0 ** (-8.0 * (i - 1.0) / (n - 1.0))
     if kind == "exp":
         return 0.99 ** i
+    if kind == "exp98":
+        return 0.98 ** i
     if kind == "step":
         s = np.full(n, 1e-6)
         s[: min(400, n)] = 1.0

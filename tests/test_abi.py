@@ -72,6 +72,20 @@ def test_argument_validation_without_device_work():
     g32 = lib.randutv_gemm_f32
     assert g32(b"N", b"Q", 1, 1, 1, 1.0, P, 1, P, 1, 0.0, P, 1) == -2
     assert g32(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 3) == -13
+    tg_ = lib.randutv_truncate_grad
+    assert tg_(-1, 3, P, 5, 2, 0, 0, P, 5, P, 5) == -1
+    assert tg_(4, 5, P, 4, 2, 0, 0, P, 4, P, 4) == -2                  # n > m
+    assert tg_(5, 3, None, 5, 2, 0, 0, P, 5, P, 5) == -3
+    assert tg_(5, 3, P, 4, 2, 0, 0, P, 5, P, 5) == -4
+    assert tg_(5, 3, P, 5, 0, 0, 0, P, 5, P, 5) == -5
+    assert tg_(5, 3, P, 5, 2, -1, 0, P, 5, P, 5) == -6
+    assert tg_(5, 3, P, 5, 2, 0, 0, None, 5, P, 5) == -8
+    assert tg_(5, 3, P, 5, 2, 0, 0, P, 4, ctypes.c_void_p(0x2000), 5) == -9
+    assert tg_(5, 3, P, 5, 2, 0, 0, ctypes.c_void_p(0x2000), 5, P, 5) == -10   # Abar aliases A
+    assert tg_(5, 3, P, 5, 2, 0, 0, ctypes.c_void_p(0x2000), 5, ctypes.c_void_p(0x3000), 4) == -11
+    assert tg_(600, 600, P, 600, 300, 0, 0, ctypes.c_void_p(0x2000), 600, ctypes.c_void_p(0x3000),
+               600) == rb.ERR_TOO_LARGE
+    assert tg_(0, 0, None, 1, 2, 0, 0, None, 1, None, 1) == 0
     assert lib.randutv_set_timing(3) == -1
     assert lib.randutv_set_timing(0) == 0
     g16 = lib.randutv_gemm_bf16
