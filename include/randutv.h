@@ -100,6 +100,20 @@ int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U,
                      const double* T, const double* V, double* Ak);
 
 /*
+ * randutv_truncate_first_block -- the first-block truncation A_k,
+ * k = min(b, n), of randutv_factor(m, n, A, lda, b, q, seed, ...) computed
+ * without the rest of the factorization: A_k = Q Q^T A with Q an orthonormal
+ * basis of the range of M = (A A^T)^(q+1) G(0) (Section 3.1's first step;
+ * why this equals U_k T(0:k, :) V^T is explained at randutv_truncate_grad).
+ * Ak: m x n output (ld ldak), must not alias A.  Device pointers, column-major
+ * FP64, synchronous.  Errors: -1 m, -2 n, -3 A, -4 lda, -5 b, -6 q, -8 Ak,
+ * -9 ldak, RANDUTV_ERR_TOO_LARGE for min(b, n) > 256, RANDUTV_ERR_NONFINITE.
+ */
+int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t lda,
+                                 int64_t b, int32_t q, uint64_t seed, double* Ak,
+                                 int64_t ldak);
+
+/*
  * randutv_truncate_grad -- reverse pass (vector-Jacobian product) of the
  * first-block truncation A_k, k = min(b, n), of randutv_factor(m, n, A, lda,
  * b, q, seed, ...) with the sketch G(0) held fixed (Section 3.1 for the first

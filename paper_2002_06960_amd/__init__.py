@@ -20,6 +20,7 @@ from .randutv import (  # noqa: F401
     randutv_sketch,
     randutv_strerror,
     randutv_truncate,
+    randutv_truncate_first_block,
     randutv_truncate_grad,
 )
 

@@ -594,6 +594,86 @@ int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const dou
   return RANDUTV_OK;
 }
 
+// Forward value of the first-block truncation without the rest of the
+// factorization: A_k = Q Q^T A, Q an orthonormal basis of the range of
+// M = (A A^T)^(q+1) G(0) (k = min(b, n); the identity is explained at
+// randutv_truncate_grad below).
+int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                                 int32_t q, uint64_t seed, double* Ak, int64_t ldak) {
+  if (m < 0) return -1;
+  if (n < 0 || n > m) return -2;
+  if (m == 0 || n == 0) return RANDUTV_OK;
+  if (!A) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (b < 1) return -5;
+  if (q < 0) return -6;
+  if (!Ak || Ak == A) return -8;
+  if (ldak < std::max<int64_t>(1, m)) return -9;
+  const i64 k = std::min<i64>(b, n);
+  if (k > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  RUTV_CHECK(cx.init());
+  hipStream_t st = cx.st;
+  i64 sk = 0;
+  for (auto s3 : {std::array<i64, 3>{n, k, m}, {m, k, n}, {k, k, m}, {k, k, k}, {m, k, k},
+                  {k, n, m}, {m, n, k}})
+    sk = std::max(sk, dgemm_work_elems(s3[0], s3[1], s3[2]));
+  double *M, *Z, *tau, *Wr, *Gram, *Tf, *X, *Q, *Cn, *wk;
+  int* status;
+  unsigned long long* xch;
+  auto lay = [&](Carver& c) {
+    M = c.take<double>(m * k);
+    Z = c.take<double>(n * k);
+    tau = c.take<double>(k);
+    Wr = c.take<double>(m * k);
+    Gram = c.take<double>(k * k);
+    Tf = c.take<double>(k * k);
+    X = c.take<double>(k * k);
+    Q = c.take<double>(m * k);
+    Cn = c.take<double>(k * n);
+    wk = c.take<double>(sk);
+    status = c.take<int>(4);
+    xch = c.take<unsigned long long>(panel_work_elems(m));
+  };
+  Carver probe;
+  lay(probe);
+  RUTV_CHECK(cx.reserve(probe.off));
+  Carver real;
+  real.base = cx.ws;
+  lay(real);
+  set_launch_timer(nullptr);
+  auto mm = [&](bool ta, bool tb, i64 M_, i64 N_, i64 K_, double alpha, const double* A_, i64 la,
+                const double* B_, i64 lb, double beta, double* C_, i64 lc) {
+    return dgemm(st, ta, tb, M_, N_, K_, alpha, A_, la, B_, lb, beta, C_, lc, wk, sk);
+  };
+  RUTV_TRY(hipMemsetAsync(status, 0, 4 * sizeof(int), st));
+  RUTV_CHECK(check_finite(st, m, n, A, lda, &status[0]));
+  RUTV_CHECK(sketch(st, seed, 0, m, k, M, m));
+  for (int j = 0; j <= q; ++j) {
+    RUTV_CHECK(mm(true, false, n, k, m, 1.0, A, lda, M, m, 0.0, Z, n));
+    RUTV_CHECK(mm(false, false, m, k, n, 1.0, A, lda, Z, n, 0.0, M, m));
+  }
+  PanelWork pw;
+  pw.xch = xch;
+  pw.err = &status[1];
+  RUTV_CHECK(panel_qr(st, m, k, M, m, tau, pw));
+  RUTV_CHECK(extract_reflectors(st, m, k, M, m, Wr, m, nullptr, 0, false));
+  RUTV_CHECK(mm(true, false, k, k, m, 1.0, Wr, m, Wr, m, 0.0, Gram, k));
+  RUTV_CHECK(larft_from_gram(st, k, Gram, k, tau, Tf, k));
+  RUTV_CHECK(mm(false, true, k, k, k, 1.0, Tf, k, Wr, m, 0.0, X, k));
+  RUTV_CHECK(set_eye(st, m, k, Q, m));
+  RUTV_CHECK(mm(false, false, m, k, k, -1.0, Wr, m, X, k, 1.0, Q, m));
+  RUTV_CHECK(mm(true, false, k, n, m, 1.0, Q, m, A, lda, 0.0, Cn, k));
+  RUTV_CHECK(mm(false, false, m, n, k, 1.0, Q, m, Cn, k, 0.0, Ak, ldak));
+  int flags[4] = {0, 0, 0, 0};
+  RUTV_TRY(hipMemcpyAsync(flags, status, sizeof(flags), hipMemcpyDeviceToHost, st));
+  RUTV_TRY(hipStreamSynchronize(st));
+  if (flags[0]) return RANDUTV_ERR_NONFINITE;
+  if (flags[1]) return RANDUTV_ERR_SYNC;
+  return RANDUTV_OK;
+}
+
 // Reverse pass of the first-block truncation A_k = U_k U_k^T A, k = min(b, n)
 // (T(0:k, :) V^T = U_k^T A since T = U^T A V).  Step 0 of the method makes
 // range(U_k) = range(M), M = (A A^T)^(q+1) G(0) (Section 3.1: the sketch and

@@ -27,6 +27,7 @@ SIGNATURES = {
     "randutv_factor_ex": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P, _I32]),
     "randutv_truncate": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _P]),
     "randutv_truncate_grad": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64, _P, _I64]),
+    "randutv_truncate_first_block": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64]),
     "randutv_sketch": (ctypes.c_int, [_U64, _U64, _I64, _I64, _P, _I64]),
     "randutv_dgemm": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
     "randutv_gemm_f32": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
@@ -175,6 +176,20 @@ def randutv_truncate(U, T, V, k: int):
     return Ak
 
 
+def randutv_truncate_first_block(A, b: int, q: int, seed: int = 0):
+    """A_k, k = min(b, n), of randutv_factor(A, b, q, seed) from the first
+    step alone (Q Q^T A with Q spanning (A A^T)^(q+1) G(0))."""
+    lib = load()
+    A, lda = as_colmajor(A)
+    m, n = A.shape
+    Ak = colmajor_empty(m, n, A.device)
+    _sync()
+    _check("randutv_truncate_first_block",
+           lib.randutv_truncate_first_block(m, n, _ptr(A), lda, b, q, seed & (2**64 - 1), _ptr(Ak),
+                                            max(1, m)))
+    return Ak
+
+
 def randutv_truncate_grad(A, b: int, q: int, seed: int, Gbar):
     """dL/dA for the first-block truncation A_k (k = min(b, n)) of
     randutv_factor(A, b, q, seed), given Gbar = dL/dA_k (sketch held fixed)."""
@@ -197,12 +212,16 @@ def _autograd_function():
 
     class FirstBlockTruncation(torch.autograd.Function):
         """A -> A_k, k = min(b, n): randutv_factor then randutv_truncate on the
-        forward pass, randutv_truncate_grad on the reverse pass."""
+        forward pass (or, with first_step_only, randutv_truncate_first_block),
+        randutv_truncate_grad on the reverse pass."""
 
         @staticmethod
-        def forward(ctx, A, b, q, seed):
-            U, T, V = randutv_factor(A, b, q, seed)
-            Ak = randutv_truncate(U, T, V, min(b, A.shape[1]))
+        def forward(ctx, A, b, q, seed, first_step_only):
+            if first_step_only:
+                Ak = randutv_truncate_first_block(A, b, q, seed)
+            else:
+                U, T, V = randutv_factor(A, b, q, seed)
+                Ak = randutv_truncate(U, T, V, min(b, A.shape[1]))
             ctx.save_for_backward(A)
             ctx.b, ctx.q, ctx.seed = b, q, seed
             return Ak
@@ -210,7 +229,7 @@ def _autograd_function():
         @staticmethod
         def backward(ctx, gout):
             (A,) = ctx.saved_tensors
-            return randutv_truncate_grad(A, ctx.b, ctx.q, ctx.seed, gout), None, None, None
+            return randutv_truncate_grad(A, ctx.b, ctx.q, ctx.seed, gout), None, None, None, None
 
     return FirstBlockTruncation
 
@@ -218,14 +237,16 @@ def _autograd_function():
 _first_block_fn = None
 
 
-def first_block_truncation(A, b: int, q: int, seed: int = 0):
+def first_block_truncation(A, b: int, q: int, seed: int = 0, first_step_only: bool = False):
     """Differentiable rank-k truncation of randUTV at k = min(b, n), the
     sketch G(0) held fixed: returns A_k = U_k T_k V^T as a tensor that
-    torch.autograd differentiates through randutv_truncate_grad."""
+    torch.autograd differentiates through randutv_truncate_grad.  With
+    first_step_only the forward value comes from the first step alone
+    (the same A_k without factoring the rest of A)."""
     global _first_block_fn
     if _first_block_fn is None:
         _first_block_fn = _autograd_function()
-    return _first_block_fn.apply(A, b, q, seed)
+    return _first_block_fn.apply(A, b, q, seed, first_step_only)
 
 
 def randutv_sketch(seed: int, step: int, rows: int, cols: int, device=None):

@@ -86,6 +86,11 @@ def test_argument_validation_without_device_work():
     assert tg_(600, 600, P, 600, 300, 0, 0, ctypes.c_void_p(0x2000), 600, ctypes.c_void_p(0x3000),
                600) == rb.ERR_TOO_LARGE
     assert tg_(0, 0, None, 1, 2, 0, 0, None, 1, None, 1) == 0
+    fb = lib.randutv_truncate_first_block
+    assert fb(-1, 3, P, 5, 2, 0, 0, P, 5) == -1
+    assert fb(5, 3, P, 5, 2, 0, 0, P, 5) == -8                         # Ak aliases A
+    assert fb(5, 3, P, 5, 2, 0, 0, ctypes.c_void_p(0x2000), 4) == -9
+    assert fb(5, 3, P, 5, 2, -1, 0, ctypes.c_void_p(0x2000), 5) == -6
     assert lib.randutv_set_timing(3) == -1
     assert lib.randutv_set_timing(0) == 0
     g16 = lib.randutv_gemm_bf16

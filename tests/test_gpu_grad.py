@@ -95,3 +95,26 @@ def test_grad_errors():
     with pytest.raises(pkg.RandUTVError) as e:
         pkg.randutv_truncate_grad(to_dev(A), 16, 1, 0, to_dev(G))
     assert e.value.code == 3
+
+
+@pytest.mark.parametrize("m,n,b,q,kind", [(512, 512, 64, 2, "exp"), (700, 500, 128, 2, "exp98"),
+                                          (300, 200, 256, 1, "iid")])
+def test_first_step_forward(m, n, b, q, kind):
+    """randutv_truncate_first_block against the closed form on the CPU and
+    against the full factorization's truncation on the GPU; the subspaces
+    agree to rounding amplified by cond(M) (as for the gradient)."""
+    A = make_matrix(kind, m, n, seed=6)
+    Ad = to_dev(A)
+    got = to_host(pkg.randutv_truncate_first_block(Ad, b, q, 2))
+    ref = tg.first_block_truncation(A, b, q, 2)
+    U, T, V = pkg.randutv_factor(Ad, b, q, 2)
+    full = to_host(pkg.randutv_truncate(U, T, V, min(b, n)))
+    M = tg.first_block_sketch(A, b, 2)
+    for _ in range(q + 1):
+        M = A @ (A.T @ M)
+    tol = max(1e-12, 100 * 2.0**-52 * np.linalg.cond(M)) * np.abs(A).max()
+    assert np.abs(got - ref).max() <= tol
+    assert np.abs(got - full).max() <= tol
+    # the autograd binding's two forward forms give the same value
+    Ak = pkg.first_block_truncation(Ad, b, q, 2, first_step_only=True)
+    assert np.abs(to_host(Ak) - got).max() == 0.0
