@@ -100,6 +100,24 @@ int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U,
                      const double* T, const double* V, double* Ak);
 
 /*
+ * randutv_hqrrp -- randomized blocked column-pivoted QR A P = Q R (HQRRP,
+ * Section 2, with the sketch of each step drawn as randutv_factor's step i:
+ * Y = G^T A(s:m, s:n), G (m - s) x b_i; b_i steps of Householder CPQR on Y
+ * choose the pivots (largest residual norm, lowest column on ties); the
+ * column holding the t-th pivot is exchanged with column s + t; unpivoted
+ * Householder QR of the b_i-column panel; compact-WY update of the rest).
+ *   A    : m x n (ld lda), overwritten in the LAPACK dgeqp3 layout: R on and
+ *          above the diagonal, the reflector vectors (v(0) = 1 implied) below.
+ *   tau  : n reflector scalars (device).
+ *   jpvt : n int64 (device): column j of A P is column jpvt[j] of A.
+ * m >= n.  b > n is clamped to n.  Synchronous.  Errors: -1 m, -2 n, -3 A,
+ * -4 lda, -5 b, -7 tau, -8 jpvt, RANDUTV_ERR_TOO_LARGE for min(b, n) > 256,
+ * RANDUTV_ERR_NONFINITE (A untouched), RANDUTV_ERR_SYNC.
+ */
+int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b,
+                  uint64_t seed, double* tau, int64_t* jpvt);
+
+/*
  * randutv_truncate_first_block -- the first-block truncation A_k,
  * k = min(b, n), of randutv_factor(m, n, A, lda, b, q, seed, ...) computed
  * without the rest of the factorization: A_k = Q Q^T A with Q an orthonormal

@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .randutv_oracle import householder_qr, householder_reflector, sketch_block
+from .randutv_oracle import householder_qr, householder_reflector, sketch_block  # noqa: F401
 
 
 def cpqr_pivots(Y: np.ndarray, k: int) -> list:

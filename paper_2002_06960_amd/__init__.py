@@ -13,6 +13,7 @@ from .randutv import (  # noqa: F401
     randutv_factor,
     randutv_geqrf,
     randutv_gesvj,
+    randutv_hqrrp,
     randutv_kernel_stats,
     randutv_larft,
     randutv_last_sweeps,

@@ -73,6 +73,29 @@ int jacobi_svd_batched(hipStream_t st, int count, i64 k, i64 k_last, const doubl
                        i64 rs, double* d, i64 ds, double* Us, double* Vs, i64 us, double* work,
                        int* status);
 
+// ---- HQRRP pivoting (hqrrp.hip) ---------------------------------------------
+struct CpqrWork {
+  double* sval = nullptr;     // 2 * 256 per-workgroup best norms (by step parity)
+  int* sidx = nullptr;        // 2 * 256 their columns
+  unsigned* counter = nullptr;  // grid barrier counter
+  int* err = nullptr;         // device status word
+};
+struct ExchangeWork {
+  int *idx = nullptr, *where = nullptr;  // N entries each
+  int *chg = nullptr, *cnt = nullptr;    // 2k entries, 1
+  double* tmp = nullptr;                 // m x 2k
+  int64_t* jtmp = nullptr;               // 2k
+};
+// J[0..k) := the columns chosen by k steps of Householder column-pivoted QR of
+// Y (k x N, ld ldy, k <= 256; Y is overwritten): largest residual norm first,
+// the lowest column on ties
+int cpqr_pivots(hipStream_t st, i64 k, i64 N, double* Y, i64 ldy, int* J, CpqrWork& w);
+// exchange, in A (m rows, columns 0..N-1, ld lda) and jp, the column holding
+// J[t] with column t for t = 0..k-1 in turn
+int exchange_columns(hipStream_t st, i64 m, i64 k, i64 N, const int* J, double* A, i64 lda,
+                     int64_t* jp, ExchangeWork& w);
+int set_iota(hipStream_t st, i64 n, int64_t* x);
+
 // ---- sketch and utilities (util.hip) ----------------------------------------
 int sketch(hipStream_t st, uint64_t seed, uint64_t step, i64 rows, i64 cols, double* G,
            i64 ldg);

@@ -594,6 +594,110 @@ int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const dou
   return RANDUTV_OK;
 }
 
+// HQRRP (Section 2): A P = Q R by blocks of b columns.  Step i (s = i b):
+// Y = G^T A(s:m, s:n) with G the (m - s) x b_i sketch of randUTV's step i;
+// b_i steps of CPQR on Y choose the pivots; the chosen columns are exchanged
+// to the front (all m rows); Householder QR of the b_i-column panel; the
+// remaining columns of rows s..m-1 get Q22^T = H^T (compact WY).
+int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint64_t seed,
+                  double* tau, int64_t* jpvt) {
+  if (m < 0) return -1;
+  if (n < 0 || n > m) return -2;
+  if (m == 0 || n == 0) return RANDUTV_OK;
+  if (!A) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (b < 1) return -5;
+  if (!tau) return -7;
+  if (!jpvt) return -8;
+  if (b > n) b = n;
+  if (b > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+  if (n > INT32_MAX / 2) return RANDUTV_ERR_TOO_LARGE;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  RUTV_CHECK(cx.init());
+  hipStream_t st = cx.st;
+  i64 sk = 0;
+  for (i64 s0 = 0; s0 < n; s0 += b) {
+    const i64 bi = std::min(b, n - s0), mi = m - s0, ni = n - s0;
+    for (auto s3 : {std::array<i64, 3>{bi, ni, mi}, {bi, bi, mi}, {mi, bi, bi}, {bi, ni - bi, mi},
+                    {mi, ni - bi, bi}})
+      if (s3[1] > 0) sk = std::max(sk, dgemm_work_elems(s3[0], s3[1], s3[2]));
+  }
+  StreamWS x;
+  double *G, *Y, *W, *Z, *X3;
+  int *J, *status;
+  CpqrWork cw;
+  ExchangeWork ew;
+  unsigned long long* xch;
+  auto lay = [&](Carver& c) {
+    x.splitk_elems = sk;
+    x.splitk = c.take<double>(sk);
+    x.Gram = c.take<double>(b * b);
+    x.Tf = c.take<double>(b * b);
+    G = c.take<double>(m * b);
+    Y = c.take<double>(b * n);
+    W = c.take<double>(m * b);
+    Z = c.take<double>(m * b);
+    X3 = c.take<double>(b * n);
+    J = c.take<int>(b);
+    cw.sval = c.take<double>(2 * 256);
+    cw.sidx = c.take<int>(2 * 256);
+    cw.counter = c.take<unsigned>(1);
+    ew.idx = c.take<int>(n);
+    ew.where = c.take<int>(n);
+    ew.chg = c.take<int>(2 * b);
+    ew.cnt = c.take<int>(1);
+    ew.tmp = c.take<double>(m * 2 * b);
+    ew.jtmp = c.take<int64_t>(2 * b);
+    status = c.take<int>(4);
+    xch = c.take<unsigned long long>(panel_work_elems(m));
+  };
+  Carver probe;
+  lay(probe);
+  RUTV_CHECK(cx.reserve(probe.off));
+  Carver real;
+  real.base = cx.ws;
+  lay(real);
+  cw.err = &status[0];
+  PanelWork pw;
+  pw.xch = xch;
+  pw.err = &status[1];
+  set_launch_timer(nullptr);
+  RUTV_TRY(hipMemsetAsync(status, 0, 4 * sizeof(int), st));
+  RUTV_CHECK(check_finite(st, m, n, A, lda, &status[2]));
+  {
+    int flag = 0;
+    RUTV_TRY(hipMemcpyAsync(&flag, &status[2], sizeof(int), hipMemcpyDeviceToHost, st));
+    RUTV_TRY(hipStreamSynchronize(st));
+    if (flag) return RANDUTV_ERR_NONFINITE;
+  }
+  RUTV_CHECK(set_iota(st, n, jpvt));
+  i64 s = 0;
+  for (i64 i = 0; s < n; ++i) {
+    const i64 bi = std::min(b, n - s), mi = m - s, ni = n - s;
+    double* As = A + s * lda;  // columns s..n-1, all rows
+    RUTV_CHECK(sketch(st, seed, (uint64_t)i, mi, bi, G, mi));
+    RUTV_CHECK(gemm(st, x, true, false, bi, ni, mi, 1.0, G, mi, As + s, lda, 0.0, Y, bi));
+    RUTV_CHECK(cpqr_pivots(st, bi, ni, Y, bi, J, cw));
+    RUTV_CHECK(exchange_columns(st, m, bi, ni, J, As, lda, jpvt + s, ew));
+    double* Pn = As + s;  // the panel, rows s..m-1
+    RUTV_CHECK(panel_qr(st, mi, bi, Pn, lda, tau + s, pw));
+    if (ni > bi) {
+      RUTV_CHECK(extract_reflectors(st, mi, bi, Pn, lda, W, mi, nullptr, 0, false));
+      RUTV_CHECK(t_factor(st, x, mi, bi, W, tau + s, Z));
+      double* C = Pn + bi * lda;
+      RUTV_CHECK(gemm(st, x, true, false, bi, ni - bi, mi, 1.0, W, mi, C, lda, 0.0, X3, bi));
+      RUTV_CHECK(gemm(st, x, false, false, mi, ni - bi, bi, -1.0, Z, mi, X3, bi, 1.0, C, lda));
+    }
+    s += bi;
+  }
+  int flags[4] = {0, 0, 0, 0};
+  RUTV_TRY(hipMemcpyAsync(flags, status, sizeof(flags), hipMemcpyDeviceToHost, st));
+  RUTV_TRY(hipStreamSynchronize(st));
+  if (flags[0] || flags[1]) return RANDUTV_ERR_SYNC;
+  return RANDUTV_OK;
+}
+
 // Forward value of the first-block truncation without the rest of the
 // factorization: A_k = Q Q^T A, Q an orthonormal basis of the range of
 // M = (A A^T)^(q+1) G(0) (k = min(b, n); the identity is explained at

@@ -28,6 +28,7 @@ SIGNATURES = {
     "randutv_truncate": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _P]),
     "randutv_truncate_grad": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64, _P, _I64]),
     "randutv_truncate_first_block": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64]),
+    "randutv_hqrrp": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _U64, _P, _P]),
     "randutv_sketch": (ctypes.c_int, [_U64, _U64, _I64, _I64, _P, _I64]),
     "randutv_dgemm": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
     "randutv_gemm_f32": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
@@ -174,6 +175,23 @@ def randutv_truncate(U, T, V, k: int):
     _sync()
     _check("randutv_truncate", lib.randutv_truncate(m, n, k, _ptr(U), _ptr(T), _ptr(V), _ptr(Ak)))
     return Ak
+
+
+def randutv_hqrrp(A, b: int, seed: int = 0):
+    """Randomized blocked column-pivoted QR A P = Q R.  Returns (F, tau, jpvt):
+    F (column-major copy of A) in the dgeqp3 layout, tau (n), jpvt (n, int64)."""
+    torch = _torch()
+    lib = load()
+    A, _ = as_colmajor(A)
+    m, n = A.shape
+    F = colmajor_empty(m, n, A.device)
+    F.copy_(A)
+    tau = torch.empty(n, dtype=torch.float64, device=F.device)
+    jpvt = torch.empty(n, dtype=torch.int64, device=F.device)
+    _sync()
+    _check("randutv_hqrrp", lib.randutv_hqrrp(m, n, _ptr(F), max(1, m), b, seed & (2**64 - 1),
+                                              _ptr(tau), _ptr(jpvt)))
+    return F, tau, jpvt
 
 
 def randutv_truncate_first_block(A, b: int, q: int, seed: int = 0):

@@ -91,6 +91,15 @@ def test_argument_validation_without_device_work():
     assert fb(5, 3, P, 5, 2, 0, 0, P, 5) == -8                         # Ak aliases A
     assert fb(5, 3, P, 5, 2, 0, 0, ctypes.c_void_p(0x2000), 4) == -9
     assert fb(5, 3, P, 5, 2, -1, 0, ctypes.c_void_p(0x2000), 5) == -6
+    hq = lib.randutv_hqrrp
+    assert hq(-1, 3, P, 5, 2, 0, P, P) == -1
+    assert hq(4, 5, P, 4, 2, 0, P, P) == -2
+    assert hq(5, 3, None, 5, 2, 0, P, P) == -3
+    assert hq(5, 3, P, 4, 2, 0, P, P) == -4
+    assert hq(5, 3, P, 5, 0, 0, P, P) == -5
+    assert hq(5, 3, P, 5, 2, 0, None, P) == -7
+    assert hq(5, 3, P, 5, 2, 0, P, None) == -8
+    assert hq(600, 600, P, 600, 300, 0, P, P) == rb.ERR_TOO_LARGE
     assert lib.randutv_set_timing(3) == -1
     assert lib.randutv_set_timing(0) == 0
     g16 = lib.randutv_gemm_bf16

@@ -1,0 +1,66 @@
+"""GPU HQRRP (randutv_hqrrp) against the FP64 CPU oracle."""
+import numpy as np
+import pytest
+import scipy.linalg.lapack as lapack
+
+import paper_2002_06960_amd as pkg
+from oracle import hqrrp_oracle as ho
+from randutv_inputs import make_matrix
+from gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _q_of(F, tau):
+    """Q's first n columns from the dgeqp3 layout via LAPACK dorgqr."""
+    Q, _, info = lapack.dorgqr(np.asfortranarray(F), tau)
+    assert info == 0
+    return Q
+
+
+@pytest.mark.parametrize("m,n,b,kind", [(500, 400, 64, "iid"), (777, 300, 50, "exp"), (300, 240, 256, "iid"),
+                                        (256, 200, 1, "iid"), (1100, 1000, 128, "log8")])
+def test_hqrrp_matches_oracle(m, n, b, kind):
+    """Pivots bit-exact (integer decisions taken on the same sketch; the GEMM's
+    rounding moves norms by ~1e-15 relative, far below the gaps between
+    candidates here), then R to 1e-11 max|A| and each column's reflector and
+    tau to 1e-11 max|A| / |R_jj|: both sides are backward stable, so the
+    data a reflector is built from carries absolute errors of order
+    u max|A|, relative u max|A| / |R_jj| (up to 1e-8 for the log8 spectrum)."""
+    A = make_matrix(kind, m, n, seed=8)
+    F, tau, jp = pkg.randutv_hqrrp(to_dev(A), b, 6)
+    Fo, tauo, jpo = ho.hqrrp(A, b, 6)
+    jp = to_host(jp)
+    assert list(jp) == list(jpo)
+    F, tau = to_host(F), to_host(tau)
+    amax = np.abs(A).max()
+    np.testing.assert_allclose(np.triu(F[:n, :]), np.triu(Fo[:n, :]), rtol=0, atol=1e-11 * amax)
+    col_tol = 1e-11 * amax / np.maximum(np.abs(np.diag(Fo)), 1e-300)
+    assert np.all(np.abs(tau - tauo) <= col_tol), np.max(np.abs(tau - tauo) / col_tol)
+    low = np.tril(F, -1) - np.tril(Fo, -1)
+    assert np.all(np.abs(low) <= col_tol[None, :]), np.max(np.abs(low) / col_tol[None, :])
+
+
+@pytest.mark.parametrize("m,n,b", [(4000, 3000, 256), (3000, 3000, 200)])
+def test_hqrrp_invariants_at_size(m, n, b):
+    """A P = Q R with Q orthonormal and R upper trapezoidal; every pivot is a
+    valid choice (checked against the oracle's pivots on the first step)."""
+    A = make_matrix("exp", m, n, seed=1)
+    F, tau, jp = pkg.randutv_hqrrp(to_dev(A), b, 3)
+    F, tau, jp = to_host(F), to_host(tau), to_host(jp)
+    assert sorted(jp) == list(range(n))
+    Q = _q_of(F, tau)
+    R = np.triu(F[:n, :])
+    assert np.linalg.norm(A[:, jp] - Q @ R) <= 1e-13 * np.linalg.norm(A)
+    assert np.abs(Q.T @ Q - np.eye(n)).max() <= 1e-13
+    G = ho.sketch_block(3, 0, m, b)
+    J0 = ho.cpqr_pivots(G.T @ A, b)
+    assert list(jp[:b]) == J0
+
+
+def test_hqrrp_errors():
+    A = np.ones((40, 30))
+    A[2, 3] = np.inf
+    with pytest.raises(pkg.RandUTVError) as e:
+        pkg.randutv_hqrrp(to_dev(A), 8, 0)
+    assert e.value.code == 3
