@@ -52,8 +52,8 @@ def parse():
     ap.add_argument("--mixed-modes", default="fp32,bf16x3,bf16",
                     help="reduced-precision sketch modes timed beside the FP64 run")
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the runs beside the FP64 headline: the reduced-precision sketches "
-                         "and the differentiable truncation")
+                    help="skip the runs beside the FP64 headline: the reduced-precision sketches, "
+                         "the differentiable truncation and HQRRP")
     ap.add_argument("--grad-batch", type=int, default=16,
                     help="matrices of the differentiable-truncation run (2048 x 2048, b=128; 0: skip)")
     ap.add_argument("--no-check", action="store_true",
@@ -249,6 +249,21 @@ def main():
               file=sys.stderr, flush=True)
         del As, Bs
 
+    # HQRRP (randomized blocked column-pivoted QR) of the same matrix, block b
+    hq = None
+    if not args.no_mixed:
+        pkg.randutv_hqrrp(A, b, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Fh, tauh, jph = pkg.randutv_hqrrp(A, b, 0)
+        torch.cuda.synchronize()
+        ms_hq = 1e3 * (time.perf_counter() - t0)
+        f_qr = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+        hq = {"workload": f"hqrrp {m}x{n} b={b}, FP64", "ms": round(ms_hq, 3),
+              "qr_flops": f_qr, "tflops_qr_count": round(f_qr / (ms_hq * 1e-3) / 1e12, 3)}
+        print(f"# hqrrp: {ms_hq:.2f} ms", file=sys.stderr, flush=True)
+        del Fh, tauh, jph
+
     roofline = None
     kern = {}
     if stats:
@@ -319,6 +334,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "truncation_grad": trunc_grad,
+        "hqrrp": hq,
         "kernels": kern,
     }
     print(json.dumps(out), flush=True)
