@@ -110,8 +110,9 @@ int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U,
  *          above the diagonal, the reflector vectors (v(0) = 1 implied) below.
  *   tau  : n reflector scalars (device).
  *   jpvt : n int64 (device): column j of A P is column jpvt[j] of A.
- * m >= n.  b > n is clamped to n.  Synchronous.  Errors: -1 m, -2 n, -3 A,
- * -4 lda, -5 b, -7 tau, -8 jpvt, RANDUTV_ERR_TOO_LARGE for min(b, n) > 256,
+ * m >= n, n <= 32768.  b > n is clamped to n.  Synchronous.  Errors: -1 m,
+ * -2 n, -3 A, -4 lda, -5 b, -7 tau, -8 jpvt, RANDUTV_ERR_TOO_LARGE for
+ * min(b, n) > 256 or n > 32768,
  * RANDUTV_ERR_NONFINITE (A untouched), RANDUTV_ERR_SYNC.
  */
 int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b,

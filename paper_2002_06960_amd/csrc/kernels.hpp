@@ -77,11 +77,12 @@ int jacobi_svd_batched(hipStream_t st, int count, i64 k, i64 k_last, const doubl
 struct CpqrWork {
   double* sval = nullptr;     // 2 * 256 per-workgroup best norms (by step parity)
   int* sidx = nullptr;        // 2 * 256 their columns
+  double* scol = nullptr;     // 2 * 256 * 256 the candidate columns (LDS variant)
   unsigned* counter = nullptr;  // grid barrier counter
   int* err = nullptr;         // device status word
 };
 struct ExchangeWork {
-  int *idx = nullptr, *where = nullptr;  // N entries each
+  int* idx = nullptr;                    // N entries
   int *chg = nullptr, *cnt = nullptr;    // 2k entries, 1
   double* tmp = nullptr;                 // m x 2k
   int64_t* jtmp = nullptr;               // 2k
@@ -91,7 +92,7 @@ struct ExchangeWork {
 // the lowest column on ties
 int cpqr_pivots(hipStream_t st, i64 k, i64 N, double* Y, i64 ldy, int* J, CpqrWork& w);
 // exchange, in A (m rows, columns 0..N-1, ld lda) and jp, the column holding
-// J[t] with column t for t = 0..k-1 in turn
+// J[t] with column t for t = 0..k-1 in turn (N <= 32768)
 int exchange_columns(hipStream_t st, i64 m, i64 k, i64 N, const int* J, double* A, i64 lda,
                      int64_t* jp, ExchangeWork& w);
 int set_iota(hipStream_t st, i64 n, int64_t* x);

@@ -611,7 +611,7 @@ int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint6
   if (!jpvt) return -8;
   if (b > n) b = n;
   if (b > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
-  if (n > INT32_MAX / 2) return RANDUTV_ERR_TOO_LARGE;
+  if (n > 32768) return RANDUTV_ERR_TOO_LARGE;  // the exchange plan's LDS index arrays
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
   RUTV_CHECK(cx.init());
@@ -642,9 +642,9 @@ int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint6
     J = c.take<int>(b);
     cw.sval = c.take<double>(2 * 256);
     cw.sidx = c.take<int>(2 * 256);
+    cw.scol = c.take<double>(2 * 256 * kPanelMaxCols);
     cw.counter = c.take<unsigned>(1);
     ew.idx = c.take<int>(n);
-    ew.where = c.take<int>(n);
     ew.chg = c.take<int>(2 * b);
     ew.cnt = c.take<int>(1);
     ew.tmp = c.take<double>(m * 2 * b);

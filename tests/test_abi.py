@@ -100,6 +100,7 @@ def test_argument_validation_without_device_work():
     assert hq(5, 3, P, 5, 2, 0, None, P) == -7
     assert hq(5, 3, P, 5, 2, 0, P, None) == -8
     assert hq(600, 600, P, 600, 300, 0, P, P) == rb.ERR_TOO_LARGE
+    assert hq(40000, 40000, P, 40000, 64, 0, P, P) == rb.ERR_TOO_LARGE    # n > 32768
     assert lib.randutv_set_timing(3) == -1
     assert lib.randutv_set_timing(0) == 0
     g16 = lib.randutv_gemm_bf16

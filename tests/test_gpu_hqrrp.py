@@ -58,6 +58,21 @@ def test_hqrrp_invariants_at_size(m, n, b):
     assert list(jp[:b]) == J0
 
 
+def test_hqrrp_pivot_kernel_without_lds_slab():
+    """n = 16640 with b = 256: the first step's 65 columns per workgroup do not
+    fit in LDS, so the pivot kernel works on Y in global memory; its pivots
+    equal the oracle's CPQR of the same sketch."""
+    m = n = 16640
+    b = 256
+    A = np.random.default_rng(12).standard_normal((m, n))
+    F, tau, jp = pkg.randutv_hqrrp(to_dev(A), b, 2)
+    jp = to_host(jp)
+    assert sorted(jp) == list(range(n))
+    G = ho.sketch_block(2, 0, m, b)
+    assert list(jp[:b]) == ho.cpqr_pivots(G.T @ A, b)
+    del F, tau
+
+
 def test_hqrrp_errors():
     A = np.ones((40, 30))
     A[2, 3] = np.inf
