@@ -144,7 +144,8 @@ int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t 
  * All device pointers, column-major FP64; the call is synchronous.  The
  * sketch and power products are recomputed (nothing is kept from the
  * forward call).  Errors: -1 m, -2 n (n < 0 or n > m), -3 A, -4 lda, -5 b,
- * -6 q, -8 Gbar, -9 ldg, -10 Abar (NULL or aliasing), -11 ldab,
+ * -6 q (q < 0 or q > 64: every power-iteration product is kept), -8 Gbar,
+ * -9 ldg, -10 Abar (NULL or aliasing), -11 ldab,
  * RANDUTV_ERR_TOO_LARGE for min(b, n) > 256, RANDUTV_ERR_NONFINITE for NaN/Inf
  * in A or Gbar, RANDUTV_ERR_RANK when M has a zero pivot (the projector is
  * not differentiable there).

@@ -22,6 +22,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "kernels.hpp"
@@ -519,6 +520,19 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
   return RANDUTV_OK;
 }
 
+// host-side allocation failures (std::vector and the like) must not cross the
+// C ABI as C++ exceptions
+template <class F>
+static int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return RANDUTV_ERR_NOMEM;
+  } catch (...) {
+    return RANDUTV_ERR_HIP;
+  }
+}
+
 }  // namespace rutv
 
 using namespace rutv;
@@ -554,7 +568,7 @@ int randutv_factor_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_
   if (std::min(b, n) > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
-  return factor_impl(m, n, A, lda, b, q, seed, U, T, V, prec);
+  return guarded([&] { return factor_impl(m, n, A, lda, b, q, seed, U, T, V, prec); });
 }
 
 int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const double* T,
@@ -778,6 +792,8 @@ int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t 
   return RANDUTV_OK;
 }
 
+constexpr int32_t kGradMaxQ = 64;
+
 // Reverse pass of the first-block truncation A_k = U_k U_k^T A, k = min(b, n)
 // (T(0:k, :) V^T = U_k^T A since T = U^T A V).  Step 0 of the method makes
 // range(U_k) = range(M), M = (A A^T)^(q+1) G(0) (Section 3.1: the sketch and
@@ -789,16 +805,16 @@ int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t 
 //   dL/dA = P Gbar + [chain of M] applied to Mbar = (I - P)(W + W^T) Q R^{-T}.
 // The chain M_{j+1} = A (A^T M_j), M_0 = G(0), is recomputed and reversed:
 //   Abar += Mbar_{j+1} Z_j^T + M_j (A^T Mbar_{j+1})^T,  Mbar_j = A A^T Mbar_{j+1}.
-int randutv_truncate_grad(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
-                          int32_t q, uint64_t seed, const double* Gbar, int64_t ldg,
-                          double* Abar, int64_t ldab) {
+static int truncate_grad_impl(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                              int32_t q, uint64_t seed, const double* Gbar, int64_t ldg,
+                              double* Abar, int64_t ldab) {
   if (m < 0) return -1;
   if (n < 0 || n > m) return -2;
   if (m == 0 || n == 0) return RANDUTV_OK;
   if (!A) return -3;
   if (lda < std::max<int64_t>(1, m)) return -4;
   if (b < 1) return -5;
-  if (q < 0) return -6;
+  if (q < 0 || q > kGradMaxQ) return -6;  // the reverse pass keeps every power-iteration product
   if (!Gbar) return -8;
   if (ldg < std::max<int64_t>(1, m)) return -9;
   if (!Abar || Abar == A || Abar == Gbar) return -10;
@@ -903,6 +919,12 @@ int randutv_truncate_grad(int64_t m, int64_t n, const double* A, int64_t lda, in
   if (flags[1]) return RANDUTV_ERR_SYNC;
   if (flags[2]) return RANDUTV_ERR_RANK;
   return RANDUTV_OK;
+}
+
+int randutv_truncate_grad(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                          int32_t q, uint64_t seed, const double* Gbar, int64_t ldg,
+                          double* Abar, int64_t ldab) {
+  return guarded([&] { return truncate_grad_impl(m, n, A, lda, b, q, seed, Gbar, ldg, Abar, ldab); });
 }
 
 int randutv_sketch(uint64_t seed, uint64_t step, int64_t rows, int64_t cols, double* G,

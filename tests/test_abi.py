@@ -79,6 +79,7 @@ def test_argument_validation_without_device_work():
     assert tg_(5, 3, P, 4, 2, 0, 0, P, 5, P, 5) == -4
     assert tg_(5, 3, P, 5, 0, 0, 0, P, 5, P, 5) == -5
     assert tg_(5, 3, P, 5, 2, -1, 0, P, 5, P, 5) == -6
+    assert tg_(5, 3, P, 5, 2, 65, 0, P, 5, P, 5) == -6                 # q above the kept products
     assert tg_(5, 3, P, 5, 2, 0, 0, None, 5, P, 5) == -8
     assert tg_(5, 3, P, 5, 2, 0, 0, P, 4, ctypes.c_void_p(0x2000), 5) == -9
     assert tg_(5, 3, P, 5, 2, 0, 0, ctypes.c_void_p(0x2000), 5, P, 5) == -10   # Abar aliases A
