@@ -15,7 +15,7 @@ constexpr int kCpMaxWG = 256;
 constexpr int kCpMaxCols = 1024;  // columns owned by one workgroup
 constexpr int kCpMinCols = 32;
 
-int cpqr_grid(i64 N) { return (int)std::min<i64>(kCpMaxWG, std::max<i64>(1, cdiv(N, kCpMinCols))); }
+static int cpqr_grid(i64 N) { return (int)std::min<i64>(kCpMaxWG, std::max<i64>(1, cdiv(N, kCpMinCols))); }
 
 // (value, column) order of the pivot search: larger residual norm first, the
 // lower column index on equal norms
