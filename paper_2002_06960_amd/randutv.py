@@ -235,11 +235,13 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, A, b, q, seed, first_step_only):
-            if first_step_only:
-                Ak = randutv_truncate_first_block(A, b, q, seed)
-            else:
-                U, T, V = randutv_factor(A, b, q, seed)
-                Ak = randutv_truncate(U, T, V, min(b, A.shape[1]))
+            def one(X):
+                if first_step_only:
+                    return randutv_truncate_first_block(X, b, q, seed)
+                U, T, V = randutv_factor(X, b, q, seed)
+                return randutv_truncate(U, T, V, min(b, X.shape[1]))
+
+            Ak = torch.stack([one(X) for X in A]) if A.dim() == 3 else one(A)
             ctx.save_for_backward(A)
             ctx.b, ctx.q, ctx.seed = b, q, seed
             return Ak
@@ -247,7 +249,11 @@ def _autograd_function():
         @staticmethod
         def backward(ctx, gout):
             (A,) = ctx.saved_tensors
-            return randutv_truncate_grad(A, ctx.b, ctx.q, ctx.seed, gout), None, None, None, None
+            if A.dim() == 3:
+                g = torch.stack([randutv_truncate_grad(X, ctx.b, ctx.q, ctx.seed, G) for X, G in zip(A, gout)])
+            else:
+                g = randutv_truncate_grad(A, ctx.b, ctx.q, ctx.seed, gout)
+            return g, None, None, None, None
 
     return FirstBlockTruncation
 
@@ -260,7 +266,8 @@ def first_block_truncation(A, b: int, q: int, seed: int = 0, first_step_only: bo
     sketch G(0) held fixed: returns A_k = U_k T_k V^T as a tensor that
     torch.autograd differentiates through randutv_truncate_grad.  With
     first_step_only the forward value comes from the first step alone
-    (the same A_k without factoring the rest of A)."""
+    (the same A_k without factoring the rest of A).  A may be a batch
+    (batch x m x n): each matrix is factored with the same (b, q, seed)."""
     global _first_block_fn
     if _first_block_fn is None:
         _first_block_fn = _autograd_function()

@@ -118,3 +118,20 @@ def test_first_step_forward(m, n, b, q, kind):
     # the autograd binding's two forward forms give the same value
     Ak = pkg.first_block_truncation(Ad, b, q, 2, first_step_only=True)
     assert np.abs(to_host(Ak) - got).max() == 0.0
+
+
+def test_autograd_batch():
+    """A batch (3 x m x n) gives, matrix by matrix, the single-matrix values
+    and gradients."""
+    m, n, b, q = 256, 200, 32, 1
+    As = np.stack([make_matrix("exp98", m, n, seed=20 + i) for i in range(3)])
+    Bs = np.random.default_rng(9).standard_normal((3, m, n))
+    X = torch.from_numpy(As).to("cuda").requires_grad_(True)
+    Ak = pkg.first_block_truncation(X, b, q, 1)
+    ((Ak - torch.from_numpy(Bs).to("cuda")) ** 2).sum().backward()
+    for i in range(3):
+        Y = to_dev(As[i]).requires_grad_(True)
+        Aki = pkg.first_block_truncation(Y, b, q, 1)
+        ((Aki - to_dev(Bs[i])) ** 2).sum().backward()
+        assert np.array_equal(to_host(Ak[i].detach()), to_host(Aki.detach()))
+        np.testing.assert_allclose(to_host(X.grad[i]), to_host(Y.grad), rtol=0, atol=1e-13 * np.abs(to_host(Y.grad)).max())
