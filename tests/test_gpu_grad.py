@@ -135,3 +135,20 @@ def test_autograd_batch():
         ((Aki - to_dev(Bs[i])) ** 2).sum().backward()
         assert np.array_equal(to_host(Ak[i].detach()), to_host(Aki.detach()))
         np.testing.assert_allclose(to_host(X.grad[i]), to_host(Y.grad), rtol=0, atol=1e-13 * np.abs(to_host(Y.grad)).max())
+
+
+def test_grad_padded_leading_dimensions():
+    """A and Gbar as column-major views with leading dimensions above m."""
+    m, n, b, q = 300, 240, 32, 2
+    A = make_matrix("exp", m, n, seed=11)
+    Gbar = np.random.default_rng(3).standard_normal((m, n))
+    Abuf = torch.zeros((n, m + 9), dtype=torch.float64, device="cuda")
+    Gbuf = torch.zeros((n, m + 5), dtype=torch.float64, device="cuda")
+    Av = Abuf.t()[:m, :]
+    Gv = Gbuf.t()[:m, :]
+    Av.copy_(to_dev(A))
+    Gv.copy_(to_dev(Gbar))
+    assert Av.stride() == (1, m + 9) and Gv.stride() == (1, m + 5)
+    got = to_host(pkg.randutv_truncate_grad(Av, b, q, 2, Gv))
+    ref = tg.first_block_truncation_grad(A, b, q, 2, Gbar)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()

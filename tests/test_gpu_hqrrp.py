@@ -79,3 +79,28 @@ def test_hqrrp_errors():
     with pytest.raises(pkg.RandUTVError) as e:
         pkg.randutv_hqrrp(to_dev(A), 8, 0)
     assert e.value.code == 3
+
+
+def test_hqrrp_padded_leading_dimension():
+    """lda > m through the C ABI: the exchanges, the panel and the update all
+    address A through lda; the padding rows stay untouched."""
+    import ctypes
+    import torch
+
+    m, n, b, lda = 300, 220, 40, 311
+    A = make_matrix("iid", m, n, seed=5)
+    buf = torch.full((n, lda), 7.0, dtype=torch.float64, device="cuda")  # column-major with ld = lda
+    buf.t()[:m, :] = to_dev(A)
+    tau = torch.empty(n, dtype=torch.float64, device="cuda")
+    jp = torch.empty(n, dtype=torch.int64, device="cuda")
+    lib = pkg.load()
+    torch.cuda.synchronize()
+    rc = lib.randutv_hqrrp(m, n, ctypes.c_void_p(buf.data_ptr()), lda, b, 4,
+                           ctypes.c_void_p(tau.data_ptr()), ctypes.c_void_p(jp.data_ptr()))
+    assert rc == 0
+    F = to_host(buf.t()[:m, :])
+    assert np.all(to_host(buf.t()[m:, :]) == 7.0)
+    Fo, tauo, jpo = ho.hqrrp(A, b, 4)
+    assert list(to_host(jp)) == list(jpo)
+    np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-11 * np.abs(A).max())
+    np.testing.assert_allclose(to_host(tau), tauo, rtol=0, atol=1e-12)
