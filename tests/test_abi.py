@@ -35,6 +35,9 @@ def test_strerror_codes():
     assert "converge" in pkg.randutv_strerror(4)
     assert "invalid" in pkg.randutv_strerror(-3)
     assert pkg.randutv_strerror(1).startswith("HIP")
+    assert "rank deficient" in pkg.randutv_strerror(rb.ERR_RANK)
+    for code in range(1, rb.ERR_RANK + 1):  # every positive code has its own message
+        assert pkg.randutv_strerror(code) != "unknown error"
 
 
 def test_argument_validation_without_device_work():
