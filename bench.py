@@ -6,17 +6,25 @@ One step = one full randUTV factorization A = U T V^T (U and V built) of the
 q = 2 power steps, sketch seed 0 -- every block step of the method (sketch,
 power iteration, QR of the sketch, right transform of all rows and of V, panel
 QR, left transform, U update, b x b SVDs and their applications) runs inside
-the timed region; A, U, T, V are resident in HBM before it starts.
+the timed region; A, U, T, V are resident in HBM before it starts, and nothing
+but the factorizations runs inside it (no event records).
 
 value = F_std / t in TFLOP/s, with the leading-order count
 F_std = (1+2q)(m n^2 - n^3/3) + 2 m n^2 + 4/3 n^3 + 4 m^2 n  (1.843e13 here).
+
 The roofline entry is the dominant kernel, the FP64 matrix-core GEMM (all its
-operand layouts): algorithmic flops per launch over its average launch time,
-from HIP events recorded on the launching stream around every launch in the
-timed steps, against the FP64 matrix-core peak (78.6 TFLOP/s); traffic is the
-HBM bytes per launch from committed rocprofv3 counters when they were taken on
-the current kernel source.  cpu_baseline
-times the FP64 CPU oracle on the first block steps of the same problem.
+operand layouts): its algorithmic flops per launch over its average launch
+duration, from HIP events recorded on the launching stream around every GEMM
+launch of one more factorization in which each GEMM launch runs alone on the
+chip (the library waits for all queued work before it), so that the duration
+is the kernel's own and not a share of a chip that the other streams' kernels
+occupy as well.  The same figure with the streams overlapping, as they do in
+the timed steps, is reported as roofline.in_place.  The roofline is refused
+(null, with the reason) when the GEMM launches of one factorization, run
+alone, take longer in total than a timed step.  traffic is the HBM bytes per
+launch from committed rocprofv3 counters when they were taken on the current
+kernel source.  cpu_baseline times the FP64 CPU oracle on the first block
+steps of the same problem.
 """
 from __future__ import annotations
 
@@ -45,14 +53,18 @@ def parse():
     ap.add_argument("--spectrum", default="exp")
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="block steps of the same problem timed for the CPU oracle baseline (0: skip)")
-    ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--all-classes-timed", action="store_true",
-                    help="time every kernel class inside the timed region (default: the GEMM "
-                         "launches there, the other classes in one more factorization after it)")
-    ap.add_argument("--mixed-modes", default="fp32,bf16x3,bf16",
-                    help="reduced-precision sketch modes timed beside the FP64 run")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="skip the factorizations after the timed region that time the kernels")
+    ap.add_argument("--roofline-pass-only", action="store_true",
+                    help="run only the warmup and the factorization whose GEMM launches run alone "
+                         "(for a profiler run that measures the same launches)")
+    ap.add_argument("--mixed-modes", default="sk32,sk48,sk16,sk32_up32,sk48_up32",
+                    help="reduced-precision modes timed beside the FP64 run: skNN = sketch products "
+                         "in NN bits (32 FP32, 48 split BF16 x3, 16 BF16), upNN = compact-WY updates too")
+    ap.add_argument("--mixed-sizes", default="12000,16000",
+                    help="square sizes of the mixed-precision comparison (FP64 and each mode)")
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the runs beside the FP64 headline: the reduced-precision sketches, "
+                    help="skip the runs beside the FP64 headline: the reduced-precision modes, "
                          "the differentiable truncation and HQRRP")
     ap.add_argument("--grad-batch", type=int, default=16,
                     help="matrices of the differentiable-truncation run (2048 x 2048, b=128; 0: skip)")
@@ -62,6 +74,12 @@ def parse():
                     help="before the factorizations, run one plain device copy of this many MiB "
                          "(a kernel of known HBM traffic, to scale hardware byte counters)")
     return ap.parse_args()
+
+
+MODES = {"sk32": (32, 64), "sk48": (48, 64), "sk16": (16, 64), "sk32_up32": (32, 32),
+         "sk48_up32": (48, 32), "sk32_up48": (32, 48)}
+MODE_TEXT = {32: "fp32 matrix cores", 48: "bf16 matrix cores, split operands hi*hi + hi*lo + lo*hi",
+             16: "bf16 matrix cores", 64: "fp64 matrix cores"}
 
 
 def traffic_entry(kernel: str):
@@ -84,13 +102,33 @@ def traffic_entry(kernel: str):
         return None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def gemm_totals(stats):
+    gemm = [k for k in stats if k.startswith("dgemm_") and stats[k][0]]
+    return (sum(stats[k][0] for k in gemm), sum(stats[k][1] for k in gemm),
+            sum(stats[k][2] for k in gemm))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the factorization has "
                                    "no multi-GPU path (use --gpus 1)"}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_2002_06960_amd as pkg
@@ -112,48 +150,69 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"# copy calibration: {nel * 8} bytes read, {nel * 8} bytes written", file=sys.stderr)
+        log(f"# copy calibration: {nel * 8} bytes read, {nel * 8} bytes written")
         del src, dst
     torch.cuda.synchronize()
-    print(f"# workload randutv fp64 {m}x{n} b={b} q={q} spectrum={args.spectrum}", file=sys.stderr, flush=True)
+    log(f"# workload randutv fp64 {m}x{n} b={b} q={q} spectrum={args.spectrum}")
+
+    def factor(**kw):
+        pkg.randutv_factor(A, b, q, 0, U=U, T=T, V=V, **kw)
 
     for w in range(args.warmup):
         t0 = time.perf_counter()
-        pkg.randutv_factor(A, b, q, 0, U=U, T=T, V=V)
+        factor()
         torch.cuda.synchronize()
-        print(f"# warmup {w}: {time.perf_counter() - t0:.3f} s", file=sys.stderr, flush=True)
+        log(f"# warmup {w}: {time.perf_counter() - t0:.3f} s")
 
-    # HIP events around every GEMM launch of the timed factorizations (on the
-    # stream it is launched on) give the dominant kernel's average duration;
-    # the other kernel classes are timed in one more factorization after the
-    # timed region (all classes timed at once cost ~2% of the step time)
-    timing = not args.no_kernel_timing
-    pkg.randutv_set_timing(timing, gemm_only=not args.all_classes_timed)
+    if args.roofline_pass_only:
+        pkg.randutv_set_timing(True, serialize_gemm=True)
+        factor()
+        torch.cuda.synchronize()
+        st = pkg.randutv_kernel_stats()
+        pkg.randutv_set_timing(False)
+        la, ms, fl = gemm_totals(st)
+        log(f"# GEMM launches run alone: {la} launches, {ms:.3f} ms, {ms / la:.4f} ms per launch, "
+            f"{fl / (ms * 1e-3) / 1e12:.3f} TFLOP/s")
+        return
+
+    # ---- timed region: the factorizations alone
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        pkg.randutv_factor(A, b, q, 0, U=U, T=T, V=V)
+        factor()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    stats = pkg.randutv_kernel_stats() if timing else {}
-    pkg.randutv_set_timing(False)
-    cls_stats, cls_steps = stats, args.steps
-    if timing and not args.all_classes_timed:
-        pkg.randutv_set_timing(True)
-        pkg.randutv_factor(A, b, q, 0, U=U, T=T, V=V)
-        torch.cuda.synchronize()
-        cls_stats, cls_steps = pkg.randutv_kernel_stats(), 1
-        pkg.randutv_set_timing(False)
     ms_step = 1e3 * elapsed / max(args.steps, 1)
-    print(f"# timed {args.steps} steps: {ms_step:.2f} ms/step", file=sys.stderr, flush=True)
+    log(f"# timed {args.steps} steps: {ms_step:.2f} ms/step")
+
+    # ---- kernel timing, after the timed region: (1) HIP events around every
+    # GEMM launch with the streams overlapping as in the timed steps; (2) every
+    # GEMM launch alone on the chip; (3) every kernel class (per-class table)
+    stats_inplace = stats_alone = cls_stats = {}
+    if not args.no_kernel_timing:
+        pkg.randutv_set_timing(True, gemm_only=True)
+        factor()
+        torch.cuda.synchronize()
+        stats_inplace = pkg.randutv_kernel_stats()
+        pkg.randutv_set_timing(True, serialize_gemm=True)
+        t1 = time.perf_counter()
+        factor()
+        torch.cuda.synchronize()
+        log(f"# factorization with every GEMM launch alone: {time.perf_counter() - t1:.3f} s")
+        stats_alone = pkg.randutv_kernel_stats()
+        pkg.randutv_set_timing(True)
+        factor()
+        torch.cuda.synchronize()
+        cls_stats = pkg.randutv_kernel_stats()
+        pkg.randutv_set_timing(False)
 
     F = pkg.flops_std(m, n, q)
     value = F / (ms_step * 1e-3) / 1e12
 
     # correctness of the timed output
     res = orth_u = orth_v = None
+    nA = torch.linalg.norm(A)
     if not args.no_check:
-        nA = torch.linalg.norm(A)
         res = (torch.linalg.norm(A - U @ T @ V.T) / nA).item()
         eye_m = torch.eye(m, dtype=torch.float64, device=dev)
         orth_u = (U.T @ U - eye_m).abs().max().item()
@@ -162,92 +221,19 @@ def main():
         orth_v = (V.T @ V - eye_n).abs().max().item()
         del eye_n
 
-    # the same factorization with the sketch and power-iteration products in
-    # reduced precision (every transform of T, U, V still FP64): FP32 matrix
-    # cores, three BF16 products of split operands, one BF16 product
+    # ---- the same factorization in reduced-precision modes, at the headline
+    # size and at 16000 x 16000: errors against the FP64 factorization of the
+    # same matrix (which the GPU tests pin to the FP64 oracle)
     mixed = None
     if not args.no_mixed:
         mixed = {}
-        U2 = pkg.colmajor_empty(m, m, dev)
-        T2 = pkg.colmajor_empty(m, n, dev)
-        V2 = pkg.colmajor_empty(n, n, dev)
-        modes = {"fp32": (32, "fp32 matrix cores (FP64 storage); all transforms FP64"),
-                 "bf16x3": (48, "bf16 matrix cores, operands split x = hi + lo, hi*hi + hi*lo + lo*hi, "
-                                "fp32 accumulation (FP64 storage); all transforms FP64"),
-                 "bf16": (16, "bf16 matrix cores, operands rounded to bf16, fp32 accumulation "
-                              "(FP64 storage); all transforms FP64")}
-        for name in args.mixed_modes.split(","):
-            bits, what = modes[name]
-            pkg.randutv_factor(A, b, q, 0, U=U2, T=T2, V=V2, sketch_bits=bits)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(args.steps):
-                pkg.randutv_factor(A, b, q, 0, U=U2, T=T2, V=V2, sketch_bits=bits)
-            torch.cuda.synchronize()
-            ms_mixed = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
-            print(f"# {name}-sketch: {ms_mixed:.2f} ms/step", file=sys.stderr, flush=True)
-            rec = {"sketch": what, "ms_per_step": round(ms_mixed, 3),
-                   "value": round(F / (ms_mixed * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
-                   "frac_of_fp64_peak": round(F / (ms_mixed * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
-            if not args.no_check:
-                nA = torch.linalg.norm(A)
-                rec["residual"] = (torch.linalg.norm(A - U2 @ T2 @ V2.T) / nA).item()
-                ranks = {}
-                for k in (kk for kk in (64, 256, 1024) if kk <= n):
-                    Ak = pkg.randutv_truncate(U, T, V, k)
-                    Ak2 = pkg.randutv_truncate(U2, T2, V2, k)
-                    ranks[str(k)] = {"fp64_trunc_err": (torch.linalg.norm(A - Ak) / nA).item(),
-                                     "mixed_trunc_err": (torch.linalg.norm(A - Ak2) / nA).item(),
-                                     "mixed_vs_fp64": (torch.linalg.norm(Ak2 - Ak) / nA).item()}
-                    del Ak, Ak2
-                rec["rank_k"] = ranks
-                rec["T_vs_fp64"] = (torch.linalg.norm(T2 - T) / nA).item()
-            mixed[name] = rec
-        del U2, T2, V2
+        for size in [int(x) for x in args.mixed_sizes.split(",") if x]:
+            mixed[f"{size}x{size}"] = mixed_block(pkg, torch, size, b, q, args, dev,
+                                                  (A, U, T, V, ms_step) if (size == m == n) else None)
 
-    # differentiable first-block truncation: a batch of 2048 x 2048 matrices
-    # (s_i = 0.98^i), b = 128, q = 2, k = 128; loss ||A_k - B||_F^2 for a
-    # seeded Gaussian B; forward (randutv_factor + randutv_truncate) and
-    # reverse pass (randutv_truncate_grad) timed separately
     trunc_grad = None
     if args.grad_batch > 0 and not args.no_mixed:
-        gm, gb, gq = 2048, 128, 2
-        gen = torch.Generator(device=dev)
-        gen.manual_seed(77)
-        As = [make_matrix_device("exp98", gm, gm, seed=100 + i, device=dev) for i in range(args.grad_batch)]
-        Bs = [torch.randn(gm, gm, dtype=torch.float64, device=dev, generator=gen) for _ in As]
-
-        def fwd_bwd(Ai, Bi, first_step_only=False):
-            X = Ai.detach().requires_grad_(True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            Ak = pkg.first_block_truncation(X, gb, gq, 0, first_step_only=first_step_only)
-            loss = ((Ak - Bi) ** 2).sum()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            loss.backward()
-            torch.cuda.synchronize()
-            return t1 - t0, time.perf_counter() - t1
-
-        fwd_bwd(As[0], Bs[0])
-        tf = tb = 0.0
-        for Ai, Bi in zip(As, Bs):
-            a, c = fwd_bwd(Ai, Bi)
-            tf += a
-            tb += c
-        tf1 = 0.0
-        for Ai, Bi in zip(As, Bs):
-            tf1 += fwd_bwd(Ai, Bi, first_step_only=True)[0]
-        trunc_grad = {"workload": f"{args.grad_batch} x {gm}x{gm}, s_i = 0.98^i, b={gb}, q={gq}, k={gb}, FP64, "
-                                  "loss ||A_k - B||_F^2",
-                      "ms_forward_per_matrix": round(1e3 * tf / len(As), 3),
-                      "ms_forward_first_step_per_matrix": round(1e3 * tf1 / len(As), 3),
-                      "ms_backward_per_matrix": round(1e3 * tb / len(As), 3),
-                      "ms_batch": round(1e3 * (tf + tb), 3)}
-        print(f"# truncation grad batch: forward {1e3 * tf / len(As):.2f} ms (first step only "
-              f"{1e3 * tf1 / len(As):.2f} ms), backward {1e3 * tb / len(As):.2f} ms per matrix",
-              file=sys.stderr, flush=True)
-        del As, Bs
+        trunc_grad = truncation_grad_block(pkg, torch, args, dev)
 
     # HQRRP (randomized blocked column-pivoted QR) of the same matrix, block b
     hq = None
@@ -261,36 +247,46 @@ def main():
         f_qr = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
         hq = {"workload": f"hqrrp {m}x{n} b={b}, FP64", "ms": round(ms_hq, 3),
               "qr_flops": f_qr, "tflops_qr_count": round(f_qr / (ms_hq * 1e-3) / 1e12, 3)}
-        print(f"# hqrrp: {ms_hq:.2f} ms", file=sys.stderr, flush=True)
+        log(f"# hqrrp: {ms_hq:.2f} ms")
         del Fh, tauh, jph
 
     roofline = None
+    refused = None
     kern = {}
-    if stats:
+    if stats_alone:
         for name, (launches, ms, fl) in cls_stats.items():
             if launches:
-                kern[name] = {"launches": launches // cls_steps, "ms_per_step": ms / cls_steps,
+                kern[name] = {"launches": launches, "ms_per_step": ms,
                               "tflops": (fl / (ms * 1e-3) / 1e12) if ms > 0 and fl > 0 else None}
-        # the dominant kernel: the FP64 matrix-core GEMM (one HIP kernel,
-        # instantiated per operand layout; its classes together take most of
-        # the device time)
-        gemm = [k for k in stats if k.startswith("dgemm_") and stats[k][0]]
-        launches = sum(stats[k][0] for k in gemm)
-        ms = sum(stats[k][1] for k in gemm)
-        fl = sum(stats[k][2] for k in gemm)
-        achieved = fl / (ms * 1e-3) / 1e12
-        tb = traffic_entry("dgemm_mfma_kernel")
-        roofline = {"bound": "mfma", "kernel": "dgemm_mfma_kernel", "achieved": round(achieved, 3),
-                    "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                    "traffic": tb, "avg_launch_ms": ms / launches, "launches": launches,
-                    "flops_per_launch": fl / launches,
-                    "device_ms_share": round(sum(cls_stats[k][1] for k in gemm if k in cls_stats)
-                                             / sum(v[1] for v in cls_stats.values()), 4)}
-        print("# kernel classes (ms/step, launches/step, TFLOP/s):", file=sys.stderr)
+        la, ms_alone, fl = gemm_totals(stats_alone)
+        li, ms_in, fli = gemm_totals(stats_inplace)
+        achieved = fl / (ms_alone * 1e-3) / 1e12
+        if ms_alone > ms_step:
+            refused = (f"the GEMM launches of one factorization take {ms_alone:.1f} ms run alone, "
+                       f"more than the {ms_step:.1f} ms step")
+        else:
+            roofline = {"bound": "mfma", "kernel": "dgemm_mfma_kernel", "achieved": round(achieved, 3),
+                        "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                        "traffic": traffic_entry("dgemm_mfma_kernel"),
+                        "avg_launch_ms": ms_alone / la, "launches": la, "flops_per_launch": fl / la,
+                        "timing": "every GEMM launch of one factorization run alone (HIP events on "
+                                  "the launching stream)",
+                        "gemm_ms_alone_per_step": round(ms_alone, 3),
+                        "in_place": {"achieved": round(fli / (ms_in * 1e-3) / 1e12, 3),
+                                     "avg_launch_ms": ms_in / li,
+                                     "timing": "HIP events around the same launches with the four "
+                                               "streams overlapping as in the timed steps"},
+                        "device_ms_share": round(sum(cls_stats[k][1] for k in cls_stats
+                                                     if k.startswith("dgemm_"))
+                                                 / max(1e-9, sum(v[1] for v in cls_stats.values())), 4)}
+        log(f"# GEMM alone: {la} launches {ms_alone:.1f} ms ({achieved:.2f} TFLOP/s); in place "
+            f"{ms_in:.1f} ms")
+        log("# kernel classes (ms/step, launches/step, TFLOP/s):")
         for name, kv in sorted(kern.items(), key=lambda x: -x[1]["ms_per_step"]):
-            print(f"#   {name:20s} {kv['ms_per_step']:9.3f} {kv['launches']:6d} {kv['tflops']}",
-                  file=sys.stderr)
+            log(f"#   {name:20s} {kv['ms_per_step']:9.3f} {kv['launches']:6d} {kv['tflops']}")
+        if refused:
+            log(f"# roofline refused: {refused}")
 
     cpu = None
     if args.cpu_steps > 0:
@@ -304,10 +300,10 @@ def main():
         fe = ro.flops_exact(m, n, b, q, max_steps=args.cpu_steps)
         scale = F / ro.flops_exact(m, n, b, q)  # express in F_std units
         cpu = {"value": round(fe * scale / tc / 1e12, 5), "unit": "TFLOP/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"first {args.cpu_steps} of {-(-n // b)} block steps of the same "
                          f"{m}x{n} b={b} q={q} factorization (U, V built), {tc:.1f} s"}
-        print(f"# cpu oracle: {tc:.1f} s for {args.cpu_steps} steps", file=sys.stderr)
+        log(f"# cpu oracle: {tc:.1f} s for {args.cpu_steps} steps")
 
     out = {
         "metric": "randUTV TFLOP/s (FP64, standard flop count) at n=12000",
@@ -331,6 +327,7 @@ def main():
         "orth_v": orth_v,
         "flops_std": F,
         "roofline": roofline,
+        "roofline_refused": refused,
         "cpu_baseline": cpu,
         "mixed": mixed,
         "truncation_grad": trunc_grad,
@@ -338,6 +335,134 @@ def main():
         "kernels": kern,
     }
     print(json.dumps(out), flush=True)
+
+
+def _aligned_col_err(X, Y, k):
+    """||X(:, :k) S - Y(:, :k)||_F / sqrt(k), S the column signs that align X with Y."""
+    import torch
+    s = torch.sign((X[:, :k] * Y[:, :k]).sum(0))
+    s[s == 0] = 1.0
+    return (torch.linalg.norm(X[:, :k] * s[None, :] - Y[:, :k]) / k ** 0.5).item()
+
+
+def mixed_block(pkg, torch, size, b, q, args, dev, reuse):
+    """FP64 and each reduced-precision mode on the size x size exp matrix:
+    time per factorization, F_std rate, residual, orthogonality, and errors
+    against the FP64 factorization: T, the leading 1024 columns of U and V
+    (sign-aligned), and the rank-k truncations for k in {64, 256, 1024}."""
+    from randutv_inputs import make_matrix_device
+
+    F = pkg.flops_std(size, size, q)
+    if reuse is not None:
+        A, U, T, V, ms64 = reuse
+    else:
+        A = make_matrix_device("exp", size, size, seed=0, device=dev)
+        U = pkg.colmajor_empty(size, size, dev)
+        T = pkg.colmajor_empty(size, size, dev)
+        V = pkg.colmajor_empty(size, size, dev)
+        pkg.randutv_factor(A, b, q, 0, U=U, T=T, V=V)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pkg.randutv_factor(A, b, q, 0, U=U, T=T, V=V)
+        torch.cuda.synchronize()
+        ms64 = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
+    nA = torch.linalg.norm(A)
+    ks = [k for k in (64, 256, 1024) if k <= size]
+    ref_err = {}
+    for k in ks:
+        Ak = pkg.randutv_truncate(U, T, V, k)
+        ref_err[k] = (Ak, (torch.linalg.norm(A - Ak) / nA).item())
+    block = {"workload": f"randutv {size}x{size} b={b} q={q} exp", "fp64": {
+        "ms_per_step": round(ms64, 3), "value": round(F / (ms64 * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+        "frac_of_fp64_peak": round(F / (ms64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+        "rank_k_trunc_err": {str(k): ref_err[k][1] for k in ks}}}
+    log(f"# mixed {size}x{size}: fp64 {ms64:.2f} ms/step")
+    U2 = pkg.colmajor_empty(size, size, dev)
+    T2 = pkg.colmajor_empty(size, size, dev)
+    V2 = pkg.colmajor_empty(size, size, dev)
+    eye = torch.eye(size, dtype=torch.float64, device=dev)
+    for name in [x for x in args.mixed_modes.split(",") if x]:
+        sk, up = MODES[name]
+        kw = dict(U=U2, T=T2, V=V2, sketch_bits=sk, update_bits=up)
+        pkg.randutv_factor(A, b, q, 0, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pkg.randutv_factor(A, b, q, 0, **kw)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
+        rec = {"sketch": MODE_TEXT[sk], "updates": MODE_TEXT[up], "ms_per_step": round(ms, 3),
+               "value": round(F / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+               "frac_of_fp64_peak": round(F / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+               "speedup_vs_fp64": round(ms64 / ms, 4)}
+        if not args.no_check:
+            rec["residual"] = (torch.linalg.norm(A - U2 @ T2 @ V2.T) / nA).item()
+            rec["orth_u"] = (U2.T @ U2 - eye).abs().max().item()
+            rec["orth_v"] = (V2.T @ V2 - eye).abs().max().item()
+            ranks = {}
+            for k in ks:
+                Ak2 = pkg.randutv_truncate(U2, T2, V2, k)
+                ranks[str(k)] = {"trunc_err": (torch.linalg.norm(A - Ak2) / nA).item(),
+                                 "vs_fp64": (torch.linalg.norm(Ak2 - ref_err[k][0]) / nA).item()}
+                del Ak2
+            rec["rank_k"] = ranks
+            kk = min(1024, size)
+            rec["vs_fp64"] = {"T": (torch.linalg.norm(T2 - T) / nA).item(),
+                              "U_1024": _aligned_col_err(U2, U, kk),
+                              "V_1024": _aligned_col_err(V2, V, kk)}
+        block[name] = rec
+        log(f"# mixed {size}x{size} {name}: {ms:.2f} ms/step")
+    del U2, T2, V2, eye
+    for k in ks:
+        del ref_err[k]
+    if reuse is None:
+        del A, U, T, V
+    torch.cuda.empty_cache()
+    return block
+
+
+def truncation_grad_block(pkg, torch, args, dev):
+    """Differentiable first-block truncation: a batch of 2048 x 2048 matrices
+    (s_i = 0.98^i), b = 128, q = 2, k = 128; loss ||A_k - B||_F^2 for a seeded
+    Gaussian B; forward and reverse pass timed separately."""
+    from randutv_inputs import make_matrix_device
+
+    gm, gb, gq = 2048, 128, 2
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(77)
+    As = [make_matrix_device("exp98", gm, gm, seed=100 + i, device=dev) for i in range(args.grad_batch)]
+    Bs = [torch.randn(gm, gm, dtype=torch.float64, device=dev, generator=gen) for _ in As]
+
+    def fwd_bwd(Ai, Bi, first_step_only=False):
+        X = Ai.detach().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Ak = pkg.first_block_truncation(X, gb, gq, 0, first_step_only=first_step_only)
+        loss = ((Ak - Bi) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        return t1 - t0, time.perf_counter() - t1
+
+    fwd_bwd(As[0], Bs[0])
+    tf = tb = 0.0
+    for Ai, Bi in zip(As, Bs):
+        a, c = fwd_bwd(Ai, Bi)
+        tf += a
+        tb += c
+    tf1 = 0.0
+    for Ai, Bi in zip(As, Bs):
+        tf1 += fwd_bwd(Ai, Bi, first_step_only=True)[0]
+    log(f"# truncation grad batch: forward {1e3 * tf / len(As):.2f} ms (first step only "
+        f"{1e3 * tf1 / len(As):.2f} ms), backward {1e3 * tb / len(As):.2f} ms per matrix")
+    return {"workload": f"{args.grad_batch} x {gm}x{gm}, s_i = 0.98^i, b={gb}, q={gq}, k={gb}, FP64, "
+                        "loss ||A_k - B||_F^2",
+            "ms_forward_per_matrix": round(1e3 * tf / len(As), 3),
+            "ms_forward_first_step_per_matrix": round(1e3 * tf1 / len(As), 3),
+            "ms_backward_per_matrix": round(1e3 * tb / len(As), 3),
+            "ms_batch": round(1e3 * (tf + tb), 3)}
 
 
 if __name__ == "__main__":

@@ -55,39 +55,140 @@ extern "C" {
  * returns RANDUTV_ERR_NONFINITE before any factorization work.
  * Errors: -1 m, -2 n (n < 0 or n > m), -3 A NULL, -4 lda, -5 b, -6 q,
  * -8 U aliases T or V, -9 T NULL (or T == A with lda != m), -10 V aliases T,
- * RANDUTV_ERR_TOO_LARGE for min(b, n) > 256, RANDUTV_ERR_* at run time.
+ * RANDUTV_ERR_TOO_LARGE for min(b, n) > 256 or m > 32768 (panel kernel
+ * limit), checked before any device work; RANDUTV_ERR_* at run time (the
+ * library drains its streams before returning an error).
  */
 int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda,
                    int64_t b, int32_t q, uint64_t seed,
                    double* U, double* T, double* V);
 
 /*
- * randutv_factor_ex -- randutv_factor with a choice of arithmetic for the
- * sketch and power-iteration products Y = (B^T B)^q B^T G of every step
- * (Section 3.1; they only choose the subspace that V^ spans).
- *   sketch_bits : RANDUTV_SKETCH_FP64 (64): FP64 matrix cores, as randutv_factor;
- *                 RANDUTV_SKETCH_FP32 (32): operands rounded to FP32 and
- *                 multiplied on the FP32 matrix cores (FP64 storage, FP32
- *                 accumulation within a K split);
- *                 RANDUTV_SKETCH_BF16 (16): operands rounded to BF16 (via
- *                 FP32), BF16 matrix cores, FP32 accumulation;
- *                 RANDUTV_SKETCH_BF16X3 (48): each operand split into two
- *                 BF16 parts x = hi + lo and the product formed as
- *                 hi*hi + hi*lo + lo*hi on the BF16 matrix cores (about 16
- *                 significant bits per operand), FP32 accumulation.
- * Every transform applied to T, U and V (Householder vectors, block factors,
- * updates, the b x b SVDs) stays FP64, so A = U T V^T holds to FP64 accuracy
- * in every mode; with a reduced-precision sketch the subspaces (hence T, U, V
- * themselves) differ from the FP64 ones by the perturbation of the sketch.
- * Errors as randutv_factor, plus -11 for an unknown sketch_bits.
+ * randutv_factor_ex -- the factorization of randutv_factor (Section 3.1,
+ * Figure 2) with every option of the method exposed through one argument
+ * structure.  Fields (the caller zero-initializes the structure, sets
+ * struct_size = sizeof(randutv_args), then fills what it needs; a zero field
+ * takes the default noted):
+ *   m, n, A, lda, b, q, seed : as randutv_factor.
+ *   U, ldu : m x m output (ldu >= m; 0 means m), or U = NULL to skip it.
+ *   T, ldt : m x n output (ldt >= m; 0 means m); T == A needs ldt == lda.
+ *   V, ldv : n x n output (ldv >= n; 0 means n), or V = NULL to skip it.
+ *   stream : with RANDUTV_FLAG_STREAM, the caller's HIP stream (a
+ *            hipStream_t; NULL is the null stream).  The library's work
+ *            starts after everything enqueued on it before the call, and
+ *            everything enqueued on it after the call starts after the
+ *            library's work; the host thread still returns only when the
+ *            factorization has finished (to report its status).  Without the
+ *            flag the field is ignored and the library waits for nothing the
+ *            caller enqueued (as randutv_factor).
+ *   G      : NULL: the library draws the sketches itself (as randutv_factor).
+ *            Otherwise the caller's sketches, which the algorithm uses
+ *            instead: G(0), G(1), ..., G(p-1) stored one after the other,
+ *            G(i) (m - i b) x b_i column-major with leading dimension
+ *            m - i b, b_i = min(b, n - i b) (b clamped to n), so G(i) starts
+ *            at element sum_{j<i} (m - j b) b_j; randutv_sketch_host writes
+ *            this layout.  Device memory, or host memory with
+ *            RANDUTV_FLAG_G_HOST (page-locked memory keeps the copies
+ *            asynchronous).  Section 3.1 only asks for i.i.d. N(0,1) entries.
+ *   sketch_bits : arithmetic of the sketch and power-iteration products
+ *            Y = (B^T B)^q B^T G (0 means 64):
+ *              RANDUTV_SKETCH_FP64 (64) FP64 matrix cores;
+ *              RANDUTV_SKETCH_FP32 (32) operands rounded to FP32, FP32
+ *                matrix cores (FP32 accumulation within a K split);
+ *              RANDUTV_SKETCH_BF16 (16) operands rounded to BF16 (via FP32),
+ *                BF16 matrix cores, FP32 accumulation;
+ *              RANDUTV_SKETCH_BF16X3 (48) each operand split into BF16 parts
+ *                x = hi + lo, product hi*hi + hi*lo + lo*hi (about 16
+ *                significant bits per operand), FP32 accumulation.
+ *            These products only choose the subspace that each step's V^
+ *            spans: A = U T V^T and the orthogonality of U and V keep FP64
+ *            accuracy in every mode.
+ *   update_bits : arithmetic (same codes; 0 means 64) of the compact-WY
+ *            updates of T, U and V (T V^, V V^, U U^, U^^T T and the
+ *            products with W inside them).  Householder vectors, tau, the
+ *            block factors and the b x b SVDs stay FP64 in every mode.  With
+ *            reduced-precision updates A = U T V^T and the orthogonality of
+ *            U and V hold only to about that precision times the number of
+ *            steps (for FP32: ||A - U T V^T||_F / ||A||_F and max|U^T U - I|
+ *            of order 1e-6 at n = 16000).
+ *   flags  : RANDUTV_FLAG_STREAM       order the call on `stream`;
+ *            RANDUTV_FLAG_G_HOST       G is in host memory;
+ *            RANDUTV_FLAG_NO_FINITE_CHECK  skip the NaN/Inf scan of A (one
+ *            read of A and one host round trip fewer; outputs are then
+ *            undefined for such an A).
+ *   jacobi_max_sweeps : sweep cap of each b x b Jacobi SVD (0 means 30);
+ *            exceeding it returns RANDUTV_ERR_NOCONV.
+ *   spin_limit : polls before a multi-workgroup kernel gives up a wait and
+ *            reports RANDUTV_ERR_SYNC (0 means the built-in limit).  A small
+ *            value makes the waits give up early: every kernel still ends,
+ *            the outputs are garbage and the call returns RANDUTV_ERR_SYNC.
+ *   max_workspace_bytes : largest device workspace the call may hold
+ *            (0 means no limit); a call that needs more returns
+ *            RANDUTV_ERR_NOMEM before any device work.
+ * Errors: -1 m, -2 n, -3 A, -4 lda, -5 b, -6 q, -8 U/ldu, -9 T/ldt,
+ * -10 V/ldv, -11 sketch_bits, -12 update_bits, -13 flags,
+ * -14 jacobi_max_sweeps (< 0 or > 1000), -15 args NULL or struct_size
+ * smaller than the structure of this header; RANDUTV_ERR_TOO_LARGE for
+ * min(b, n) > 256 or m > 32768; RANDUTV_ERR_* at run time.  On a run-time
+ * error the library drains its streams before it returns: no work of the
+ * call is left running on the caller's buffers.
  */
 #define RANDUTV_SKETCH_FP64 64
 #define RANDUTV_SKETCH_FP32 32
 #define RANDUTV_SKETCH_BF16 16
 #define RANDUTV_SKETCH_BF16X3 48
-int randutv_factor_ex(int64_t m, int64_t n, const double* A, int64_t lda,
-                      int64_t b, int32_t q, uint64_t seed,
-                      double* U, double* T, double* V, int32_t sketch_bits);
+#define RANDUTV_FLAG_G_HOST 1u
+#define RANDUTV_FLAG_NO_FINITE_CHECK 2u
+#define RANDUTV_FLAG_STREAM 4u
+struct ihipStream_t;
+typedef struct randutv_args {
+  int64_t struct_size;
+  int64_t m, n;
+  const double* A;
+  int64_t lda;
+  int64_t b;
+  int32_t q;
+  int32_t sketch_bits;
+  uint64_t seed;
+  double* U;
+  int64_t ldu;
+  double* T;
+  int64_t ldt;
+  double* V;
+  int64_t ldv;
+  struct ihipStream_t* stream;
+  const double* G;
+  int32_t update_bits;
+  uint32_t flags;
+  int32_t jacobi_max_sweeps;
+  uint32_t spin_limit;
+  int64_t max_workspace_bytes;
+} randutv_args;
+int randutv_factor_ex(const randutv_args* args);
+
+/*
+ * randutv_sketch_host -- every sketch G(0), ..., G(p-1) that randutv_factor
+ * (m, n, ..., b, ..., seed) draws, written to HOST memory in the layout that
+ * randutv_factor_ex takes as a caller's G (G(i) of (m - i b) x b_i,
+ * column-major, ld m - i b, one after the other; b clamped to n, p =
+ * ceil(n / b)): sum_i (m - i b) b_i doubles.  The values are generated on the
+ * device by the generator described at randutv_factor, then copied out.
+ * Errors: -2 m (m < 0), -3 n (n < 0 or n > m), -4 b, -5 G_host;
+ * RANDUTV_ERR_NOMEM, RANDUTV_ERR_HIP.
+ */
+int randutv_sketch_host(uint64_t seed, int64_t m, int64_t n, int64_t b, double* G_host);
+
+/*
+ * randutv_sketch_words -- the raw 64-bit Philox4x64-10 words behind the
+ * sketch of step `step` (key (seed, step), counter (k, 0, 0, 0) for block
+ * k = first_block, ..., first_block + nblocks - 1): out[4 j + w] is word w of
+ * block first_block + j (device memory, 4 nblocks words).  Exported so that
+ * the integer stream can be compared bit for bit with an independent
+ * implementation of the published generator.
+ * Errors: -4 nblocks (< 0), -5 out.
+ */
+int randutv_sketch_words(uint64_t seed, uint64_t step, uint64_t first_block, int64_t nblocks,
+                         uint64_t* out);
 
 /*
  * randutv_truncate -- rank-k truncation A_k = U(:, 0:k) T(0:k, :) V^T
@@ -223,8 +324,12 @@ int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d,
 /* Per-kernel timing.  randutv_set_timing(1) clears the counters and makes
  * every later randutv_factor call record a HIP event pair around each kernel
  * launch on the stream it is launched on; randutv_set_timing(2) does the same
- * for the GEMM launches only (half the event records); randutv_set_timing(0)
- * stops it.  Other values return -1.
+ * for the GEMM launches only (half the event records); randutv_set_timing(3)
+ * times the GEMM launches only and runs each of them alone (the host waits
+ * for all queued work before the launch and for the launch after it), so
+ * that the recorded durations are the kernel's own rather than shares of a
+ * chip that other streams' kernels also occupy; randutv_set_timing(0) stops
+ * it.  Other values return -1.
  * randutv_kernel_stats writes, per kernel class, the number of launches, the
  * summed device time in ms and the algorithmic FP64 flops accumulated since
  * timing was enabled.  Returns the number of classes written (at most cap);
@@ -240,6 +345,12 @@ int randutv_last_sweeps(int32_t cap, int32_t* sweeps);
 /* Text of the last HIP runtime error met by the calling thread inside the
  * library ("" if none), for diagnosing RANDUTV_ERR_HIP / RANDUTV_ERR_NOMEM. */
 const char* randutv_last_hip_error(void);
+
+/* Releases the library's streams, events and device workspace on the current
+ * device after waiting for its work (the next call creates them again).
+ * Meant for an orderly process exit: the Python binding calls it at
+ * interpreter shutdown, before the HIP runtime is torn down.  Returns 0. */
+int randutv_finalize(void);
 
 /* Human-readable text for a return code (static storage). */
 const char* randutv_strerror(int code);

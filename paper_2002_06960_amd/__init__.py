@@ -5,6 +5,11 @@ The factorization runs in hand-written HIP kernels behind a C ABI
 """
 from .randutv import (  # noqa: F401
     RandUTVError,
+    RandutvArgs,
+    make_args,
+    sketch_offsets,
+    randutv_sketch_host,
+    randutv_sketch_words,
     as_colmajor,
     colmajor_empty,
     first_block_truncation,

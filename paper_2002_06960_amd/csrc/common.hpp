@@ -43,14 +43,15 @@ __device__ __forceinline__ double wave_max(double v) {
 // ---------------------------------------------------------------------------
 constexpr unsigned kSpinLimit = 1u << 26;
 
-__device__ __forceinline__ void grid_barrier(unsigned* counter, unsigned target, int* err) {
+__device__ __forceinline__ void grid_barrier(unsigned* counter, unsigned target, int* err,
+                                             unsigned limit = kSpinLimit) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
     while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) {
+      if (++spins > limit) {
         __hip_atomic_store(err, RANDUTV_ERR_SYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }

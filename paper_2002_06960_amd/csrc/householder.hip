@@ -131,7 +131,7 @@ struct ForColumns<kPQNB> {
 template <int kPQThreads>
 __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
     int m, int k, double* __restrict__ A, i64 lda, double* __restrict__ tau, u64* __restrict__ xch,
-    int* __restrict__ err) {
+    int* __restrict__ err, unsigned spin_limit) {
   constexpr int kPQWaves = kPQThreads / WAVE;
   const int P = gridDim.x, wg = blockIdx.x;
   const int r0 = (int)((i64)m * wg / P), r1 = (int)((i64)m * (wg + 1) / P), R = r1 - r0;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
   // a bounded wait: on expiry record the error and stop waiting for good
   auto give_up = [&](unsigned& spins) -> bool {
     if (*(volatile int*)&dead) return true;
-    if (++spins > kPQSpinLimit) {
+    if (++spins > spin_limit) {
       dead = 1;
       __hip_atomic_store(err, RANDUTV_ERR_SYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return true;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
             }
             int have = 1;
 #pragma unroll
-            for (int i = 0; i < NB; ++i) have &= (w0 + i >= P) | (xhas(lo[i], tag) & xhas(hi[i], tag));
+            for (int i = 0; i < NB; ++i) have &= (int)(w0 + i >= P) | ((int)xhas(lo[i], tag) & (int)xhas(hi[i], tag));
             if (have || give_up(spins)) break;
           }
 #pragma unroll
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
           while (true) {
             lo = xget(xt + (i64)e * 2);
             hi = xget(xt + (i64)e * 2 + 1);
-            if ((xhas(lo, tag) & xhas(hi, tag)) || give_up(spins)) break;
+            if (((int)xhas(lo, tag) & (int)xhas(hi, tag)) || give_up(spins)) break;
           }
           v = xval(lo, hi);
         }
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
             }
             int have = 1;
 #pragma unroll
-            for (int i = 0; i < NB; ++i) have &= (w0 + i >= P) | (xhas(lo[i], tag1) & xhas(hi[i], tag1));
+            for (int i = 0; i < NB; ++i) have &= (int)(w0 + i >= P) | ((int)xhas(lo[i], tag1) & (int)xhas(hi[i], tag1));
             if (have || give_up(spins)) break;
           }
 #pragma unroll
@@ -562,7 +562,7 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
         }
         int have = 1;
 #pragma unroll
-        for (int i = 0; i < NE; ++i) have &= (xhas(lo[i], tag2) & xhas(hi[i], tag2));
+        for (int i = 0; i < NE; ++i) have &= ((int)xhas(lo[i], tag2) & (int)xhas(hi[i], tag2));
         if (have || give_up(spins)) break;
       }
 #pragma unroll
@@ -684,10 +684,11 @@ int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau, cons
   LaunchTimer* tm = launch_timer();
   RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(w.xch), 2 * panel_words(P)));
   if (tm) tm->begin(st, K_PANEL);
+  const unsigned lim = w.spin_limit ? w.spin_limit : kPQSpinLimit;
   if (shared_cus)
-    panel_qr_kernel<256><<<P, 256, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err);
+    panel_qr_kernel<256><<<P, 256, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err, lim);
   else
-    panel_qr_kernel<512><<<P, 512, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err);
+    panel_qr_kernel<512><<<P, 512, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err, lim);
   RUTV_TRY(hipGetLastError());
   if (tm) tm->end(st, K_PANEL, 2.0 * m * k * k - 2.0 * k * k * k / 3.0);
   return RANDUTV_OK;

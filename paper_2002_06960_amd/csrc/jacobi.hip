@@ -157,7 +157,8 @@ __global__ __launch_bounds__(kJThreads) void jacobi_block_kernel(int kfull, int 
                                                                  double* __restrict__ Usall,
                                                                  double* __restrict__ Vsall, i64 us,
                                                                  double* __restrict__ wall, i64 ws,
-                                                                 int* __restrict__ stall) {
+                                                                 int* __restrict__ stall,
+                                                                 int max_sweeps, unsigned spin_limit) {
   const int prob = blockIdx.x / P, wg = blockIdx.x % P;
   const int count = gridDim.x / P;
   const int k = prob == count - 1 ? k_last : kfull;
@@ -187,13 +188,13 @@ __global__ __launch_bounds__(kJThreads) void jacobi_block_kernel(int kfull, int 
     W[e] = R[r + (i64)c * ldr];
     V[e] = r == c ? 1.0 : 0.0;
   }
-  grid_barrier(ctr, (++nbar) * (unsigned)P, err);
+  grid_barrier(ctr, (++nbar) * (unsigned)P, err, spin_limit);
 
   const double tol = (double)k * 0x1p-53;
   int sweeps = 0;
   bool converged = k <= 1;
   unsigned prev_total = 0;
-  while (!converged && sweeps < kJacobiMaxSweeps) {
+  while (!converged && sweeps < max_sweeps) {
     ++sweeps;
     if (tid == 0) lrot = 0;
     for (int round = 0; round < nblk - 1 || (nblk == 2 && round == 0); ++round) {
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(kJThreads) void jacobi_block_kernel(int kfull, int 
         if (tid == 0)
           __hip_atomic_fetch_add(&ctr[1], (unsigned)lrot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      grid_barrier(ctr, (++nbar) * (unsigned)P, err);
+      grid_barrier(ctr, (++nbar) * (unsigned)P, err, spin_limit);
       if (last) {
         if (tid == 0) {
           const unsigned tot = __hip_atomic_load(&ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(kJThreads) void jacobi_block_kernel(int kfull, int 
   any_zero = dn[perm[k - 1]] == 0.0;
   if (!any_zero) return;
   // rare: exact zero singular values -> complete U (workgroup 0, wave 0)
-  grid_barrier(ctr, (++nbar) * (unsigned)P, err);
+  grid_barrier(ctr, (++nbar) * (unsigned)P, err, spin_limit);
   if (wg != 0 || wave != 0) return;
   int cand = 0;
   for (int qo = 0; qo < k; ++qo) {
@@ -431,7 +432,7 @@ __global__ void jacobi_zero_kernel(int count, int kfull, double* __restrict__ wa
 
 int jacobi_svd_batched(hipStream_t st, int count, i64 k, i64 k_last, const double* R, i64 ldr,
                        i64 rs, double* d, i64 ds, double* Us, double* Vs, i64 us, double* work,
-                       int* status) {
+                       int* status, int max_sweeps, unsigned spin_limit) {
   if (count <= 0 || k <= 0) return RANDUTV_OK;
   if (k > kJacobiMaxN || k_last > k || k_last <= 0) return RANDUTV_ERR_TOO_LARGE;
   const int P = (int)std::max<i64>(1, std::min<i64>(kJMaxWG, cdiv(k, 2 * kJBW)));
@@ -440,16 +441,18 @@ int jacobi_svd_batched(hipStream_t st, int count, i64 k, i64 k_last, const doubl
   jacobi_zero_kernel<<<(count + 63) / 64, 64, 0, st>>>(count, (int)k, work, ws, status);
   RUTV_TRY(hipGetLastError());
   if (tm) tm->begin(st, K_JACOBI);
-  jacobi_block_kernel<<<P * count, kJThreads, 0, st>>>((int)k, (int)k_last, P, R, ldr, rs, d, ds, Us,
-                                                       Vs, us, work, ws, status);
+  jacobi_block_kernel<<<P * count, kJThreads, 0, st>>>(
+      (int)k, (int)k_last, P, R, ldr, rs, d, ds, Us, Vs, us, work, ws, status,
+      max_sweeps > 0 ? max_sweeps : kJacobiMaxSweeps, spin_limit ? spin_limit : kSpinLimit);
   RUTV_TRY(hipGetLastError());
   if (tm) tm->end(st, K_JACOBI, 0.0);
   return RANDUTV_OK;
 }
 
 int jacobi_svd(hipStream_t st, i64 k, const double* R, i64 ldr, double* d, double* Us, double* Vs,
-               double* work, int* status) {
-  return jacobi_svd_batched(st, 1, k, k, R, ldr, 0, d, 0, Us, Vs, 0, work, status);
+               double* work, int* status, int max_sweeps, unsigned spin_limit) {
+  return jacobi_svd_batched(st, 1, k, k, R, ldr, 0, d, 0, Us, Vs, 0, work, status, max_sweeps,
+                            spin_limit);
 }
 
 }  // namespace rutv

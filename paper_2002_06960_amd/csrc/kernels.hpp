@@ -42,6 +42,7 @@ constexpr int kPanelMaxCols = 256;
 struct PanelWork {
   unsigned long long* xch = nullptr;  // exchange words between workgroups
   int* err = nullptr;                 // device status word
+  unsigned spin_limit = 0;            // polls before a wait gives up (0: built-in limit)
 };
 // size (64-bit words) of PanelWork::xch for panels of up to m rows
 i64 panel_work_elems(i64 m);
@@ -64,14 +65,17 @@ constexpr int kJacobiMaxN = 256;
 constexpr int kJacobiMaxSweeps = 30;
 i64 jacobi_work_elems(i64 k);
 // status[0] = sweeps, status[1] = converged flag, status[2] = barrier error (device ints)
+// max_sweeps: sweep cap (0: kJacobiMaxSweeps); spin_limit: polls before a
+// grid-barrier wait gives up (0: built-in limit)
 int jacobi_svd(hipStream_t st, i64 k, const double* R, i64 ldr, double* d, double* Us,
-               double* Vs, double* work, int* status);
+               double* Vs, double* work, int* status, int max_sweeps = 0,
+               unsigned spin_limit = 0);
 // count independent SVDs in one launch: problem p is R + p*rs (k x k, ld ldr;
 // the last one k_last x k_last), outputs d + p*ds, Us/Vs + p*us (ld = its k),
 // work + p*jacobi_work_elems(k), status + 3p.
 int jacobi_svd_batched(hipStream_t st, int count, i64 k, i64 k_last, const double* R, i64 ldr,
                        i64 rs, double* d, i64 ds, double* Us, double* Vs, i64 us, double* work,
-                       int* status);
+                       int* status, int max_sweeps = 0, unsigned spin_limit = 0);
 
 // ---- HQRRP pivoting (hqrrp.hip) ---------------------------------------------
 struct CpqrWork {
@@ -100,6 +104,9 @@ int set_iota(hipStream_t st, i64 n, int64_t* x);
 // ---- sketch and utilities (util.hip) ----------------------------------------
 int sketch(hipStream_t st, uint64_t seed, uint64_t step, i64 rows, i64 cols, double* G,
            i64 ldg);
+// out[4 j + w] := word w of the generator block first + j, j < nblocks
+int sketch_words(hipStream_t st, uint64_t seed, uint64_t step, uint64_t first, i64 nblocks,
+                 uint64_t* out);
 int set_identity(hipStream_t st, i64 n, double* X, i64 ldx);
 // X (rows x cols, ld ldx) := the first cols columns of the rows x rows identity
 int set_eye(hipStream_t st, i64 rows, i64 cols, double* X, i64 ldx);

@@ -60,6 +60,9 @@ struct EventTimer final : LaunchTimer {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> open;  // begin events awaiting their end (one per class nesting level)
   bool gemm_only = false;  // time the GEMM launches alone (fewer event records)
+  // run every GEMM launch alone: wait for all queued work before it and for
+  // the launch itself after it, so that its duration is the kernel's own
+  bool serialize = false;
   int64_t launches[K_NUM_CLASSES] = {};
   double ms[K_NUM_CLASSES] = {};
   double flops[K_NUM_CLASSES] = {};
@@ -80,8 +83,16 @@ struct EventTimer final : LaunchTimer {
   void clear_counts() {
     for (int c = 0; c < K_NUM_CLASSES; ++c) launches[c] = 0, ms[c] = 0.0, flops[c] = 0.0;
   }
+  void destroy() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+    used = 0;
+    recs.clear();
+    open.clear();
+  }
   static bool is_gemm(int cls) { return cls >= K_GEMM_NN && cls <= K_GEMM_TT; }
   void begin(hipStream_t st, int cls) override {
+    if (serialize && is_gemm(cls)) (void)hipDeviceSynchronize();
     hipEvent_t e = gemm_only && !is_gemm(cls) ? nullptr : take();
     if (e) (void)hipEventRecord(e, st);
     open.push_back(e);
@@ -94,6 +105,7 @@ struct EventTimer final : LaunchTimer {
       (void)hipEventRecord(b, st);
       recs.push_back({a, b, cls, f});
     }
+    if (serialize && is_gemm(cls)) (void)hipStreamSynchronize(st);
   }
   void collect() {
     for (auto& r : recs) {
@@ -173,6 +185,29 @@ struct Context {
     st = streams[ST_T];
     return RANDUTV_OK;
   }
+  // release streams, events and the workspace (explicit teardown, before the
+  // HIP runtime itself is torn down at process exit)
+  void release() {
+    if (!st) return;
+    for (auto& x : streams) (void)hipStreamSynchronize(x);
+    for (auto& x : streams) (void)hipStreamDestroy(x);
+    for (auto& kind : ev)
+      for (auto& e : kind) (void)hipEventDestroy(e);
+    for (auto& e : ev_misc) (void)hipEventDestroy(e);
+    timer.destroy();
+    if (ws) (void)hipFree(ws);
+    ws = nullptr;
+    ws_bytes = 0;
+    st = nullptr;
+    for (auto& x : streams) x = nullptr;
+    device = -1;
+  }
+  // wait for everything the library enqueued (used before returning an error,
+  // so that no kernel of a failed call keeps running on the caller's buffers)
+  void drain() {
+    for (auto& x : streams)
+      if (x) (void)hipStreamSynchronize(x);
+  }
   int reserve(size_t bytes) {
     if (bytes <= ws_bytes) return RANDUTV_OK;
     if (ws) {
@@ -230,6 +265,8 @@ struct StreamWS {
 #define RUTV_SVD_GROUP 8
 #endif
 constexpr int kSvdGroup = RUTV_SVD_GROUP;  // SVDs per batched launch
+// the panel kernel's row limit (its workgroups times their slab)
+constexpr i64 kMaxRows = 32768;
 
 struct FactorWS {
   StreamWS sw[NSTREAMS];
@@ -331,9 +368,9 @@ static int t_factor(hipStream_t st, const StreamWS& x, i64 rows, i64 k, const do
 // C(rows x cols, ld ldc) <- C (I - W Tf W^T) = C - (C W) Z^T, W and Z: cols x k
 // (ld cols)
 static int right_apply(hipStream_t st, const StreamWS& x, i64 rows, i64 cols, i64 k, double* C,
-                       i64 ldc, const double* W, const double* Z) {
-  RUTV_CHECK(gemm(st, x, false, false, rows, k, cols, 1.0, C, ldc, W, cols, 0.0, x.X, rows));
-  RUTV_CHECK(gemm(st, x, false, true, rows, cols, k, -1.0, x.X, rows, Z, cols, 1.0, C, ldc));
+                       i64 ldc, const double* W, const double* Z, int prec = PREC_F64) {
+  RUTV_CHECK(gemm(st, x, false, false, rows, k, cols, 1.0, C, ldc, W, cols, 0.0, x.X, rows, prec));
+  RUTV_CHECK(gemm(st, x, false, true, rows, cols, k, -1.0, x.X, rows, Z, cols, 1.0, C, ldc, prec));
   return RANDUTV_OK;
 }
 
@@ -349,14 +386,48 @@ static int right_mul_small(hipStream_t st, const StreamWS& x, i64 rows, i64 k, d
 // sketch_prec: arithmetic of the sketch and power-iteration products
 // Y = (B^T B)^q B^T G (a GemmPrec; FP64 storage either way); every transform
 // of T, U and V stays FP64
-static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uint64_t seed,
-                       double* U, double* T, double* V, int sketch_prec) {
+// Everything a factorization call needs (validated by the entry points).
+struct FactorCfg {
+  i64 m = 0, n = 0;
+  const double* A = nullptr;
+  i64 lda = 0, b = 0;
+  int q = 0;
+  uint64_t seed = 0;
+  double *U = nullptr, *T = nullptr, *V = nullptr;
+  i64 ldu = 0, ldt = 0, ldv = 0;
+  bool has_caller = false;       // order the call on the caller's stream
+  hipStream_t caller = nullptr;  // that stream (null: the null stream)
+  const double* G = nullptr;     // the caller's sketches (concatenated), or null
+  bool g_host = false;           // G is host memory
+  bool finite_check = true;
+  int sketch_prec = PREC_F64;    // sketch and power-iteration products
+  int update_prec = PREC_F64;    // compact-WY updates of T, U and V
+  int max_sweeps = 0;            // Jacobi sweep cap (0: default)
+  unsigned spin_limit = 0;       // bounded waits (0: default)
+  size_t max_ws = 0;             // workspace cap (0: none)
+};
+
+static int factor_run(const FactorCfg& c, Context& cx);
+
+static int factor_impl(const FactorCfg& c) {
   Context& cx = ctx();
   RUTV_CHECK(cx.init());
+  const int rc = factor_run(c, cx);
+  if (rc != RANDUTV_OK) cx.drain();
+  return rc;
+}
+
+static int factor_run(const FactorCfg& c, Context& cx) {
   hipStream_t sT = cx.streams[ST_T], sP = cx.streams[ST_P], sUV = cx.streams[ST_UV],
               sS = cx.streams[ST_S];
+  const i64 m = c.m, n = c.n, lda = c.lda, ldt = c.ldt, ldu = c.ldu, ldv = c.ldv;
+  const double* A = c.A;
+  double *U = c.U, *T = c.T, *V = c.V;
+  const int q = c.q;
+  const uint64_t seed = c.seed;
+  const int sketch_prec = c.sketch_prec, update_prec = c.update_prec;
   const bool wantU = U != nullptr, wantV = V != nullptr;
-  const i64 ldt = m, ldu = m, ldv = n;
+  i64 b = c.b;
   if (b > n) b = n;
   const i64 nsteps = cdiv(n, b);
   const i64 b_last = n - (nsteps - 1) * b;
@@ -364,12 +435,22 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
   FactorWS w{};
   Carver probe;
   const size_t bytes = layout(probe, w, m, n, b, q, wantU, wantV);
+  if (c.max_ws && bytes > c.max_ws) return RANDUTV_ERR_NOMEM;
   RUTV_CHECK(cx.reserve(bytes));
   Carver real;
   real.base = cx.ws;
   layout(real, w, m, n, b, q, wantU, wantV);
-  for (auto& x : w.sw) x.pw.err = &w.status[1];
+  for (auto& x : w.sw) {
+    x.pw.err = &w.status[1];
+    x.pw.spin_limit = c.spin_limit;
+  }
   const StreamWS &xT = w.sw[ST_T], &xP = w.sw[ST_P], &xUV = w.sw[ST_UV], &xS = w.sw[ST_S];
+  // the caller's sketch of step i: offset of G(i) in the concatenation
+  auto g_offset = [&](i64 i) {
+    i64 off = 0;
+    for (i64 j = 0; j < i; ++j) off += (m - j * b) * std::min(b, n - j * b);
+    return off;
+  };
 
   cx.timer.start_call();
   set_launch_timer(cx.timing ? &cx.timer : nullptr);
@@ -378,13 +459,19 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
   } reset_timer;
   auto ev = [&](int kind, i64 i) { return cx.ev[kind][i % kEvRing]; };
 
+  // ---- the caller's stream: the library's streams start after the work
+  // enqueued on it so far
+  if (c.has_caller) {
+    RUTV_TRY(hipEventRecord(cx.ev_misc[3], c.caller));
+    for (auto x : cx.streams) RUTV_TRY(hipStreamWaitEvent(x, cx.ev_misc[3], 0));
+  }
   // ---- prologue (stream T): status, T := A with a finiteness check
-  RUTV_TRY(hipMemsetAsync(w.status, 0, sizeof(int) * (2 + 3 * nsteps), sT));
+  RUTV_CHECK(fill_zero_u32(sT, reinterpret_cast<unsigned*>(w.status), 2 + 3 * nsteps));
   if (T != A)
-    RUTV_CHECK(copy_check(sT, m, n, A, lda, T, ldt, &w.status[0]));
-  else
+    RUTV_CHECK(copy_check(sT, m, n, A, lda, T, ldt, c.finite_check ? &w.status[0] : nullptr));
+  else if (c.finite_check)
     RUTV_CHECK(check_finite(sT, m, n, T, ldt, &w.status[0]));
-  {
+  if (c.finite_check) {
     int flag = 0;
     RUTV_TRY(hipMemcpyAsync(&flag, &w.status[0], sizeof(int), hipMemcpyDeviceToHost, sT));
     RUTV_TRY(hipStreamSynchronize(sT));
@@ -403,9 +490,11 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     const int bf = (int)(j % kWyBuf);
     if (wait_pre) RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_PRE, j + 1), 0));
     RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_V, j), 0));
-    if (wantV) RUTV_CHECK(right_apply(sUV, xUV, n, nj, bj, V + sj * ldv, ldv, w.WV[bf], w.ZV[bf]));
+    if (wantV)
+      RUTV_CHECK(right_apply(sUV, xUV, n, nj, bj, V + sj * ldv, ldv, w.WV[bf], w.ZV[bf], update_prec));
     RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_U, j), 0));
-    if (wantU) RUTV_CHECK(right_apply(sUV, xUV, m, mj, bj, U + sj * ldu, ldu, w.WU[bf], w.ZU[bf]));
+    if (wantU)
+      RUTV_CHECK(right_apply(sUV, xUV, m, mj, bj, U + sj * ldu, ldu, w.WU[bf], w.ZU[bf], update_prec));
     RUTV_TRY(hipEventRecord(ev(EV_UV, j), sUV));
     // stream S: b x b SVDs in groups, then their right factors
     const bool last = sj + bj >= n;
@@ -414,7 +503,8 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
       RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_U, j), 0));
       RUTV_CHECK(jacobi_svd_batched(sS, cnt, b, last ? b_last : b, w.Rall + g0 * b * b, b, b * b,
                                     w.dall + g0 * b, b, w.Usall + g0 * b * b, w.Vsall + g0 * b * b,
-                                    b * b, w.jwork, &w.status[2 + 3 * g0]));
+                                    b * b, w.jwork, &w.status[2 + 3 * g0], c.max_sweeps,
+                                    c.spin_limit));
       for (i64 t = g0; t <= j; ++t) {
         const i64 st_ = t * b, bt = std::min(b, n - st_);
         const double* d = w.dall + t * b;
@@ -438,8 +528,16 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     double* Bm = T + s + s * ldt;
     // ---- stream T: sketch, power iteration, QR(Y), compact WY of V^
     if (i >= kWyBuf) RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_UV, i - kWyBuf), 0));  // WV[buf] free
-    RUTV_CHECK(sketch(sT, seed, (uint64_t)i, mi, bi, w.G, mi));
-    RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.G, mi, 0.0, w.Y, ni, sketch_prec));
+    const double* Gi = w.G;
+    if (!c.G) {
+      RUTV_CHECK(sketch(sT, seed, (uint64_t)i, mi, bi, w.G, mi));
+    } else if (c.g_host) {
+      RUTV_TRY(hipMemcpyAsync(w.G, c.G + g_offset(i), sizeof(double) * mi * bi,
+                              hipMemcpyHostToDevice, sT));
+    } else {
+      Gi = c.G + g_offset(i);
+    }
+    RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, Gi, mi, 0.0, w.Y, ni, sketch_prec));
     for (int it = 0; it < q; ++it) {
       RUTV_CHECK(gemm(sT, xT, false, false, mi, bi, ni, 1.0, Bm, ldt, w.Y, ni, 0.0, w.Zp, mi, sketch_prec));
       RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.Zp, mi, 0.0, w.Y, ni, sketch_prec));
@@ -456,13 +554,15 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     RUTV_TRY(hipEventRecord(ev(EV_V, i), sP));
     // right transform of all m rows, T <- T - (T W) Z^T: first the
     // current column block (it feeds the panel QR on stream P), then the rest
-    RUTV_CHECK(gemm(sT, xT, false, false, m, bi, ni, 1.0, T + s * ldt, ldt, w.WV[buf], ni, 0.0, xT.X, m));
+    RUTV_CHECK(gemm(sT, xT, false, false, m, bi, ni, 1.0, T + s * ldt, ldt, w.WV[buf], ni, 0.0, xT.X, m,
+                    update_prec));
     RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_V, i), 0));
-    RUTV_CHECK(gemm(sT, xT, false, true, m, bi, bi, -1.0, xT.X, m, w.ZV[buf], ni, 1.0, T + s * ldt, ldt));
+    RUTV_CHECK(gemm(sT, xT, false, true, m, bi, bi, -1.0, xT.X, m, w.ZV[buf], ni, 1.0, T + s * ldt, ldt,
+                    update_prec));
     RUTV_TRY(hipEventRecord(ev(EV_COLS, i), sT));
     if (e < n)
       RUTV_CHECK(gemm(sT, xT, false, true, m, ni - bi, bi, -1.0, xT.X, m, w.ZV[buf] + bi, ni, 1.0,
-                      T + e * ldt, ldt));
+                      T + e * ldt, ldt, update_prec));
     // ---- stream P: panel QR of the column block, its reflectors, then their
     // block factor while stream T forms W^T C
     RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_COLS, i), 0));
@@ -479,9 +579,11 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
     RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_WU, i), 0));
     if (e < n) {
       double* C = T + s + e * ldt;
-      RUTV_CHECK(gemm(sT, xT, true, false, bi, ni - bi, mi, 1.0, w.WU[buf], mi, C, ldt, 0.0, w.X3, bi));
+      RUTV_CHECK(gemm(sT, xT, true, false, bi, ni - bi, mi, 1.0, w.WU[buf], mi, C, ldt, 0.0, w.X3, bi,
+                      update_prec));
       RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_U, i), 0));
-      RUTV_CHECK(gemm(sT, xT, false, false, mi, ni - bi, bi, -1.0, w.ZU[buf], mi, w.X3, bi, 1.0, C, ldt));
+      RUTV_CHECK(gemm(sT, xT, false, false, mi, ni - bi, bi, -1.0, w.ZU[buf], mi, w.X3, bi, 1.0, C, ldt,
+                      update_prec));
     } else {
       RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_U, i), 0));
     }
@@ -505,6 +607,10 @@ static int factor_impl(i64 m, i64 n, const double* A, i64 lda, i64 b, int q, uin
       RUTV_CHECK(copy_matrix(sT, bi, n - e, w.X3, bi, C, ldt));
     }
     s = e;
+  }
+  if (c.has_caller) {
+    RUTV_TRY(hipEventRecord(cx.ev_misc[3], sT));
+    RUTV_TRY(hipStreamWaitEvent(c.caller, cx.ev_misc[3], 0));
   }
   RUTV_TRY(hipStreamSynchronize(sT));
   if (cx.timing) cx.timer.collect();
@@ -533,42 +639,100 @@ static int guarded(F&& f) {
   }
 }
 
+// an entry point's device work: on any failure after work was enqueued, wait
+// for the library's streams before returning, so that no kernel of the call
+// is left running on the caller's buffers
+template <class F>
+static int drained(Context& cx, F&& f) {
+  int rc;
+  try {
+    rc = f();
+  } catch (const std::bad_alloc&) {
+    rc = RANDUTV_ERR_NOMEM;
+  } catch (...) {
+    rc = RANDUTV_ERR_HIP;
+  }
+  if (rc != RANDUTV_OK) cx.drain();
+  return rc;
+}
+
 }  // namespace rutv
 
 using namespace rutv;
 
 extern "C" {
 
-int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
-                   uint64_t seed, double* U, double* T, double* V) {
-  return randutv_factor_ex(m, n, A, lda, b, q, seed, U, T, V, RANDUTV_SKETCH_FP64);
+static int prec_of_bits(int32_t bits, int& prec) {
+  switch (bits) {
+    case 0:
+    case RANDUTV_SKETCH_FP64: prec = PREC_F64; return 0;
+    case RANDUTV_SKETCH_FP32: prec = PREC_F32; return 0;
+    case RANDUTV_SKETCH_BF16: prec = PREC_BF16; return 0;
+    case RANDUTV_SKETCH_BF16X3: prec = PREC_BF16X3; return 0;
+    default: return -1;
+  }
 }
 
-int randutv_factor_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
-                      uint64_t seed, double* U, double* T, double* V, int32_t sketch_bits) {
-  if (m < 0) return -1;
-  if (n < 0 || n > m) return -2;
-  if (m == 0 || n == 0) return RANDUTV_OK;
-  if (!A) return -3;
-  if (lda < std::max<int64_t>(1, m)) return -4;
-  if (b < 1) return -5;
-  if (q < 0) return -6;
-  if (!T) return -9;
-  if (T == A && lda != m) return -9;
-  if (U && (U == T || U == V)) return -8;
-  if (V && V == T) return -10;
-  int prec;
-  switch (sketch_bits) {
-    case RANDUTV_SKETCH_FP64: prec = PREC_F64; break;
-    case RANDUTV_SKETCH_FP32: prec = PREC_F32; break;
-    case RANDUTV_SKETCH_BF16: prec = PREC_BF16; break;
-    case RANDUTV_SKETCH_BF16X3: prec = PREC_BF16X3; break;
-    default: return -11;
-  }
-  if (std::min(b, n) > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+// checks shared by both factorization entry points; returns 0, a negative
+// argument code, or RANDUTV_ERR_TOO_LARGE
+static int check_factor(const FactorCfg& c) {
+  if (c.m < 0) return -1;
+  if (c.n < 0 || c.n > c.m) return -2;
+  if (c.m == 0 || c.n == 0) return RANDUTV_OK;
+  if (!c.A) return -3;
+  if (c.lda < std::max<int64_t>(1, c.m)) return -4;
+  if (c.b < 1) return -5;
+  if (c.q < 0) return -6;
+  if (c.U && c.ldu < c.m) return -8;
+  if (!c.T || c.ldt < c.m) return -9;
+  if (c.T == c.A && c.lda != c.ldt) return -9;
+  if (c.V && c.ldv < c.n) return -10;
+  if (c.U && (c.U == c.T || c.U == c.V)) return -8;
+  if (c.V && c.V == c.T) return -10;
+  if (std::min(c.b, c.n) > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+  if (c.m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
+  return RANDUTV_OK;
+}
+
+static int factor_entry(const FactorCfg& c) {
+  const int rc = check_factor(c);
+  if (rc != RANDUTV_OK || c.m == 0 || c.n == 0) return rc;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
-  return guarded([&] { return factor_impl(m, n, A, lda, b, q, seed, U, T, V, prec); });
+  return guarded([&] { return factor_impl(c); });
+}
+
+int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                   uint64_t seed, double* U, double* T, double* V) {
+  FactorCfg c;
+  c.m = m, c.n = n, c.A = A, c.lda = lda, c.b = b, c.q = q, c.seed = seed;
+  c.U = U, c.T = T, c.V = V, c.ldu = m, c.ldt = m, c.ldv = n;
+  return factor_entry(c);
+}
+
+int randutv_factor_ex(const randutv_args* a) {
+  if (!a || a->struct_size < (int64_t)sizeof(randutv_args)) return -15;
+  FactorCfg c;
+  c.m = a->m, c.n = a->n, c.A = a->A, c.lda = a->lda, c.b = a->b, c.q = a->q, c.seed = a->seed;
+  c.U = a->U, c.T = a->T, c.V = a->V;
+  c.ldu = a->ldu ? a->ldu : a->m;
+  c.ldt = a->ldt ? a->ldt : a->m;
+  c.ldv = a->ldv ? a->ldv : a->n;
+  constexpr uint32_t kKnown = RANDUTV_FLAG_G_HOST | RANDUTV_FLAG_NO_FINITE_CHECK | RANDUTV_FLAG_STREAM;
+  if (a->flags & ~kKnown) return -13;
+  if ((a->flags & RANDUTV_FLAG_G_HOST) && !a->G) return -13;
+  if (prec_of_bits(a->sketch_bits, c.sketch_prec)) return -11;
+  if (prec_of_bits(a->update_bits, c.update_prec)) return -12;
+  if (a->jacobi_max_sweeps < 0 || a->jacobi_max_sweeps > 1000) return -14;
+  c.has_caller = (a->flags & RANDUTV_FLAG_STREAM) != 0;
+  c.caller = c.has_caller ? reinterpret_cast<hipStream_t>(a->stream) : nullptr;
+  c.G = a->G;
+  c.g_host = (a->flags & RANDUTV_FLAG_G_HOST) != 0;
+  c.finite_check = (a->flags & RANDUTV_FLAG_NO_FINITE_CHECK) == 0;
+  c.max_sweeps = a->jacobi_max_sweeps;
+  c.spin_limit = a->spin_limit;
+  c.max_ws = a->max_workspace_bytes > 0 ? (size_t)a->max_workspace_bytes : 0;
+  return factor_entry(c);
 }
 
 int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const double* T,
@@ -583,6 +747,7 @@ int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const dou
   if (!Ak) return -7;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
+  return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   hipStream_t st = cx.st;
   if (k == 0) {
@@ -606,6 +771,7 @@ int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const dou
   RUTV_CHECK(dgemm(st, false, false, m, n, k, 1.0, U, m, M1, k, 0.0, Ak, m, wk, sk));
   RUTV_TRY(hipStreamSynchronize(st));
   return RANDUTV_OK;
+  });
 }
 
 // HQRRP (Section 2): A P = Q R by blocks of b columns.  Step i (s = i b):
@@ -626,8 +792,10 @@ int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint6
   if (b > n) b = n;
   if (b > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
   if (n > 32768) return RANDUTV_ERR_TOO_LARGE;  // the exchange plan's LDS index arrays
+  if (m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
+  return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   hipStream_t st = cx.st;
   i64 sk = 0;
@@ -677,7 +845,7 @@ int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint6
   pw.xch = xch;
   pw.err = &status[1];
   set_launch_timer(nullptr);
-  RUTV_TRY(hipMemsetAsync(status, 0, 4 * sizeof(int), st));
+  RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(status), 4));
   RUTV_CHECK(check_finite(st, m, n, A, lda, &status[2]));
   {
     int flag = 0;
@@ -710,6 +878,7 @@ int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint6
   RUTV_TRY(hipStreamSynchronize(st));
   if (flags[0] || flags[1]) return RANDUTV_ERR_SYNC;
   return RANDUTV_OK;
+  });
 }
 
 // Forward value of the first-block truncation without the rest of the
@@ -728,9 +897,10 @@ int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t 
   if (!Ak || Ak == A) return -8;
   if (ldak < std::max<int64_t>(1, m)) return -9;
   const i64 k = std::min<i64>(b, n);
-  if (k > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+  if (k > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
+  return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   hipStream_t st = cx.st;
   i64 sk = 0;
@@ -765,7 +935,7 @@ int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t 
                 const double* B_, i64 lb, double beta, double* C_, i64 lc) {
     return dgemm(st, ta, tb, M_, N_, K_, alpha, A_, la, B_, lb, beta, C_, lc, wk, sk);
   };
-  RUTV_TRY(hipMemsetAsync(status, 0, 4 * sizeof(int), st));
+  RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(status), 4));
   RUTV_CHECK(check_finite(st, m, n, A, lda, &status[0]));
   RUTV_CHECK(sketch(st, seed, 0, m, k, M, m));
   for (int j = 0; j <= q; ++j) {
@@ -790,6 +960,7 @@ int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t 
   if (flags[0]) return RANDUTV_ERR_NONFINITE;
   if (flags[1]) return RANDUTV_ERR_SYNC;
   return RANDUTV_OK;
+  });
 }
 
 constexpr int32_t kGradMaxQ = 64;
@@ -820,9 +991,10 @@ static int truncate_grad_impl(int64_t m, int64_t n, const double* A, int64_t lda
   if (!Abar || Abar == A || Abar == Gbar) return -10;
   if (ldab < std::max<int64_t>(1, m)) return -11;
   const i64 k = std::min<i64>(b, n);
-  if (k > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+  if (k > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
+  return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   hipStream_t st = cx.st;
   i64 sk = 0;
@@ -872,7 +1044,7 @@ static int truncate_grad_impl(int64_t m, int64_t n, const double* A, int64_t lda
                 const double* B_, i64 lb, double beta, double* C_, i64 lc) {
     return dgemm(st, ta, tb, M_, N_, K_, alpha, A_, la, B_, lb, beta, C_, lc, wk, sk);
   };
-  RUTV_TRY(hipMemsetAsync(status, 0, 4 * sizeof(int), st));
+  RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(status), 4));
   RUTV_CHECK(check_finite(st, m, n, A, lda, &status[0]));
   RUTV_CHECK(check_finite(st, m, n, Gbar, ldg, &status[0]));
   // M_0 = G(0); Z_j = A^T M_j; M_{j+1} = A Z_j
@@ -919,6 +1091,7 @@ static int truncate_grad_impl(int64_t m, int64_t n, const double* A, int64_t lda
   if (flags[1]) return RANDUTV_ERR_SYNC;
   if (flags[2]) return RANDUTV_ERR_RANK;
   return RANDUTV_OK;
+  });
 }
 
 int randutv_truncate_grad(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
@@ -936,10 +1109,79 @@ int randutv_sketch(uint64_t seed, uint64_t step, int64_t rows, int64_t cols, dou
   if (ldg < std::max<int64_t>(1, rows)) return -6;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
+  return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   set_launch_timer(nullptr);
   RUTV_CHECK(sketch(cx.st, seed, step, rows, cols, G, ldg));
   RUTV_TRY(hipStreamSynchronize(cx.st));
+  return RANDUTV_OK;
+  });
+}
+
+int randutv_sketch_host(uint64_t seed, int64_t m, int64_t n, int64_t b, double* G_host) {
+  if (m < 0) return -2;
+  if (n < 0 || n > m) return -3;
+  if (m == 0 || n == 0) return RANDUTV_OK;
+  if (b < 1) return -4;
+  if (!G_host) return -5;
+  if (b > n) b = n;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  return guarded([&]() -> int {
+    RUTV_CHECK(cx.init());
+    RUTV_CHECK(cx.reserve(sizeof(double) * (size_t)(m * b)));
+    double* G = reinterpret_cast<double*>(cx.ws);
+    set_launch_timer(nullptr);
+    i64 off = 0;
+    for (i64 i = 0, s = 0; s < n; ++i, s += b) {
+      const i64 bi = std::min(b, n - s), mi = m - s;
+      int rc = sketch(cx.st, seed, (uint64_t)i, mi, bi, G, mi);
+      if (rc == RANDUTV_OK) {
+        const hipError_t e =
+            hipMemcpyAsync(G_host + off, G, sizeof(double) * mi * bi, hipMemcpyDeviceToHost, cx.st);
+        if (e == hipSuccess) {
+          const hipError_t e2 = hipStreamSynchronize(cx.st);
+          rc = e2 == hipSuccess ? RANDUTV_OK : hip_code(e2);
+        } else {
+          rc = hip_code(e);
+        }
+      }
+      if (rc != RANDUTV_OK) {
+        cx.drain();
+        return rc;
+      }
+      off += mi * bi;
+    }
+    return RANDUTV_OK;
+  });
+}
+
+int randutv_sketch_words(uint64_t seed, uint64_t step, uint64_t first_block, int64_t nblocks,
+                         uint64_t* out) {
+  if (nblocks < 0) return -4;
+  if (nblocks == 0) return RANDUTV_OK;
+  if (!out) return -5;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  return guarded([&]() -> int {
+    RUTV_CHECK(cx.init());
+    set_launch_timer(nullptr);
+    RUTV_CHECK(sketch_words(cx.st, seed, step, first_block, nblocks, out));
+    RUTV_TRY(hipStreamSynchronize(cx.st));
+    return RANDUTV_OK;
+  });
+}
+
+int randutv_finalize(void) {
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(cx.mu);
+  if (!cx.st) return RANDUTV_OK;
+  int cur = -1;
+  const int dev = cx.device;
+  if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+  if (cur != dev) (void)hipSetDevice(dev);
+  cx.release();
+  if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
   return RANDUTV_OK;
 }
 
@@ -961,6 +1203,7 @@ static int gemm_entry(char transa, char transb, int64_t M, int64_t N, int64_t K,
   if (ldc < std::max<int64_t>(1, M)) return -13;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
+  return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   const i64 sk = dgemm_work_elems(M, N, K);
   RUTV_CHECK(cx.reserve(sizeof(double) * std::max<i64>(sk, 1)));
@@ -969,6 +1212,7 @@ static int gemm_entry(char transa, char transb, int64_t M, int64_t N, int64_t K,
                    reinterpret_cast<double*>(cx.ws), sk, prec));
   RUTV_TRY(hipStreamSynchronize(cx.st));
   return RANDUTV_OK;
+  });
 }
 
 int randutv_dgemm(char transa, char transb, int64_t M, int64_t N, int64_t K, double alpha,
@@ -998,9 +1242,10 @@ int randutv_geqrf(int64_t m, int64_t k, double* A, int64_t lda, double* tau) {
   if (!A) return -3;
   if (lda < std::max<int64_t>(1, m)) return -4;
   if (!tau) return -5;
-  if (k > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+  if (k > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
+  return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   Carver c;
   c.take<unsigned long long>(panel_work_elems(m));
@@ -1012,12 +1257,13 @@ int randutv_geqrf(int64_t m, int64_t k, double* A, int64_t lda, double* tau) {
   pw.xch = r.take<unsigned long long>(panel_work_elems(m));
   pw.err = r.take<int>(4);
   set_launch_timer(nullptr);
-  RUTV_TRY(hipMemsetAsync(pw.err, 0, sizeof(int), cx.st));
+  RUTV_CHECK(fill_zero_u32(cx.st, reinterpret_cast<unsigned*>(pw.err), 1));
   RUTV_CHECK(panel_qr(cx.st, m, k, A, lda, tau, pw));
   int err = 0;
   RUTV_TRY(hipMemcpyAsync(&err, pw.err, sizeof(int), hipMemcpyDeviceToHost, cx.st));
   RUTV_TRY(hipStreamSynchronize(cx.st));
   return err ? RANDUTV_ERR_SYNC : RANDUTV_OK;
+  });
 }
 
 int randutv_larft(int64_t m, int64_t k, const double* W, int64_t ldw, const double* tau,
@@ -1032,6 +1278,7 @@ int randutv_larft(int64_t m, int64_t k, const double* W, int64_t ldw, const doub
   if (ldt < k) return -7;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
+  return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   const i64 sk = dgemm_work_elems(k, k, m);
   Carver c;
@@ -1050,6 +1297,7 @@ int randutv_larft(int64_t m, int64_t k, const double* W, int64_t ldw, const doub
   RUTV_CHECK(larft_from_gram(cx.st, k, G, k, tau, Tf, ldt));
   RUTV_TRY(hipStreamSynchronize(cx.st));
   return RANDUTV_OK;
+  });
 }
 
 int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d, double* Us, double* Vs,
@@ -1064,6 +1312,7 @@ int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d, double* Us
   if (k > kJacobiMaxN) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
+  return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   Carver c;
   c.take<double>(jacobi_work_elems(k));
@@ -1076,7 +1325,7 @@ int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d, double* Us
   set_launch_timer(nullptr);
   {
     int flag = 0;
-    RUTV_TRY(hipMemsetAsync(status, 0, sizeof(int), cx.st));
+    RUTV_CHECK(fill_zero_u32(cx.st, reinterpret_cast<unsigned*>(status), 1));
     RUTV_CHECK(check_finite(cx.st, k, k, R, ldr, status));
     RUTV_TRY(hipMemcpyAsync(&flag, status, sizeof(int), hipMemcpyDeviceToHost, cx.st));
     RUTV_TRY(hipStreamSynchronize(cx.st));
@@ -1089,14 +1338,16 @@ int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d, double* Us
   if (sweeps) *sweeps = hs[0];
   if (hs[2]) return RANDUTV_ERR_SYNC;
   return hs[1] ? RANDUTV_OK : RANDUTV_ERR_NOCONV;
+  });
 }
 
 int randutv_set_timing(int32_t enable) {
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(cx.mu);
-  if (enable < 0 || enable > 2) return -1;
+  if (enable < 0 || enable > 3) return -1;
   cx.timing = enable != 0;
-  cx.timer.gemm_only = enable == 2;
+  cx.timer.gemm_only = enable >= 2;
+  cx.timer.serialize = enable == 3;
   cx.timer.clear_counts();
   return RANDUTV_OK;
 }

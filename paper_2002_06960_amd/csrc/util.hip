@@ -77,6 +77,28 @@ int sketch(hipStream_t st, uint64_t seed, uint64_t step, i64 rows, i64 cols, dou
   return RANDUTV_OK;
 }
 
+// raw generator words of blocks first .. first + nblocks - 1 (for bit-exact
+// checks of the integer stream)
+__global__ __launch_bounds__(256) void sketch_words_kernel(uint64_t seed, uint64_t step,
+                                                           uint64_t first, i64 nblocks,
+                                                           uint64_t* __restrict__ out) {
+  for (i64 j = (i64)blockIdx.x * 256 + threadIdx.x; j < nblocks; j += (i64)gridDim.x * 256) {
+    u64x4 c{{first + (uint64_t)j, 0ull, 0ull, 0ull}};
+    const u64x4 x = philox4x64_10(c, seed, step);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) out[4 * j + w] = x.v[w];
+  }
+}
+
+int sketch_words(hipStream_t st, uint64_t seed, uint64_t step, uint64_t first, i64 nblocks,
+                 uint64_t* out) {
+  if (nblocks <= 0) return RANDUTV_OK;
+  const int blocks = (int)std::min<i64>(cdiv(nblocks, 256), 16384);
+  sketch_words_kernel<<<blocks, 256, 0, st>>>(seed, step, first, nblocks, out);
+  RUTV_TRY(hipGetLastError());
+  return RANDUTV_OK;
+}
+
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void identity_kernel(i64 rows, i64 cols, double* __restrict__ X,
                                                       i64 ldx) {

@@ -1,14 +1,18 @@
 """Python binding of the gfx950 randUTV library (ctypes over include/randutv.h).
 
 Argument marshalling only: every step of the factorization runs in the HIP
-kernels of librandutv.so.  Torch is used for device memory: matrices are
-float64 CUDA (HIP) tensors in column-major layout (stride (1, ld)); inputs in
-another layout are copied to column-major first.  Calls are synchronous: the
-current torch stream is synchronised before the library runs, and outputs are
-ready on return.  A missing or unloadable library raises RuntimeError.
+kernels of librandutv.so.  Torch is used for device memory and streams:
+matrices are float64 CUDA (HIP) tensors in column-major layout (stride
+(1, ld)); inputs in another layout are copied to column-major first.  The
+factorization is ordered on torch's current stream (randutv_factor_ex with
+RANDUTV_FLAG_STREAM): it starts after the work already queued there and the
+work queued there afterwards sees its outputs; the other entry points
+synchronise the current stream first.  Every call returns when its device work
+has finished.  A missing or unloadable library raises RuntimeError.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from typing import Optional, Tuple
@@ -18,13 +22,39 @@ LIB_PATH = os.path.join(_HERE, "librandutv.so")
 
 RANDUTV_OK = 0
 ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONV, ERR_SYNC, ERR_TOO_LARGE, ERR_RANK = 1, 2, 3, 4, 5, 6, 7
+FLAG_G_HOST, FLAG_NO_FINITE_CHECK, FLAG_STREAM = 1, 2, 4
+PRECISION_BITS = (64, 32, 16, 48)
+
+
+class RandutvArgs(ctypes.Structure):
+    """struct randutv_args of include/randutv.h (field for field)."""
+    _fields_ = [("struct_size", ctypes.c_int64), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("b", ctypes.c_int64),
+                ("q", ctypes.c_int32), ("sketch_bits", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64), ("T", ctypes.c_void_p),
+                ("ldt", ctypes.c_int64), ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64),
+                ("stream", ctypes.c_void_p), ("G", ctypes.c_void_p), ("update_bits", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("jacobi_max_sweeps", ctypes.c_int32),
+                ("spin_limit", ctypes.c_uint32), ("max_workspace_bytes", ctypes.c_int64)]
+
+
+def make_args(**kw) -> RandutvArgs:
+    a = RandutvArgs()
+    ctypes.memset(ctypes.byref(a), 0, ctypes.sizeof(a))
+    a.struct_size = ctypes.sizeof(a)
+    for k, v in kw.items():
+        setattr(a, k, v)
+    return a
 
 # name -> (restype, argtypes)
 _I64, _I32, _U64, _D, _P, _C = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double,
                                 ctypes.c_void_p, ctypes.c_char)
 SIGNATURES = {
     "randutv_factor": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P]),
-    "randutv_factor_ex": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P, _I32]),
+    "randutv_factor_ex": (ctypes.c_int, [ctypes.POINTER(RandutvArgs)]),
+    "randutv_sketch_host": (ctypes.c_int, [_U64, _I64, _I64, _I64, _P]),
+    "randutv_sketch_words": (ctypes.c_int, [_U64, _U64, _U64, _I64, _P]),
+    "randutv_finalize": (ctypes.c_int, []),
     "randutv_truncate": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _P]),
     "randutv_truncate_grad": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64, _P, _I64]),
     "randutv_truncate_first_block": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64]),
@@ -82,6 +112,9 @@ def load(path: Optional[str] = None):
         f.argtypes = args
     if path is None:
         _lib = lib
+        # release the library's streams and workspace before the HIP runtime
+        # is torn down at exit
+        atexit.register(lib.randutv_finalize)
     return lib
 
 
@@ -125,52 +158,108 @@ def _sync():
 
 
 # --------------------------------------------------------------------------- API
-def _out(x, rows, cols, device):
+def _check_f64(x, name: str, shape):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(x.shape)}")
+
+
+def _out(x, rows, cols, device, name="output"):
     if x is None:
         return colmajor_empty(rows, cols, device)
-    if (tuple(x.shape) != (rows, cols) or x.stride(0) != 1 or (cols > 1 and x.stride(1) != rows)
-            or x.dtype.itemsize != 8 or not x.is_cuda):
-        raise ValueError(f"output must be a column-major float64 CUDA tensor of shape {(rows, cols)}")
+    _check_f64(x, name, (rows, cols))
+    if x.stride(0) != 1 or (cols > 1 and x.stride(1) != rows):
+        raise ValueError(f"{name} must be column-major with leading dimension {rows}")
     return x
+
+
+def _stream_handle() -> int:
+    """HIP handle of torch's current stream on the current device (0 = null stream)."""
+    torch = _torch()
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def sketch_offsets(m: int, n: int, b: int):
+    """Element offsets of G(0), G(1), ... in the concatenated sketch layout
+    (G(i) of (m - i b) x min(b, n - i b), ld m - i b); the last entry is the total."""
+    b = min(b, n)
+    offs, off, s = [], 0, 0
+    while s < n:
+        offs.append(off)
+        off += (m - s) * min(b, n - s)
+        s += b
+    offs.append(off)
+    return offs
 
 
 def randutv_factor(A, b: int, q: int, seed: int = 0, build_u: bool = True,
                    build_v: bool = True, in_place: bool = False, U=None, T=None, V=None,
-                   sketch_bits: int = 64) -> Tuple:
+                   sketch_bits: int = 64, update_bits: int = 64, G=None,
+                   jacobi_max_sweeps: int = 0, spin_limit: int = 0,
+                   max_workspace_bytes: int = 0, finite_check: bool = True) -> Tuple:
     """A = U T V^T.  Returns (U, T, V) column-major tensors (U/V None if not built).
 
     U, T, V may be given as preallocated column-major outputs.  sketch_bits
-    selects the arithmetic of the sketch and power-iteration products
-    (randutv_factor_ex): 32 the FP32 matrix cores, 16 the BF16 matrix cores,
-    48 three BF16 products of split operands; 64 is the all-FP64
-    randutv_factor."""
+    selects the arithmetic of the sketch and power-iteration products, and
+    update_bits that of the compact-WY updates of T, U and V: 64 the FP64
+    matrix cores, 32 the FP32 matrix cores, 16 the BF16 matrix cores, 48
+    three BF16 products of split operands.  G, if given, holds the caller's
+    sketches in the layout of sketch_offsets: a float64 CUDA tensor, or a
+    numpy float64 array / CPU tensor (host memory).  The call is ordered on
+    torch's current stream."""
+    torch = _torch()
     lib = load()
     A, lda = as_colmajor(A)
     m, n = A.shape
     if in_place and lda == m:
         T = A
     else:
-        T = _out(T, m, n, A.device)
-    U = _out(U, m, m, A.device) if build_u else None
-    V = _out(V, n, n, A.device) if build_v else None
-    _sync()
-    if sketch_bits == 64:
-        _check("randutv_factor", lib.randutv_factor(m, n, _ptr(A), lda, b, q, seed & (2**64 - 1),
-                                                    _ptr(U), _ptr(T), _ptr(V)))
-    else:
-        _check("randutv_factor_ex", lib.randutv_factor_ex(m, n, _ptr(A), lda, b, q,
-                                                          seed & (2**64 - 1), _ptr(U), _ptr(T),
-                                                          _ptr(V), sketch_bits))
+        T = _out(T, m, n, A.device, "T")
+    U = _out(U, m, m, A.device, "U") if build_u else None
+    V = _out(V, n, n, A.device, "V") if build_v else None
+    flags = FLAG_STREAM | (0 if finite_check else FLAG_NO_FINITE_CHECK)
+    gptr, keep = 0, None
+    if G is not None:
+        total = sketch_offsets(m, n, b)[-1]
+        if isinstance(G, torch.Tensor) and G.is_cuda:
+            if G.dtype != torch.float64 or G.numel() != total or not G.is_contiguous():
+                raise ValueError(f"G must be a contiguous float64 tensor of {total} elements")
+            gptr = G.data_ptr()
+        else:
+            import numpy as np
+            keep = np.ascontiguousarray(G.numpy() if isinstance(G, torch.Tensor) else G,
+                                        dtype=np.float64).reshape(-1)
+            if keep.size != total:
+                raise ValueError(f"G must hold {total} elements")
+            gptr = keep.ctypes.data
+            flags |= FLAG_G_HOST
+    args = make_args(m=m, n=n, A=_ptr(A), lda=lda, b=b, q=q, seed=seed & (2**64 - 1),
+                     U=_ptr(U), ldu=m, T=_ptr(T), ldt=m, V=_ptr(V), ldv=n,
+                     stream=_stream_handle() if m and n else 0, G=gptr,
+                     sketch_bits=sketch_bits, update_bits=update_bits, flags=flags,
+                     jacobi_max_sweeps=jacobi_max_sweeps, spin_limit=spin_limit,
+                     max_workspace_bytes=max_workspace_bytes)
+    _check("randutv_factor_ex", lib.randutv_factor_ex(ctypes.byref(args)))
+    del keep
     return U, T, V
 
 
 def randutv_truncate(U, T, V, k: int):
     """A_k = U(:, :k) T(:k, :) V^T."""
     lib = load()
+    if T.dim() != 2:
+        raise ValueError("T must be a matrix")
     m, n = T.shape
+    _check_f64(U, "U", (m, m))
+    _check_f64(T, "T", (m, n))
+    _check_f64(V, "V", (n, n))
     for x, ld in ((U, m), (T, m), (V, n)):
         if x.stride(0) != 1 or (x.shape[1] > 1 and x.stride(1) != ld):
             raise ValueError("randutv_truncate expects the column-major outputs of randutv_factor")
+    if not 0 <= k <= n:
+        raise ValueError(f"k must lie in [0, {n}]")
     Ak = colmajor_empty(m, n, T.device)
     _sync()
     _check("randutv_truncate", lib.randutv_truncate(m, n, k, _ptr(U), _ptr(T), _ptr(V), _ptr(Ak)))
@@ -283,6 +372,30 @@ def randutv_sketch(seed: int, step: int, rows: int, cols: int, device=None):
     return G
 
 
+def randutv_sketch_host(seed: int, m: int, n: int, b: int):
+    """Every sketch G(0), ..., G(p-1) of a factorization with these sizes, as a
+    host numpy float64 array in the concatenated layout (sketch_offsets)."""
+    import numpy as np
+    lib = load()
+    G = np.empty(max(1, sketch_offsets(m, n, b)[-1]) if m and n else 1, dtype=np.float64)
+    _check("randutv_sketch_host", lib.randutv_sketch_host(seed & (2**64 - 1), m, n, b,
+                                                          G.ctypes.data))
+    return G[: sketch_offsets(m, n, b)[-1]] if m and n else G[:0]
+
+
+def randutv_sketch_words(seed: int, step: int, first_block: int, nblocks: int, device=None):
+    """Raw Philox4x64-10 words of blocks first_block .. first_block + nblocks - 1
+    of the (seed, step) stream, as a host numpy uint64 array (nblocks, 4)."""
+    import numpy as np
+    torch = _torch()
+    lib = load()
+    out = torch.empty(4 * max(nblocks, 1), dtype=torch.int64, device=device or "cuda")
+    _sync()
+    _check("randutv_sketch_words", lib.randutv_sketch_words(seed & (2**64 - 1), step, first_block,
+                                                            nblocks, _ptr(out)))
+    return out.cpu().numpy().view(np.uint64)[: 4 * nblocks].reshape(nblocks, 4)
+
+
 def randutv_dgemm(transa: str, transb: str, alpha: float, A, B, beta: float = 0.0, C=None,
                   f32: bool = False, bf16_terms: int = 0):
     """C = alpha op(A) op(B) + beta C (FP64 MFMA kernels; f32: FP64 operands and
@@ -295,11 +408,14 @@ def randutv_dgemm(transa: str, transb: str, alpha: float, A, B, beta: float = 0.
     M = A.shape[1] if transa in "Tt" else A.shape[0]
     K = A.shape[0] if transa in "Tt" else A.shape[1]
     N = B.shape[0] if transb in "Tt" else B.shape[1]
+    if (B.shape[1] if transb in "Tt" else B.shape[0]) != K:
+        raise ValueError("inner dimensions of op(A) and op(B) differ")
     if C is None:
         C = colmajor_empty(M, N, A.device)
         ldc = max(1, M)
     else:
-        if C.stride(0) != 1:
+        _check_f64(C, "C", (M, N))
+        if C.stride(0) != 1 or (N > 1 and C.stride(1) < M):
             raise ValueError("C must be column-major")
         ldc = max(1, C.stride(1) if N > 1 else M)
     _sync()
@@ -352,10 +468,11 @@ def randutv_gesvj(R):
     return Us, d, Vs, sw.value
 
 
-def randutv_set_timing(enable, gemm_only: bool = False):
+def randutv_set_timing(enable, gemm_only: bool = False, serialize_gemm: bool = False):
     """Per-launch HIP-event timing of later randutv_factor calls (all kernel
-    classes, or the GEMM launches only)."""
-    mode = (2 if gemm_only else 1) if enable else 0
+    classes, or the GEMM launches only; serialize_gemm: the GEMM launches only,
+    each run alone on the chip)."""
+    mode = (3 if serialize_gemm else 2 if gemm_only else 1) if enable else 0
     _check("randutv_set_timing", load().randutv_set_timing(mode))
 
 

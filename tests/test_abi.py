@@ -69,9 +69,7 @@ def test_argument_validation_without_device_work():
     assert lib.randutv_sketch(0, 0, -1, 3, P, 1) == -3
     assert lib.randutv_sketch(0, 0, 4, 3, P, 2) == -6
     assert lib.randutv_larft(5, 6, P, 5, P, P, 6) == -2
-    fx = lib.randutv_factor_ex
-    assert fx(5, 3, P, 5, 2, 0, 0, None, P, None, 8) == -11      # unknown sketch precision
-    assert fx(5, 3, P, 4, 2, 0, 0, None, P, None, 32) == -4
+    assert f(40000, 64, P, 40000, 64, 0, 0, None, P, None) == rb.ERR_TOO_LARGE   # m > 32768
     g32 = lib.randutv_gemm_f32
     assert g32(b"N", b"Q", 1, 1, 1, 1.0, P, 1, P, 1, 0.0, P, 1) == -2
     assert g32(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 3) == -13
@@ -105,12 +103,87 @@ def test_argument_validation_without_device_work():
     assert hq(5, 3, P, 5, 2, 0, P, None) == -8
     assert hq(600, 600, P, 600, 300, 0, P, P) == rb.ERR_TOO_LARGE
     assert hq(40000, 40000, P, 40000, 64, 0, P, P) == rb.ERR_TOO_LARGE    # n > 32768
-    assert lib.randutv_set_timing(3) == -1
+    assert lib.randutv_set_timing(4) == -1
     assert lib.randutv_set_timing(0) == 0
     g16 = lib.randutv_gemm_bf16
     assert g16(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 4, 2) == -14   # one or three terms
     assert g16(b"X", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 4, 3) == -1
     assert g16(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 3, 1) == -13
+
+
+def _fx(**kw):
+    """randutv_factor_ex on a 5 x 3 problem with fake (never dereferenced) pointers."""
+    base = dict(m=5, n=3, A=0x1000, lda=5, b=2, q=0, T=0x2000)
+    base.update(kw)
+    a = rb.make_args(**base)
+    return pkg.load().randutv_factor_ex(ctypes.byref(a))
+
+
+def test_factor_ex_argument_checks_without_device_work():
+    lib = pkg.load()
+    assert lib.randutv_factor_ex(None) == -15
+    small = rb.make_args(m=5, n=3, A=0x1000, lda=5, b=2, T=0x2000)
+    small.struct_size = 8
+    assert lib.randutv_factor_ex(ctypes.byref(small)) == -15       # an older, smaller structure
+    assert _fx(m=-1) == -1
+    assert _fx(n=6) == -2
+    assert _fx(A=None) == -3
+    assert _fx(lda=4) == -4
+    assert _fx(b=0) == -5
+    assert _fx(q=-1) == -6
+    assert _fx(U=0x3000, ldu=4) == -8                              # ldu < m
+    assert _fx(U=0x2000) == -8                                     # U aliases T
+    assert _fx(T=None) == -9
+    assert _fx(ldt=4) == -9
+    assert _fx(T=0x1000, ldt=6, lda=5) == -9                       # in place needs ldt == lda
+    assert _fx(V=0x3000, ldv=2) == -10                             # ldv < n
+    assert _fx(V=0x2000) == -10
+    assert _fx(sketch_bits=8) == -11
+    assert _fx(update_bits=24) == -12
+    assert _fx(flags=64) == -13                                    # unknown flag
+    assert _fx(flags=rb.FLAG_G_HOST) == -13                        # host G flag without G
+    assert _fx(jacobi_max_sweeps=-1) == -14
+    assert _fx(jacobi_max_sweeps=1001) == -14
+    assert _fx(b=300, m=600, n=600, lda=600) == rb.ERR_TOO_LARGE
+    assert _fx(m=40000, lda=40000, n=64, b=64) == rb.ERR_TOO_LARGE
+    assert _fx(m=0, n=0, A=None, T=None) == 0                      # empty: no-op
+
+
+def test_factor_ex_leading_dimensions_pass_validation():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible: the fake pointers below would reach a kernel")
+    # leading dimensions above the minimum pass validation and then fail on the
+    # missing device, never on the arguments
+    assert _fx(U=0x3000, ldu=7, ldt=9, V=0x4000, ldv=5) == rb.ERR_HIP
+
+
+def test_sketch_export_argument_checks():
+    lib = pkg.load()
+    P = ctypes.c_void_p(0x1000)
+    assert lib.randutv_sketch_host(0, -1, 1, 1, P) == -2
+    assert lib.randutv_sketch_host(0, 3, 5, 1, P) == -3
+    assert lib.randutv_sketch_host(0, 5, 3, 0, P) == -4
+    assert lib.randutv_sketch_host(0, 5, 3, 2, None) == -5
+    assert lib.randutv_sketch_host(0, 0, 0, 2, None) == 0
+    assert lib.randutv_sketch_words(0, 0, 0, -1, P) == -4
+    assert lib.randutv_sketch_words(0, 0, 0, 3, None) == -5
+    assert lib.randutv_sketch_words(0, 0, 0, 0, None) == 0
+
+
+def test_sketch_offsets_layout():
+    # G(i) is (m - i b) x min(b, n - i b), one after the other
+    offs = pkg.sketch_offsets(10, 7, 3)
+    assert offs == [0, 30, 30 + 21, 30 + 21 + 4]
+    assert pkg.sketch_offsets(12000, 12000, 256)[-1] == sum((12000 - 256 * i) * min(256, 12000 - 256 * i)
+                                                           for i in range(47))
+
+
+def test_binding_validates_tensors_before_the_call():
+    import torch
+    x = torch.zeros(4, 3, dtype=torch.float64)     # a CPU tensor: rejected before any ABI call
+    with pytest.raises(TypeError):
+        pkg.randutv_truncate(x, x, x, 1)
 
 
 def test_b_above_kernel_limit_is_reported():

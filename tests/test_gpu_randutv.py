@@ -159,8 +159,14 @@ def test_config2_parity(kind):
     """4000 x 4000, b = 128, q = 2 for the three spectra."""
     A = make_matrix(kind, 4000, seed=0)
     Th, To, rows = check_against_oracle(A, 128, 2, 0)
-    # the leading block is always determined by the input
-    assert rows >= 128
+    # every row of T is determined by the input for the exp and iid spectra;
+    # for the step spectrum (400 unit singular values, the rest 1e-6 plus
+    # 1e-10 noise) the oracle reproduces the first three blocks under a
+    # last-bit perturbation of A (the rest is chosen by rounding)
+    if kind == "step":
+        assert rows >= 384
+    else:
+        assert rows == 4000
 
 
 @pytest.mark.parametrize("m,n", [(12000, 12000), (16000, 8000)])

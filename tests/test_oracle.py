@@ -343,3 +343,72 @@ def test_pins_catch_planted_mistakes(monkeypatch):
     monkeypatch.setattr(ro, "jacobi_svd", lambda R, **k: (lambda u, d, v, s, c: (v, d, u, s, c))(*orig_j(R)))
     assert res_of()[0] > 1e-6
     monkeypatch.setattr(ro, "jacobi_svd", orig_j)
+
+
+# ----------------------------------------------------------------------------
+# brute-force pin of the b x b SVD and of the single-step factorization
+# ----------------------------------------------------------------------------
+def _brute_force_singular_values(A):
+    """Singular values of a tiny matrix as the n largest eigenvalues of the
+    symmetric matrix [[0, A], [A^T, 0]] (its eigenvalues are +-sigma_i and
+    zeros), found by the classical cyclic two-sided Jacobi eigenvalue method
+    (symmetric 2 x 2 Schur rotations; Golub & Van Loan, Matrix Computations,
+    Section 8.5) in plain Python loops.  Shares nothing with the oracle's
+    one-sided Jacobi and does not square A."""
+    m, n = A.shape
+    N = m + n
+    S = [[0.0] * N for _ in range(N)]
+    for i in range(m):
+        for j in range(n):
+            S[i][m + j] = S[m + j][i] = float(A[i, j])
+    total = sum(S[i][j] ** 2 for i in range(N) for j in range(N))
+    for _ in range(60):
+        off = sum(S[i][j] ** 2 for i in range(N) for j in range(N) if i != j)
+        if off <= 1e-30 * total:
+            break
+        for p in range(N - 1):
+            for q in range(p + 1, N):
+                apq = S[p][q]
+                if apq == 0.0:
+                    continue
+                th = (S[q][q] - S[p][p]) / (2.0 * apq)
+                t = (1.0 if th >= 0.0 else -1.0) / (abs(th) + math.sqrt(1.0 + th * th))
+                c = 1.0 / math.sqrt(1.0 + t * t)
+                s = t * c
+                for k in range(N):
+                    a, b = S[k][p], S[k][q]
+                    S[k][p], S[k][q] = c * a - s * b, s * a + c * b
+                for k in range(N):
+                    a, b = S[p][k], S[q][k]
+                    S[p][k], S[q][k] = c * a - s * b, s * a + c * b
+    return np.array(sorted((S[i][i] for i in range(N)), reverse=True)[:n])
+
+
+@pytest.mark.parametrize("n,kind", [(1, "iid"), (2, "iid"), (5, "iid"), (9, "graded"), (16, "iid"),
+                                    (16, "graded")])
+def test_jacobi_svd_against_brute_force(n, kind):
+    """The oracle's one-sided Jacobi singular values equal the brute-force
+    two-sided Jacobi ones on tiny triangular blocks (as the b x b step sees them)."""
+    rng = np.random.default_rng(40 + n)
+    R = np.triu(rng.standard_normal((n, n)))
+    if kind == "graded":
+        R = R * np.logspace(0, -6, n)[None, :]
+    _, d, _, _, ok = ro.jacobi_svd(R)
+    assert ok
+    sv = _brute_force_singular_values(R)
+    np.testing.assert_allclose(d, sv, rtol=0, atol=1e-13 * sv[0])
+
+
+@pytest.mark.parametrize("m,n,kind", [(12, 9, "iid"), (16, 16, "log8"), (7, 5, "exp"), (16, 13, "iid")])
+def test_single_step_diag_T_against_brute_force(m, n, kind):
+    """b >= n: one step, and |diag T| is the singular values of A; on tiny
+    inputs they equal the brute-force ones.  With b < n the first block's
+    |T_jj| interlace below sigma_j."""
+    A = make_matrix(kind, m, n, seed=2)
+    sv = _brute_force_singular_values(A)
+    _, T, _ = ro.randutv(A, n + 3, 2, 0)
+    np.testing.assert_allclose(np.abs(np.diag(T)), sv, rtol=0, atol=1e-13 * sv[0])
+    b = max(1, n // 3)
+    _, T2, _ = ro.randutv(A, b, 1, 0)
+    d0 = np.abs(np.diag(T2))[:b]
+    assert np.all(d0 <= sv[:b] * (1 + 1e-12) + 1e-15 * sv[0])
