@@ -69,3 +69,19 @@ def stable_rows(T1: np.ndarray, T2: np.ndarray, nA: float, b: int, tol: float = 
             break
         r = e
     return m if r >= n else r
+
+
+def block_sensitivity(T1: np.ndarray, T2: np.ndarray, nA: float, b: int) -> np.ndarray:
+    """Per b x b block of T, ||T1 - T2||_F / ||A||_F for two oracle runs on
+    ulp-perturbed inputs: how far the input itself determines that block.
+    Diagonal blocks (singular values of a projected block) are determined to
+    ~u; off-diagonal blocks depend on the chosen bases of the sketched
+    subspaces and move with cond(Y) * u, where Y is the powered sketch."""
+    m, n = T1.shape
+    nb_r, nb_c = -(-m // b), -(-n // b)
+    out = np.zeros((nb_r, nb_c))
+    for i in range(nb_r):
+        for j in range(nb_c):
+            d = T1[i * b:(i + 1) * b, j * b:(j + 1) * b] - T2[i * b:(i + 1) * b, j * b:(j + 1) * b]
+            out[i, j] = np.linalg.norm(d) / nA
+    return out

@@ -8,10 +8,16 @@ act on columns and rows past kb), and for j <= kb the norm of T(j:m, :) is
 final as well (later steps apply orthogonal transforms within those rows and
 columns), so
 
-  * S T_gpu(0:r, 0:1024) S against T_ora(0:r, 0:1024) to 1e-11 ||A||_F, where
-    r <= 1024 is the number of leading rows that a second oracle run on A
-    perturbed in its last bits reproduces to 1e-12 ||A||_F (the rows the input
-    determines; S aligns the sign of each (u_j, v_j) pair);
+  * S T_gpu(0:1024, 0:1024) S against T_ora(0:1024, 0:1024) to 1e-11 ||A||_F
+    over the b x b blocks that the input determines: every block that a
+    second oracle run on A perturbed in its last bits reproduces to
+    1e-12 ||A||_F (S aligns the sign of each (u_j, v_j) pair).  Other blocks
+    move with cond(Y) u, where Y = (A^T A)^q A^T G is the powered sketch
+    (about (1/0.99^256)^5 ~ 4e5 on the exp spectrum; on the step spectrum
+    the sketch of the 1e-6 part is rank deficient and blocks past the first
+    move by up to 1e-9 |A|): several results are correct there, and the GPU
+    block may differ from the oracle's by at most 10x the oracle's own
+    movement;
   * ||A - A_k||_F / ||A||_F for k = 64, 256, 1024 from the GPU's U, T, V
     (randutv_truncate) against ||T_ora(k:m, :)||_F / ||A||_F to 1e-11;
   * every diagonal b x b block of the GPU's T exactly diagonal, non-negative
@@ -23,12 +29,14 @@ import pytest
 import paper_2002_06960_amd as pkg
 from oracle import randutv_oracle as ro
 from randutv_inputs import make_matrix_device
-from gpu_util import diag_blocks_ok, invariants_dev, sign_align, stable_rows, to_host
+from gpu_util import block_sensitivity, diag_blocks_ok, invariants_dev, sign_align, to_host
 
 pytestmark = pytest.mark.gpu
 
 B, Q, SEED, STEPS = 256, 2, 0, 4
 TOL = 1e-11
+SENS = 1e-12  # blocks the input fixes to 10x below the gate
+SPREAD = 10.0  # GPU deviation allowed on the other blocks, in units of the oracle's ulp movement
 
 
 def _perturbed(A, seed=123):
@@ -64,16 +72,28 @@ def test_headline_parity_against_oracle_steps(m, n, kind):
     print(f"headline parity {m}x{n} {kind}: oracle, {STEPS} steps (and a perturbed rerun)", flush=True)
     _, To, Vo = ro.randutv(Ah, B, Q, SEED, build_u=False, max_steps=STEPS)
     _, To2, _ = ro.randutv(_perturbed(Ah), B, Q, SEED, build_u=False, build_v=False, max_steps=STEPS)
-    rows = stable_rows(To[:kb, :kb], To2[:kb, :kb], nA, B)
-    rows = min(rows, kb)
+    sens = block_sensitivity(To[:kb, :kb], To2[:kb, :kb], nA, B)
     Ts, flips = sign_align(Th[:kb, :kb], Vh, Vo[:, :kb])
-    diff = np.linalg.norm(Ts[:rows] - To[:rows, :kb]) / nA if rows else 0.0
+    dev = block_sensitivity(Ts, To[:kb, :kb], nA, B)
     ora_err = {k: np.linalg.norm(To[k:, :]) / nA for k in (64, 256, 1024)}
-    print(f"headline parity {m}x{n} {kind}: stable rows {rows} of {kb}, |S T S - T_ora| / |A| = "
-          f"{diff:.2e}, sign flips {flips}, residual {res:.2e}; rank-k errors (gpu, oracle): "
-          + ", ".join(f"k={k}: {gpu_err[k]:.12e} / {ora_err[k]:.12e}" for k in gpu_err), flush=True)
-    # the leading block is determined by the input on every spectrum here
-    assert rows >= B
-    assert diff <= TOL, (diff, rows, flips)
+    print(f"headline parity {m}x{n} {kind}: sign flips {flips}, residual {res:.2e}; rank-k errors "
+          "(gpu / oracle): " + ", ".join(f"k={k}: {gpu_err[k]:.12e} / {ora_err[k]:.12e}" for k in gpu_err),
+          flush=True)
+    nbk = kb // B
+    for i in range(nbk):
+        print("  block row %d: |gpu - oracle| / |A| = %s; oracle ulp sensitivity = %s" % (
+            i, " ".join(f"{dev[i, j]:.1e}" for j in range(nbk)),
+            " ".join(f"{sens[i, j]:.1e}" for j in range(nbk))), flush=True)
+    # the gate covers every block that the input fixes to 10x below it; the
+    # others (where the oracle itself moves by more than 1e-12 |A| under a
+    # last-bit change of A) may differ by a few times the oracle's own
+    # movement: the GPU's rounding acts like a perturbation of A of a few ulps
+    gated = sens <= SENS
+    diff = np.sqrt(np.sum(dev[gated] ** 2))
+    print(f"headline parity {m}x{n} {kind}: {int(gated.sum())} of {nbk * nbk} blocks gated, "
+          f"|S T S - T_ora| / |A| over them = {diff:.2e}", flush=True)
+    assert gated[0, 0], sens[0, 0]  # the leading block is determined on every spectrum here
+    assert diff <= TOL, (diff, flips)
+    assert np.all(dev[~gated] <= SPREAD * sens[~gated]), (dev[~gated], sens[~gated])
     for k in (64, 256, 1024):
         assert abs(gpu_err[k] - ora_err[k]) <= TOL, (k, gpu_err[k], ora_err[k])
