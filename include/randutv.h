@@ -35,6 +35,7 @@ extern "C" {
 #define RANDUTV_ERR_SYNC 5         /* a multi-workgroup kernel's bounded wait expired */
 #define RANDUTV_ERR_TOO_LARGE 6    /* a dimension exceeds a documented kernel limit */
 #define RANDUTV_ERR_RANK 7         /* the first block's sketch is rank deficient */
+#define RANDUTV_ERR_SCRATCH 8      /* beyond the fixed scratch of randutv_factor_noalloc */
 
 /*
  * randutv_factor -- A = U T V^T (Section 3.1, Figure 2).
@@ -165,6 +166,31 @@ typedef struct randutv_args {
   int64_t max_workspace_bytes;
 } randutv_args;
 int randutv_factor_ex(const randutv_args* args);
+
+/*
+ * randutv_factor_noalloc -- randutv_factor_ex for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same factorization and kernels, with
+ * every temporary carved out of a fixed device array of
+ * RANDUTV_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs
+ * on until the process ends.  The call makes no hipMalloc, hipFree or other
+ * allocating call (the library's first call on a device still creates its
+ * streams and events).  Arguments as randutv_factor_ex, except that
+ * max_workspace_bytes must be 0.  The split-K partial sums get what the
+ * fixed scratch leaves, so a large problem may use fewer K splits than
+ * randutv_factor_ex (same arithmetic per split, different summation order).
+ * What fits: about 4096 x 4096 at b = 128 or 2048 x 2048 at b = 256 with U
+ * and V built; a problem whose other temporaries exceed the scratch returns
+ * RANDUTV_ERR_SCRATCH before any device work.  Every call on a GPU shares
+ * that GPU's scratch and leaves the last call's contents in it (each call
+ * clears what must start at zero).  Two calls whose device work overlapped
+ * on one GPU would race on it; the library prevents that within a process
+ * (calls take one lock and return only after their device work has ended).
+ * Errors: as randutv_factor_ex (-15 also for max_workspace_bytes != 0);
+ * RANDUTV_ERR_SCRATCH.
+ */
+#define RANDUTV_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int randutv_factor_noalloc(const randutv_args* args);
 
 /*
  * randutv_sketch_host -- every sketch G(0), ..., G(p-1) that randutv_factor

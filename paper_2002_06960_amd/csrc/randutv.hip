@@ -135,9 +135,18 @@ constexpr int kWyBuf = RUTV_WY_BUFFERS;
 static_assert(kWyBuf >= 2 && kWyBuf - 2 < kEvRing, "an awaited event must not be re-recorded first");
 enum { EV_V = 0, EV_COLS, EV_U, EV_UV, EV_PRE, EV_WV, EV_WU, EV_KINDS };
 
+// Device scratch of the allocation-free factorization entry point: file-scope
+// device memory, one copy per GPU, resolved to a device address per device
+// at set-up (host code never passes the array's name to a kernel).
+static __device__ __align__(256) char scratch[RANDUTV_NOALLOC_SCRATCH_BYTES];
+
+// one library lock: calls are serialized across threads and devices (the
+// launch timer is process-wide)
+static std::mutex g_mu;
+
 struct Context {
-  std::mutex mu;
   int device = -1;
+  char* scratch_ptr = nullptr;  // this device's copy of `scratch`
   hipStream_t st = nullptr;  // == streams[ST_T]
   hipStream_t streams[NSTREAMS] = {};
   hipEvent_t ev[EV_KINDS][kEvRing] = {};
@@ -148,21 +157,13 @@ struct Context {
   EventTimer timer;
   std::vector<int> sweeps;
 
+  // set-up on the current device (each device has a Context of its own)
   int init() {
     int dev = 0;
     RUTV_TRY(hipGetDevice(&dev));
-    if (st && dev == device) return RANDUTV_OK;
-    if (st) {
-      for (auto& x : streams) (void)hipStreamDestroy(x);
-      for (auto& kind : ev)
-        for (auto& e : kind) (void)hipEventDestroy(e);
-      for (auto& e : ev_misc) (void)hipEventDestroy(e);
-      st = nullptr;
-      if (ws) (void)hipFree(ws);
-      ws = nullptr;
-      ws_bytes = 0;
-    }
+    if (st) return RANDUTV_OK;
     device = dev;
+    RUTV_TRY(hipGetSymbolAddress(reinterpret_cast<void**>(&scratch_ptr), HIP_SYMBOL(scratch)));
     // Streams created with a CU mask (here: every CU) get a hardware queue of
     // their own; pooled streams share the few queues a process has by default,
     // and a long kernel (a batch of Jacobi SVDs) then holds up every kernel of
@@ -201,6 +202,7 @@ struct Context {
     st = nullptr;
     for (auto& x : streams) x = nullptr;
     device = -1;
+    scratch_ptr = nullptr;
   }
   // wait for everything the library enqueued (used before returning an error,
   // so that no kernel of a failed call keeps running on the caller's buffers)
@@ -227,9 +229,14 @@ struct Context {
   }
 };
 
+constexpr int kMaxDevices = 64;
+static Context g_ctx[kMaxDevices];
+
+// the current device's library state
 static Context& ctx() {
-  static Context c;
-  return c;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+  return g_ctx[dev];
 }
 
 // carve aligned regions out of one allocation
@@ -312,10 +319,14 @@ static i64 splitk_need(i64 m, i64 n, i64 b, int q, bool wantU, bool wantV) {
   return need;
 }
 
-static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wantU, bool wantV) {
+// sk_cap >= 0 bounds each stream's split-K partial space (in doubles); the
+// GEMMs then take as many K splits as fit (none when it is 0)
+static size_t layout(Carver& c, FactorWS& w, i64 m, i64 n, i64 b, int q, bool wantU, bool wantV,
+                     i64 sk_cap = -1) {
   const i64 nsteps = cdiv(n, b);
   const i64 mx = std::max(m, n);
-  const i64 sk = splitk_need(m, n, b, q, wantU, wantV);
+  i64 sk = splitk_need(m, n, b, q, wantU, wantV);
+  if (sk_cap >= 0) sk = std::min(sk, sk_cap);
   for (int t = 0; t < NSTREAMS; ++t) {
     StreamWS& x = w.sw[t];
     x.splitk_elems = sk;
@@ -405,6 +416,7 @@ struct FactorCfg {
   int max_sweeps = 0;            // Jacobi sweep cap (0: default)
   unsigned spin_limit = 0;       // bounded waits (0: default)
   size_t max_ws = 0;             // workspace cap (0: none)
+  bool noalloc = false;          // carve the workspace out of the device's `scratch`
 };
 
 static int factor_run(const FactorCfg& c, Context& cx);
@@ -433,13 +445,29 @@ static int factor_run(const FactorCfg& c, Context& cx) {
   const i64 b_last = n - (nsteps - 1) * b;
 
   FactorWS w{};
-  Carver probe;
-  const size_t bytes = layout(probe, w, m, n, b, q, wantU, wantV);
-  if (c.max_ws && bytes > c.max_ws) return RANDUTV_ERR_NOMEM;
-  RUTV_CHECK(cx.reserve(bytes));
   Carver real;
-  real.base = cx.ws;
-  layout(real, w, m, n, b, q, wantU, wantV);
+  i64 sk_cap = -1;
+  if (c.noalloc) {
+    // the fixed scratch: everything but the split-K partials must fit; the
+    // partials get what is left (fewer K splits, same arithmetic per split)
+    constexpr size_t cap = RANDUTV_NOALLOC_SCRATCH_BYTES;
+    Carver p0, pf;
+    const size_t fixed = layout(p0, w, m, n, b, q, wantU, wantV, 0);
+    if (fixed > cap) return RANDUTV_ERR_SCRATCH;
+    if (layout(pf, w, m, n, b, q, wantU, wantV) > cap)
+      sk_cap = std::max<i64>(0, (i64)((cap - fixed) / (NSTREAMS * sizeof(double))) - 64);
+    Carver pc;
+    if (layout(pc, w, m, n, b, q, wantU, wantV, sk_cap) > cap) return RANDUTV_ERR_SCRATCH;
+    if (!cx.scratch_ptr) return RANDUTV_ERR_HIP;
+    real.base = cx.scratch_ptr;
+  } else {
+    Carver probe;
+    const size_t bytes = layout(probe, w, m, n, b, q, wantU, wantV);
+    if (c.max_ws && bytes > c.max_ws) return RANDUTV_ERR_NOMEM;
+    RUTV_CHECK(cx.reserve(bytes));
+    real.base = cx.ws;
+  }
+  layout(real, w, m, n, b, q, wantU, wantV, sk_cap);
   for (auto& x : w.sw) {
     x.pw.err = &w.status[1];
     x.pw.spin_limit = c.spin_limit;
@@ -697,8 +725,7 @@ static int check_factor(const FactorCfg& c) {
 static int factor_entry(const FactorCfg& c) {
   const int rc = check_factor(c);
   if (rc != RANDUTV_OK || c.m == 0 || c.n == 0) return rc;
-  Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return guarded([&] { return factor_impl(c); });
 }
 
@@ -710,9 +737,7 @@ int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
   return factor_entry(c);
 }
 
-int randutv_factor_ex(const randutv_args* a) {
-  if (!a || a->struct_size < (int64_t)sizeof(randutv_args)) return -15;
-  FactorCfg c;
+static int cfg_from_args(const randutv_args* a, FactorCfg& c) {
   c.m = a->m, c.n = a->n, c.A = a->A, c.lda = a->lda, c.b = a->b, c.q = a->q, c.seed = a->seed;
   c.U = a->U, c.T = a->T, c.V = a->V;
   c.ldu = a->ldu ? a->ldu : a->m;
@@ -732,6 +757,24 @@ int randutv_factor_ex(const randutv_args* a) {
   c.max_sweeps = a->jacobi_max_sweeps;
   c.spin_limit = a->spin_limit;
   c.max_ws = a->max_workspace_bytes > 0 ? (size_t)a->max_workspace_bytes : 0;
+  return RANDUTV_OK;
+}
+
+int randutv_factor_ex(const randutv_args* a) {
+  if (!a || a->struct_size < (int64_t)sizeof(randutv_args)) return -15;
+  FactorCfg c;
+  const int rc = cfg_from_args(a, c);
+  if (rc != RANDUTV_OK) return rc;
+  return factor_entry(c);
+}
+
+int randutv_factor_noalloc(const randutv_args* a) {
+  if (!a || a->struct_size < (int64_t)sizeof(randutv_args)) return -15;
+  if (a->max_workspace_bytes != 0) return -15;
+  FactorCfg c;
+  const int rc = cfg_from_args(a, c);
+  if (rc != RANDUTV_OK) return rc;
+  c.noalloc = true;
   return factor_entry(c);
 }
 
@@ -746,7 +789,7 @@ int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const dou
   if (!V) return -6;
   if (!Ak) return -7;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   hipStream_t st = cx.st;
@@ -794,7 +837,7 @@ int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint6
   if (n > 32768) return RANDUTV_ERR_TOO_LARGE;  // the exchange plan's LDS index arrays
   if (m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   hipStream_t st = cx.st;
@@ -899,7 +942,7 @@ int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t 
   const i64 k = std::min<i64>(b, n);
   if (k > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   hipStream_t st = cx.st;
@@ -993,7 +1036,7 @@ static int truncate_grad_impl(int64_t m, int64_t n, const double* A, int64_t lda
   const i64 k = std::min<i64>(b, n);
   if (k > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   hipStream_t st = cx.st;
@@ -1108,7 +1151,7 @@ int randutv_sketch(uint64_t seed, uint64_t step, int64_t rows, int64_t cols, dou
   if (!G) return -5;
   if (ldg < std::max<int64_t>(1, rows)) return -6;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   set_launch_timer(nullptr);
@@ -1126,7 +1169,7 @@ int randutv_sketch_host(uint64_t seed, int64_t m, int64_t n, int64_t b, double* 
   if (!G_host) return -5;
   if (b > n) b = n;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return guarded([&]() -> int {
     RUTV_CHECK(cx.init());
     RUTV_CHECK(cx.reserve(sizeof(double) * (size_t)(m * b)));
@@ -1162,7 +1205,7 @@ int randutv_sketch_words(uint64_t seed, uint64_t step, uint64_t first_block, int
   if (nblocks == 0) return RANDUTV_OK;
   if (!out) return -5;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return guarded([&]() -> int {
     RUTV_CHECK(cx.init());
     set_launch_timer(nullptr);
@@ -1173,15 +1216,16 @@ int randutv_sketch_words(uint64_t seed, uint64_t step, uint64_t first_block, int
 }
 
 int randutv_finalize(void) {
-  Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
-  if (!cx.st) return RANDUTV_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
   int cur = -1;
-  const int dev = cx.device;
   if (hipGetDevice(&cur) != hipSuccess) cur = -1;
-  if (cur != dev) (void)hipSetDevice(dev);
-  cx.release();
-  if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+  for (Context& cx : g_ctx) {
+    if (!cx.st) continue;
+    const int dev = cx.device;
+    if (dev != cur) (void)hipSetDevice(dev);
+    cx.release();
+  }
+  if (cur >= 0) (void)hipSetDevice(cur);
   return RANDUTV_OK;
 }
 
@@ -1202,7 +1246,7 @@ static int gemm_entry(char transa, char transb, int64_t M, int64_t N, int64_t K,
   if (!C) return -12;
   if (ldc < std::max<int64_t>(1, M)) return -13;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   const i64 sk = dgemm_work_elems(M, N, K);
@@ -1244,7 +1288,7 @@ int randutv_geqrf(int64_t m, int64_t k, double* A, int64_t lda, double* tau) {
   if (!tau) return -5;
   if (k > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   Carver c;
@@ -1277,7 +1321,7 @@ int randutv_larft(int64_t m, int64_t k, const double* W, int64_t ldw, const doub
   if (!Tf) return -6;
   if (ldt < k) return -7;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   const i64 sk = dgemm_work_elems(k, k, m);
@@ -1311,7 +1355,7 @@ int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d, double* Us
   if (!Vs) return -6;
   if (k > kJacobiMaxN) return RANDUTV_ERR_TOO_LARGE;
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   return drained(cx, [&]() -> int {
   RUTV_CHECK(cx.init());
   Carver c;
@@ -1343,7 +1387,7 @@ int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d, double* Us
 
 int randutv_set_timing(int32_t enable) {
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   if (enable < 0 || enable > 3) return -1;
   cx.timing = enable != 0;
   cx.timer.gemm_only = enable >= 2;
@@ -1355,7 +1399,7 @@ int randutv_set_timing(int32_t enable) {
 int randutv_kernel_stats(int32_t cap, const char** names, int64_t* launches, double* ms,
                          double* flops) {
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   int nout = 0;
   for (int c = 0; c < K_NUM_CLASSES && nout < cap; ++c) {
     if (names) names[nout] = kernel_class_name(c);
@@ -1369,7 +1413,7 @@ int randutv_kernel_stats(int32_t cap, const char** names, int64_t* launches, dou
 
 int randutv_last_sweeps(int32_t cap, int32_t* sweeps) {
   Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(cx.mu);
+  std::lock_guard<std::mutex> lk(g_mu);
   const int n = (int)cx.sweeps.size();
   for (int i = 0; i < n && i < cap; ++i) sweeps[i] = cx.sweeps[i];
   return n;
@@ -1387,6 +1431,9 @@ const char* randutv_strerror(int code) {
     case RANDUTV_ERR_SYNC: return "multi-workgroup kernel wait expired";
     case RANDUTV_ERR_TOO_LARGE: return "dimension exceeds a kernel limit";
     case RANDUTV_ERR_RANK: return "the first block's sketch is rank deficient (no derivative)";
+    case RANDUTV_ERR_SCRATCH:
+      return "the problem needs more device scratch than the allocation-free entry point's fixed "
+             "RANDUTV_NOALLOC_SCRATCH_BYTES";
     default: return code < 0 ? "invalid argument" : "unknown error";
   }
 }

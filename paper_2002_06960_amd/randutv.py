@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(_HERE, "librandutv.so")
 
 RANDUTV_OK = 0
 ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONV, ERR_SYNC, ERR_TOO_LARGE, ERR_RANK = 1, 2, 3, 4, 5, 6, 7
+ERR_SCRATCH = 8
+NOALLOC_SCRATCH_BYTES = 128 << 20
 FLAG_G_HOST, FLAG_NO_FINITE_CHECK, FLAG_STREAM = 1, 2, 4
 PRECISION_BITS = (64, 32, 16, 48)
 
@@ -52,6 +54,7 @@ _I64, _I32, _U64, _D, _P, _C = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
 SIGNATURES = {
     "randutv_factor": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P]),
     "randutv_factor_ex": (ctypes.c_int, [ctypes.POINTER(RandutvArgs)]),
+    "randutv_factor_noalloc": (ctypes.c_int, [ctypes.POINTER(RandutvArgs)]),
     "randutv_sketch_host": (ctypes.c_int, [_U64, _I64, _I64, _I64, _P]),
     "randutv_sketch_words": (ctypes.c_int, [_U64, _U64, _U64, _I64, _P]),
     "randutv_finalize": (ctypes.c_int, []),

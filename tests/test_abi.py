@@ -36,7 +36,8 @@ def test_strerror_codes():
     assert "invalid" in pkg.randutv_strerror(-3)
     assert pkg.randutv_strerror(1).startswith("HIP")
     assert "rank deficient" in pkg.randutv_strerror(rb.ERR_RANK)
-    for code in range(1, rb.ERR_RANK + 1):  # every positive code has its own message
+    assert "scratch" in pkg.randutv_strerror(rb.ERR_SCRATCH)
+    for code in range(1, rb.ERR_SCRATCH + 1):  # every positive code has its own message
         assert pkg.randutv_strerror(code) != "unknown error"
 
 
@@ -206,3 +207,18 @@ def test_flop_count_matches_oracle_definition():
         for bu in (True, False):
             for bv in (True, False):
                 assert abs(pkg.flops_std(m, n, q, bu, bv) / ro.flops_std(m, n, q, bu, bv) - 1) < 1e-14
+
+
+def test_noalloc_argument_validation_without_device_work():
+    lib = pkg.load()
+    na = lib.randutv_factor_noalloc
+    a = rb.make_args(m=3, n=5, A=0x1000, lda=3, b=2, T=0x2000)
+    assert na(ctypes.byref(a)) == -2
+    a = rb.make_args(m=5, n=3, A=0x1000, lda=5, b=2, T=0x2000, max_workspace_bytes=1 << 20)
+    assert na(ctypes.byref(a)) == -15                # the workspace cap has no meaning here
+    a = rb.make_args(m=5, n=3, A=0x1000, lda=5, b=2, T=0x2000)
+    a.struct_size = 8
+    assert na(ctypes.byref(a)) == -15
+    a = rb.make_args(m=5, n=3, A=0x1000, lda=5, b=2, T=0x2000, sketch_bits=7)
+    assert na(ctypes.byref(a)) == -11
+    assert na(None) == -15
