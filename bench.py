@@ -66,6 +66,10 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the runs beside the FP64 headline: the reduced-precision modes, "
                          "the differentiable truncation and HQRRP")
+    ap.add_argument("--ooc-n", type=int, default=12000,
+                    help="size of the out-of-core run (0: skip)")
+    ap.add_argument("--ooc-budget-gib", type=float, default=1.0,
+                    help="HBM tile cache of the out-of-core run")
     ap.add_argument("--grad-batch", type=int, default=16,
                     help="matrices of the differentiable-truncation run (2048 x 2048, b=128; 0: skip)")
     ap.add_argument("--no-check", action="store_true",
@@ -235,6 +239,10 @@ def main():
     if args.grad_batch > 0 and not args.no_mixed:
         trunc_grad = truncation_grad_block(pkg, torch, args, dev)
 
+    ooc = None
+    if args.ooc_n > 0 and not args.no_mixed:
+        ooc = ooc_block(pkg, torch, args, dev)
+
     # HQRRP (randomized blocked column-pivoted QR) of the same matrix, block b
     hq = None
     if not args.no_mixed:
@@ -282,6 +290,10 @@ def main():
                                                  / max(1e-9, sum(v[1] for v in cls_stats.values())), 4)}
         log(f"# GEMM alone: {la} launches {ms_alone:.1f} ms ({achieved:.2f} TFLOP/s); in place "
             f"{ms_in:.1f} ms")
+        for name in sorted(stats_alone):
+            l_, t_, f_ = stats_alone[name]
+            if name.startswith("dgemm_") and l_:
+                log(f"#   alone {name}: {l_} launches {t_:.1f} ms {f_ / (t_ * 1e-3) / 1e12:.2f} TFLOP/s")
         log("# kernel classes (ms/step, launches/step, TFLOP/s):")
         for name, kv in sorted(kern.items(), key=lambda x: -x[1]["ms_per_step"]):
             log(f"#   {name:20s} {kv['ms_per_step']:9.3f} {kv['launches']:6d} {kv['tflops']}")
@@ -332,6 +344,7 @@ def main():
         "mixed": mixed,
         "truncation_grad": trunc_grad,
         "hqrrp": hq,
+        "ooc": ooc,
         "kernels": kern,
     }
     print(json.dumps(out), flush=True)
@@ -423,47 +436,75 @@ def mixed_block(pkg, torch, size, b, q, args, dev, reuse):
 
 
 def truncation_grad_block(pkg, torch, args, dev):
-    """Differentiable first-block truncation: a batch of 2048 x 2048 matrices
-    (s_i = 0.98^i), b = 128, q = 2, k = 128; loss ||A_k - B||_F^2 for a seeded
-    Gaussian B; forward and reverse pass timed separately."""
+    """Differentiable rank-k truncation on the 2048 x 2048 workload: a batch of
+    float32 matrices (s_i = 0.98^i), b = 128, q = 2, k = 128 (and k = 64), loss
+    ||A_k - B||_F^2 for a seeded Gaussian B, through pkg.truncation (forward
+    from the first step, reverse pass randutv_truncate_grad_k; the library
+    computes in FP64).  Forward and reverse timed over the whole batch."""
     from randutv_inputs import make_matrix_device
 
     gm, gb, gq = 2048, 128, 2
     gen = torch.Generator(device=dev)
     gen.manual_seed(77)
-    As = [make_matrix_device("exp98", gm, gm, seed=100 + i, device=dev) for i in range(args.grad_batch)]
-    Bs = [torch.randn(gm, gm, dtype=torch.float64, device=dev, generator=gen) for _ in As]
+    A = torch.stack([make_matrix_device("exp98", gm, gm, seed=100 + i, device=dev)
+                     for i in range(args.grad_batch)]).to(torch.float32)
+    B = torch.randn(A.shape, dtype=torch.float32, device=dev, generator=gen)
 
-    def fwd_bwd(Ai, Bi, first_step_only=False):
-        X = Ai.detach().requires_grad_(True)
+    def fwd_bwd(k, full=False):
+        X = A.detach().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Ak = pkg.first_block_truncation(X, gb, gq, 0, first_step_only=first_step_only)
-        loss = ((Ak - Bi) ** 2).sum()
+        Ak = pkg.truncation(X, gb, gq, 0, k, full_factorization=full)
+        loss = ((Ak - B) ** 2).sum()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         loss.backward()
         torch.cuda.synchronize()
-        return t1 - t0, time.perf_counter() - t1
+        return 1e3 * (t1 - t0) / len(A), 1e3 * (time.perf_counter() - t1) / len(A)
 
-    fwd_bwd(As[0], Bs[0])
-    tf = tb = 0.0
-    for Ai, Bi in zip(As, Bs):
-        a, c = fwd_bwd(Ai, Bi)
-        tf += a
-        tb += c
-    tf1 = 0.0
-    for Ai, Bi in zip(As, Bs):
-        tf1 += fwd_bwd(Ai, Bi, first_step_only=True)[0]
-    log(f"# truncation grad batch: forward {1e3 * tf / len(As):.2f} ms (first step only "
-        f"{1e3 * tf1 / len(As):.2f} ms), backward {1e3 * tb / len(As):.2f} ms per matrix")
-    return {"workload": f"{args.grad_batch} x {gm}x{gm}, s_i = 0.98^i, b={gb}, q={gq}, k={gb}, FP64, "
-                        "loss ||A_k - B||_F^2",
-            "ms_forward_per_matrix": round(1e3 * tf / len(As), 3),
-            "ms_forward_first_step_per_matrix": round(1e3 * tf1 / len(As), 3),
-            "ms_backward_per_matrix": round(1e3 * tb / len(As), 3),
-            "ms_batch": round(1e3 * (tf + tb), 3)}
+    fwd_bwd(gb)
+    f128, b128 = fwd_bwd(gb)
+    f64, b64 = fwd_bwd(64)
+    ffull, _ = fwd_bwd(gb, full=True)
+    log(f"# truncation grad batch of {len(A)}: k=128 forward {f128:.2f} + backward {b128:.2f} ms per "
+        f"matrix; k=64 {f64:.2f} + {b64:.2f} ms; forward through the whole factorization {ffull:.2f} ms")
+    return {"workload": f"{args.grad_batch} x {gm}x{gm} float32, s_i = 0.98^i, b={gb}, q={gq}, k={gb}, "
+                        "loss ||A_k - B||_F^2 (computed in FP64)",
+            "ms_forward_per_matrix": round(f128, 3), "ms_backward_per_matrix": round(b128, 3),
+            "ms_forward_backward_per_matrix": round(f128 + b128, 3),
+            "k64": {"ms_forward_per_matrix": round(f64, 3), "ms_backward_per_matrix": round(b64, 3)},
+            "ms_forward_full_factorization_per_matrix": round(ffull, 3)}
 
+
+def ooc_block(pkg, torch, args, dev):
+    """Out-of-core factorization (Section 3.2) of the n x n exp matrix held in
+    page-locked host memory, with an HBM tile cache of args.ooc_budget_gib,
+    in the three variants of Section 3.2.4: wall time against the summed
+    compute and copy times, the paper's Table 1 quantities."""
+    from randutv_inputs import make_matrix_device
+
+    n, b, q = args.ooc_n, 256, 2
+    Ad = make_matrix_device("exp", n, n, seed=0, device=dev)
+    Ah = pkg.host_colmajor_empty(n, n)
+    Ah.copy_(Ad.cpu())
+    del Ad
+    budget = int(args.ooc_budget_gib * (1 << 30))
+    U = pkg.host_colmajor_empty(n, n)
+    T = pkg.host_colmajor_empty(n, n)
+    V = pkg.host_colmajor_empty(n, n)
+    out = {"workload": f"randutv {n}x{n} b={b} q={q} exp, A/U/T/V in page-locked host memory "
+                       f"({3 * 8 * n * n / 2**30:.2f} GiB), HBM tile cache {args.ooc_budget_gib} GiB",
+           "modes": {}}
+    for mode in ("overlapped", "cached", "traditional"):
+        _, _, _, st = pkg.randutv_factor_ooc(Ah, b, q, 0, budget, mode, U=U, T=T, V=V)
+        e = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+        e["real_over_compute"] = round(st["real_ms"] / st["compute_ms"], 3)
+        e["compute_over_io"] = round(st["compute_ms"] / st["io_ms"], 3) if st["io_ms"] > 0 else None
+        out["modes"][mode] = e
+        log(f"# ooc {n}^2 {mode}: real {st['real_ms']:.0f} ms, compute {st['compute_ms']:.0f} ms, "
+            f"I/O {st['io_ms']:.0f} ms (in {st['h2d_ms']:.0f}, out {st['d2h_ms']:.0f}), "
+            f"{(st['h2d_bytes'] + st['d2h_bytes']) / 1e9:.1f} GB moved")
+    return out
 
 if __name__ == "__main__":
     main()

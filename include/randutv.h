@@ -193,6 +193,61 @@ int randutv_factor_ex(const randutv_args* args);
 int randutv_factor_noalloc(const randutv_args* args);
 
 /*
+ * randutv_factor_ooc -- the factorization of randutv_factor (Section 3.1,
+ * Figure 2) for matrices that stay in HOST memory, computed out of core as in
+ * Section 3.2: HBM holds a cache of tiles (block columns of b columns, all
+ * rows, of T, U and V) of at most hbm_budget_bytes, and a copy stream moves
+ * tiles between host and HBM while the compute stream works on them
+ * (Section 3.2.4; copies in and write-backs run on two streams, so both
+ * directions of the host link work at once).  The result equals
+ * randutv_factor's up to the summation
+ * order of the products (sums over tiles instead of over whole columns).
+ *   m, n, b, q, seed : as randutv_factor (same sketches G(i)).
+ *   A, lda  : HOST m x n input, lda >= m.  Read only, unless T == A (then
+ *             lda == ldt and A is factored in place).
+ *   U, ldu  : HOST m x m output (ldu >= m), or NULL to skip it.
+ *   T, ldt  : HOST m x n output (ldt >= m).
+ *   V, ldv  : HOST n x n output (ldv >= n), or NULL to skip it.
+ *   hbm_budget_bytes : device memory for the tile cache; it holds
+ *             floor(budget / (8 max(m, n) b)) tiles and must hold at least 2.
+ *             The fixed buffers of a step (sketch, reflectors, products of
+ *             max(m, n) x b) come on top (stats->fixed_bytes).
+ *   mode    : RANDUTV_OOC_TRADITIONAL (0) every access reads its tile from
+ *             host memory and writes a changed tile straight back;
+ *             RANDUTV_OOC_CACHED (1) least-recently-used cache with dirty
+ *             bits, tiles copied when a miss needs them;
+ *             RANDUTV_OOC_OVERLAPPED (2) the cache plus prefetch of the next
+ *             tile of each sweep on the copy stream.
+ *   stats   : NULL, or filled on return (struct_size set by the caller):
+ *             wall time, time of the compute tasks and of the copies (HIP
+ *             events on their streams), bytes and tiles moved, cache hits.
+ * Page-locked host memory (hipHostMalloc) lets the copies run beside the
+ * computation; pageable memory works but serializes them.  The call is
+ * synchronous.  b <= 256 and m <= 32768 as in randutv_factor.
+ * Errors: -1 m, -2 n, -3 A, -4 lda, -5 b, -6 q, -8 U/ldu, -9 T/ldt,
+ * -10 V/ldv, -11 hbm_budget_bytes (< 2 tiles), -12 mode;
+ * RANDUTV_ERR_TOO_LARGE, RANDUTV_ERR_NONFINITE, RANDUTV_ERR_* at run time.
+ */
+#define RANDUTV_OOC_TRADITIONAL 0
+#define RANDUTV_OOC_CACHED 1
+#define RANDUTV_OOC_OVERLAPPED 2
+typedef struct randutv_ooc_stats {
+  int64_t struct_size;
+  double real_ms;      /* wall time of the call */
+  double compute_ms;   /* sum of the compute tasks' durations */
+  double io_ms;        /* h2d_ms + d2h_ms */
+  double h2d_ms;       /* sum of the host -> HBM copies' durations */
+  double d2h_ms;       /* sum of the HBM -> host write-backs' durations */
+  int64_t h2d_bytes, d2h_bytes;
+  int64_t tile_loads, tile_writebacks, tile_hits;
+  int64_t slots, slot_bytes, fixed_bytes;
+} randutv_ooc_stats;
+int randutv_factor_ooc(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                       int32_t q, uint64_t seed, double* U, int64_t ldu, double* T,
+                       int64_t ldt, double* V, int64_t ldv, int64_t hbm_budget_bytes,
+                       int32_t mode, randutv_ooc_stats* stats);
+
+/*
  * randutv_sketch_host -- every sketch G(0), ..., G(p-1) that randutv_factor
  * (m, n, ..., b, ..., seed) draws, written to HOST memory in the layout that
  * randutv_factor_ex takes as a caller's G (G(i) of (m - i b) x b_i,
@@ -280,6 +335,43 @@ int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t 
 int randutv_truncate_grad(int64_t m, int64_t n, const double* A, int64_t lda,
                           int64_t b, int32_t q, uint64_t seed, const double* Gbar,
                           int64_t ldg, double* Abar, int64_t ldab);
+
+/*
+ * randutv_truncate_grad_k -- reverse pass of the truncation A_k of
+ * randutv_factor(m, n, A, lda, b, q, seed, ...) for any 0 < k <= min(b, n),
+ * with the sketch G(0) held fixed (Section 1.1 for A_k, Section 3.1 for the
+ * first step).  After step 0, U's first min(b, n) columns are the leading
+ * left singular vectors of C = A Q_Y, Q_Y an orthonormal basis of
+ * Y = (A^T A)^q A^T G(0) (the panel Q of C times the b x b SVD's left
+ * factor), so A_k = U_k U_k^T A projects A onto C's leading k left singular
+ * vectors; the reverse pass differentiates that projector (the eigenvalue
+ * gaps d_i^2 - d_j^2 of the first block enter for i < k <= j) and the power
+ * chain.  k = min(b, n) gives randutv_truncate_grad's value.
+ *   Gbar : m x n (ld ldg), dL/dA_k.   Abar : m x n (ld ldab) output, dL/dA.
+ * Device pointers, column-major FP64, synchronous.  Errors: -1 m, -2 n,
+ * -3 A, -4 lda, -5 b, -6 q (q < 0 or q > 64), -8 k, -9 Gbar, -10 ldg,
+ * -11 Abar (NULL or aliasing), -12 ldab; RANDUTV_ERR_TOO_LARGE for
+ * min(b, n) > 256; RANDUTV_ERR_NONFINITE; RANDUTV_ERR_RANK when C's leading
+ * k singular values include zero or d_k = d_{k+1} (no derivative there);
+ * RANDUTV_ERR_NOCONV / RANDUTV_ERR_SYNC from the b x b SVD.
+ */
+int randutv_truncate_grad_k(int64_t m, int64_t n, const double* A, int64_t lda,
+                            int64_t b, int32_t q, uint64_t seed, int64_t k,
+                            const double* Gbar, int64_t ldg, double* Abar, int64_t ldab);
+
+/*
+ * randutv_truncate_first_block_k -- the forward value of the truncation A_k,
+ * 0 < k <= min(b, n), of randutv_factor(m, n, A, lda, b, q, seed, ...) from
+ * the first step alone: A_k = U_1 U_1^T A with U_1 the leading k left
+ * singular vectors of C = A Q_Y (see randutv_truncate_grad_k; Section 1.1,
+ * Section 3.1).  Ak: m x n output (ld ldak), must not alias A.  Device
+ * pointers, column-major FP64, synchronous.  Errors: -1 m, -2 n, -3 A,
+ * -4 lda, -5 b, -6 q, -8 k, -9 Ak, -10 ldak; RANDUTV_ERR_TOO_LARGE,
+ * RANDUTV_ERR_NONFINITE, RANDUTV_ERR_NOCONV, RANDUTV_ERR_SYNC.
+ */
+int randutv_truncate_first_block_k(int64_t m, int64_t n, const double* A, int64_t lda,
+                                   int64_t b, int32_t q, uint64_t seed, int64_t k,
+                                   double* Ak, int64_t ldak);
 
 /*
  * randutv_sketch -- write the sketch G(step) (rows x cols, ld = ldg) that

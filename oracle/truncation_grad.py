@@ -37,6 +37,43 @@ def _closed_form(At, G, q: int):
     return Q @ (Q.T @ At)
 
 
+def _closed_form_k(At, G, q: int, k: int):
+    """A_k for k <= b_0: the projector onto the leading k left singular
+    vectors of C = A orth(Y), Y = (A^T A)^q A^T G(0).  After step 0 the first
+    b_0 columns of U are (panel Q of C) U_S with C = Q R, R = U_S D V_S^T the
+    b x b SVD (Section 3.1), i.e. the left singular vectors of C in descending
+    order; later steps leave them alone.  They do not depend on which
+    orthonormal basis of range(Y) forms C, so any QR of Y gives the same A_k."""
+    Y = At.T @ G
+    for _ in range(q):
+        Y = At.T @ (At @ Y)  # (A^T A)^q A^T G(0), no re-orthonormalisation (R9)
+    Qv, _ = torch.linalg.qr(Y, mode="reduced")
+    C = At @ Qv
+    Uc, _, _ = torch.linalg.svd(C, full_matrices=False)
+    Uk = Uc[:, :k]
+    return Uk @ (Uk.T @ At)
+
+
+def first_block_truncation_k(A: np.ndarray, b: int, q: int, seed: int, k: int) -> np.ndarray:
+    """A_k for 0 < k <= min(b, n) from the closed form (leading left singular
+    subspace of A orth(Y))."""
+    At = torch.from_numpy(np.asarray(A, dtype=np.float64))
+    G = torch.from_numpy(first_block_sketch(A, b, seed))
+    return _closed_form_k(At, G, q, k).numpy()
+
+
+def first_block_truncation_k_grad(A: np.ndarray, b: int, q: int, seed: int, k: int,
+                                  Gbar: np.ndarray) -> np.ndarray:
+    """d<Gbar, A_k>/dA for 0 < k <= min(b, n), G(0) fixed, by torch's reverse
+    mode through the QR and the SVD (its rule needs distinct singular values
+    of C around k, which holds for the test matrices here)."""
+    At = torch.from_numpy(np.array(A, dtype=np.float64)).requires_grad_(True)
+    G = torch.from_numpy(first_block_sketch(A, b, seed))
+    Ak = _closed_form_k(At, G, q, k)
+    (Ak * torch.from_numpy(np.asarray(Gbar, dtype=np.float64))).sum().backward()
+    return At.grad.numpy()
+
+
 def first_block_truncation(A: np.ndarray, b: int, q: int, seed: int = 0) -> np.ndarray:
     """A_k for k = min(b, n) from the closed form Q Q^T A."""
     At = torch.from_numpy(np.asarray(A, dtype=np.float64))

@@ -13,9 +13,12 @@ from .randutv import (  # noqa: F401
     as_colmajor,
     colmajor_empty,
     first_block_truncation,
+    truncation,
     load,
     randutv_dgemm,
     randutv_factor,
+    randutv_factor_ooc,
+    host_colmajor_empty,
     randutv_geqrf,
     randutv_gesvj,
     randutv_hqrrp,
@@ -27,7 +30,9 @@ from .randutv import (  # noqa: F401
     randutv_strerror,
     randutv_truncate,
     randutv_truncate_first_block,
+    randutv_truncate_first_block_k,
     randutv_truncate_grad,
+    randutv_truncate_grad_k,
 )
 
 

@@ -137,12 +137,14 @@ __device__ __forceinline__ void tile_of(int L, int tilesM, int tilesN, int split
 
 // MINB: workgroups that must fit on a CU at once (the launch bound counts
 // waves per SIMD, four SIMDs per CU)
-template <class CT, bool TA, bool TB, int BM, int BN, int BK, int MINB = 2, int WGM = 2, int WGN = 2>
+template <class CT, bool TA, bool TB, int BM, int BN, int BK, int MINB = 2, int WGM = 2, int WGN = 2,
+          int CINIT = 0>
 __global__ __launch_bounds__(64 * WGM * WGN, MINB * WGM * WGN / 4) void dgemm_mfma_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, i64 lda,
     const double* __restrict__ B, i64 ldb, double beta, double* __restrict__ C, i64 ldc,
     int kchunk, double* __restrict__ part, int tilesM, int tilesN, int splits) {
   constexpr int NT = 64 * WGM * WGN;  // threads: a WGM x WGN grid of waves
+  constexpr int cinit = CINIT;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int MI = WM / 16, NJ = WN / 16;
   constexpr int LDAS = BM + 1, LDBS = BN + 1;  // +1 double: conflict-free transposing stores
@@ -168,20 +170,41 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB * WGM * WGN / 4) void dgemm_mf
   lb.init(B, ldb, tid, n0, N);
   double ra[AE], rb[BE];
   bool ka[AE], kb[BE];
+  // cinit (FP64 only, one K split, beta = 1, alpha = +-1): the accumulators
+  // start from C and op(A) enters with the sign of alpha, so the result
+  // C + alpha op(A) op(B) needs no read of C after the K loop; the C loads
+  // are issued with the first slice's and share its latency
+  constexpr unsigned long long sgnA = cinit == 1 ? 0x8000000000000000ull : 0ull;
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < AE; ++r)
-      As[buf][la.lds_k(r) * LDAS + la.lds_e(r)] = static_cast<CT>(keep_or_zero(ra[r], ka[r]));
+      As[buf][la.lds_k(r) * LDAS + la.lds_e(r)] = static_cast<CT>(__longlong_as_double(
+          __double_as_longlong(keep_or_zero(ra[r], ka[r])) ^ (long long)sgnA));
 #pragma unroll
     for (int r = 0; r < BE; ++r)
       Bs[buf][lb.lds_k(r) * LDBS + lb.lds_e(r)] = static_cast<CT>(keep_or_zero(rb[r], kb[r]));
   };
 
   V4 acc[MI][NJ];
+  if constexpr (cinit != 0) {
+    const int cm = lane & 15;
 #pragma unroll
-  for (int i = 0; i < MI; ++i)
+    for (int i = 0; i < MI; ++i) {
+      const int gmc = min(m0 + wm0 + 16 * i + cm, M - 1);
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[i][j] = V4{0, 0, 0, 0};
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gnc = min(n0 + wn0 + 16 * j + MT::row(r, lane), N - 1);
+          acc[i][j][r] = static_cast<CT>(C[gmc + (i64)gnc * ldc]);
+        }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = V4{0, 0, 0, 0};
+  }
 
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   if (nk > 0) {
@@ -223,7 +246,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB * WGM * WGN / 4) void dgemm_mf
   // results of row block i are stored, into alternating register sets, so
   // that the wait for a load never includes the stores issued after it.
   const int cm = lane & 15;
-  const bool read_c = !part && beta != 0.0;
+  const bool read_c = !part && beta != 0.0 && !cinit;
   double cva[NJ][4], cvb[NJ][4];
   auto load_c = [&](int i, double (&cv)[NJ][4]) {
     const int gmc = min(m0 + wm0 + 16 * i + cm, M - 1);
@@ -242,7 +265,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB * WGM * WGN / 4) void dgemm_mf
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gn = n0 + wn0 + 16 * j + MT::row(r, lane);
-        double v = alpha * static_cast<double>(acc[i][j][r]);
+        double v = cinit ? static_cast<double>(acc[i][j][r]) : alpha * static_cast<double>(acc[i][j][r]);
         if (read_c) v += beta * cv[j][r];
         if (gm < M && gn < N) {
           if (part)
@@ -487,6 +510,10 @@ struct Plan {
 };
 
 constexpr int kBK = 16;
+#ifndef RUTV_GEMM_CINIT
+#define RUTV_GEMM_CINIT 1
+#endif
+constexpr bool kCInit = RUTV_GEMM_CINIT != 0;
 #ifndef RUTV_SPLITK_RESIDENT
 #define RUTV_SPLITK_RESIDENT 768
 #endif
@@ -527,12 +554,29 @@ void launch_tile(hipStream_t st, int bm, int M, int N, int K, double alpha, cons
                  int splits, double* part) {
   const int tilesM = (int)cdiv(M, bm), tilesN = (int)cdiv(N, bm);
   const dim3 grid(tilesM * tilesN * splits);
-  if (bm == 128)
-    dgemm_mfma_kernel<CT, TA, TB, 128, 128, kBK, 2, kWavesM, kWavesN><<<grid, kGemmThreads, 0, st>>>(
-        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, tilesN, splits);
+  // accumulate onto C (no read of C after the K loop) for C += +-op(A) op(B)
+  // in FP64 without a K split
+  int cinit = 0;
+  if (std::is_same<CT, double>::value && !part && beta == 1.0 && K > 0 &&
+      (alpha == 1.0 || alpha == -1.0) && kCInit)
+    cinit = alpha == -1.0 ? 1 : 2;
+  auto go = [&](auto ci) {
+    constexpr int CI = decltype(ci)::value;
+    if (bm == 128)
+      dgemm_mfma_kernel<CT, TA, TB, 128, 128, kBK, 2, kWavesM, kWavesN, CI>
+          <<<grid, kGemmThreads, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part,
+                                          tilesM, tilesN, splits);
+    else
+      dgemm_mfma_kernel<CT, TA, TB, 64, 64, kBK, 2, kWavesM, kWavesN, CI>
+          <<<grid, kGemmThreads, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part,
+                                          tilesM, tilesN, splits);
+  };
+  if (cinit == 1)
+    go(std::integral_constant<int, std::is_same<CT, double>::value ? 1 : 0>{});
+  else if (cinit == 2)
+    go(std::integral_constant<int, std::is_same<CT, double>::value ? 2 : 0>{});
   else
-    dgemm_mfma_kernel<CT, TA, TB, 64, 64, kBK, 2, kWavesM, kWavesN><<<grid, kGemmThreads, 0, st>>>(
-        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tilesM, tilesN, splits);
+    go(std::integral_constant<int, 0>{});
 }
 
 template <bool TA, bool TB>

@@ -123,5 +123,32 @@ int set_diag_block(hipStream_t st, i64 k, const double* d, double* D, i64 ldd);
 // X (rows x cols, ld ldx) := Y (same shape, ld ldy)
 int copy_matrix(hipStream_t st, i64 rows, i64 cols, const double* Y, i64 ldy, double* X,
                 i64 ldx);
+// X(:, i) *= c / lam[i] (rows x cols); flag[0] |= 1 on lam[i] == 0 or a non-finite result
+int scale_cols(hipStream_t st, i64 rows, i64 cols, double* X, i64 ldx, const double* lam,
+               double c, int* flag);
+// X (r x k): X[j, i] *= 2 / (d_i^2 - d_{k+j}^2); flag[0] |= 1 on a zero gap
+int gap_divide(hipStream_t st, i64 r, i64 k, double* X, i64 ldx, const double* d, int* flag);
+// lam[i] := d[i]^2
+int square_vec(hipStream_t st, i64 n, const double* d, double* lam);
+
+// ---- out-of-core factorization (ooc.hip) -------------------------------------
+struct OocCfg {
+  i64 m = 0, n = 0, b = 0;
+  int q = 0;
+  uint64_t seed = 0;
+  const double* A = nullptr;  // host
+  i64 lda = 0;
+  double *U = nullptr, *T = nullptr, *V = nullptr;  // host (U, V may be null)
+  i64 ldu = 0, ldt = 0, ldv = 0;
+  size_t budget = 0;          // bytes of HBM for the tile cache
+  int mode = 2;               // 0 traditional, 1 cached, 2 overlapped
+  bool finite_check = true;
+  int max_sweeps = 0;
+  unsigned spin_limit = 0;
+};
+// the factorization with the matrices in host memory: cs computes, xs copies
+// tiles in, ws writes them back
+int ooc_factor(const OocCfg& c, hipStream_t cs, hipStream_t xs, hipStream_t ws,
+               randutv_ooc_stats* stats);
 
 }  // namespace rutv

@@ -508,12 +508,39 @@ static int factor_run(const FactorCfg& c, Context& cx) {
   if (wantU) RUTV_CHECK(set_identity(sUV, m, U, ldu));
   if (wantV) RUTV_CHECK(set_identity(sUV, n, V, ldv));
 
-  // stream UV: V and U updates of step j; they are enqueued one step late,
-  // behind the event that marks the end of the next step's power iteration,
-  // so that they fill the chip during the next QR of the sketch (a latency-
-  // bound kernel on 32 CUs) instead of competing with the power iteration
   i64 g0 = 0;
-  auto uv_and_svd = [&](i64 j, bool wait_pre) -> int {
+  // stream S: once step j's U/V update is enqueued, the SVD group that ends
+  // at step j (every kSvdGroup steps, and the last), then its right factors
+  auto svd_group = [&](i64 j) -> int {
+    const i64 sj = j * b, bj = std::min(b, n - sj);
+    const bool last = sj + bj >= n;
+    if ((j + 1 - g0) != kSvdGroup && !last) return RANDUTV_OK;
+    const int cnt = (int)(j + 1 - g0);
+    RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_U, j), 0));
+    RUTV_CHECK(jacobi_svd_batched(sS, cnt, b, last ? b_last : b, w.Rall + g0 * b * b, b, b * b,
+                                  w.dall + g0 * b, b, w.Usall + g0 * b * b, w.Vsall + g0 * b * b,
+                                  b * b, w.jwork, &w.status[2 + 3 * g0], c.max_sweeps,
+                                  c.spin_limit));
+    for (i64 t = g0; t <= j; ++t) {
+      const i64 st_ = t * b, bt = std::min(b, n - st_);
+      const double* d = w.dall + t * b;
+      const double* Vs = w.Vsall + t * b * b;
+      const double* Us = w.Usall + t * b * b;
+      RUTV_CHECK(set_diag_block(sS, bt, d, T + st_ + st_ * ldt, ldt));
+      RUTV_CHECK(right_mul_small(sS, xS, st_, bt, T + st_ * ldt, ldt, Vs));
+      RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_UV, t), 0));
+      if (wantV) RUTV_CHECK(right_mul_small(sS, xS, n, bt, V + st_ * ldv, ldv, Vs));
+      if (wantU) RUTV_CHECK(right_mul_small(sS, xS, m, bt, U + st_ * ldu, ldu, Us));
+    }
+    g0 = j + 1;
+    return RANDUTV_OK;
+  };
+  // stream UV: the V and U updates of step j.  They are enqueued one step
+  // late, behind the event that marks the end of the next step's power
+  // iteration, so that they fill the chip during the next QR of the sketch (a
+  // latency-bound kernel on few CUs) instead of competing with the power
+  // iteration.
+  auto uv_updates = [&](i64 j, bool wait_pre) -> int {
     const i64 sj = j * b, bj = std::min(b, n - sj), mj = m - sj, nj = n - sj;
     const int bf = (int)(j % kWyBuf);
     if (wait_pre) RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_PRE, j + 1), 0));
@@ -524,29 +551,7 @@ static int factor_run(const FactorCfg& c, Context& cx) {
     if (wantU)
       RUTV_CHECK(right_apply(sUV, xUV, m, mj, bj, U + sj * ldu, ldu, w.WU[bf], w.ZU[bf], update_prec));
     RUTV_TRY(hipEventRecord(ev(EV_UV, j), sUV));
-    // stream S: b x b SVDs in groups, then their right factors
-    const bool last = sj + bj >= n;
-    if ((j + 1 - g0) == kSvdGroup || last) {
-      const int cnt = (int)(j + 1 - g0);
-      RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_U, j), 0));
-      RUTV_CHECK(jacobi_svd_batched(sS, cnt, b, last ? b_last : b, w.Rall + g0 * b * b, b, b * b,
-                                    w.dall + g0 * b, b, w.Usall + g0 * b * b, w.Vsall + g0 * b * b,
-                                    b * b, w.jwork, &w.status[2 + 3 * g0], c.max_sweeps,
-                                    c.spin_limit));
-      for (i64 t = g0; t <= j; ++t) {
-        const i64 st_ = t * b, bt = std::min(b, n - st_);
-        const double* d = w.dall + t * b;
-        const double* Vs = w.Vsall + t * b * b;
-        const double* Us = w.Usall + t * b * b;
-        RUTV_CHECK(set_diag_block(sS, bt, d, T + st_ + st_ * ldt, ldt));
-        RUTV_CHECK(right_mul_small(sS, xS, st_, bt, T + st_ * ldt, ldt, Vs));
-        RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_UV, t), 0));
-        if (wantV) RUTV_CHECK(right_mul_small(sS, xS, n, bt, V + st_ * ldv, ldv, Vs));
-        if (wantU) RUTV_CHECK(right_mul_small(sS, xS, m, bt, U + st_ * ldu, ldu, Us));
-      }
-      g0 = j + 1;
-    }
-    return RANDUTV_OK;
+    return svd_group(j);
   };
 
   i64 s = 0;
@@ -571,7 +576,7 @@ static int factor_run(const FactorCfg& c, Context& cx) {
       RUTV_CHECK(gemm(sT, xT, true, false, ni, bi, mi, 1.0, Bm, ldt, w.Zp, mi, 0.0, w.Y, ni, sketch_prec));
     }
     RUTV_TRY(hipEventRecord(ev(EV_PRE, i), sT));
-    if (i >= 1) RUTV_CHECK(uv_and_svd(i - 1, true));
+    if (i >= 1) RUTV_CHECK(uv_updates(i - 1, true));
     RUTV_CHECK(panel_qr(sT, ni, bi, w.Y, ni, w.tauV, xT.pw));
     RUTV_CHECK(extract_reflectors(sT, ni, bi, w.Y, ni, w.WV[buf], ni, nullptr, 0, false));
     RUTV_TRY(hipEventRecord(ev(EV_WV, i), sT));
@@ -617,7 +622,7 @@ static int factor_run(const FactorCfg& c, Context& cx) {
     }
     s = e;
   }
-  RUTV_CHECK(uv_and_svd(nsteps - 1, false));
+  RUTV_CHECK(uv_updates(nsteps - 1, false));
   // ---- join, then the deferred left factors: T(s:e, e:n) <- U_S^T T(s:e, e:n)
   RUTV_TRY(hipEventRecord(cx.ev_misc[0], sS));
   RUTV_TRY(hipEventRecord(cx.ev_misc[1], sUV));
@@ -776,6 +781,39 @@ int randutv_factor_noalloc(const randutv_args* a) {
   if (rc != RANDUTV_OK) return rc;
   c.noalloc = true;
   return factor_entry(c);
+}
+
+int randutv_factor_ooc(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                       uint64_t seed, double* U, int64_t ldu, double* T, int64_t ldt, double* V,
+                       int64_t ldv, int64_t hbm_budget_bytes, int32_t mode,
+                       randutv_ooc_stats* stats) {
+  if (m < 0) return -1;
+  if (n < 0 || n > m) return -2;
+  if (m == 0 || n == 0) return RANDUTV_OK;
+  if (!A) return -3;
+  if (lda < m) return -4;
+  if (b < 1) return -5;
+  if (q < 0) return -6;
+  if (U && (ldu < m || U == T || U == V)) return -8;
+  if (!T || ldt < m || (T == A && lda != ldt)) return -9;
+  if (V && (ldv < n || V == T)) return -10;
+  const i64 bb = std::min<i64>(b, n);
+  if (hbm_budget_bytes < 0 || (uint64_t)hbm_budget_bytes / (8ull * (uint64_t)m * (uint64_t)bb) < 2)
+    return -11;
+  if (mode < RANDUTV_OOC_TRADITIONAL || mode > RANDUTV_OOC_OVERLAPPED) return -12;
+  if (bb > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
+  OocCfg c;
+  c.m = m, c.n = n, c.b = b, c.q = q, c.seed = seed, c.A = A, c.lda = lda;
+  c.U = U, c.T = T, c.V = V, c.ldu = ldu, c.ldt = ldt, c.ldv = ldv;
+  c.budget = (size_t)hbm_budget_bytes;
+  c.mode = mode;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context& cx = ctx();
+  return drained(cx, [&]() -> int {
+    RUTV_CHECK(cx.init());
+    set_launch_timer(nullptr);
+    return ooc_factor(c, cx.streams[ST_T], cx.streams[ST_P], cx.streams[ST_UV], stats);
+  });
 }
 
 int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const double* T,
@@ -1134,6 +1172,220 @@ static int truncate_grad_impl(int64_t m, int64_t n, const double* A, int64_t lda
   if (flags[1]) return RANDUTV_ERR_SYNC;
   if (flags[2]) return RANDUTV_ERR_RANK;
   return RANDUTV_OK;
+  });
+}
+
+// Reverse pass of A_k = P_k A for 0 < k <= b_0 = min(b, n): P_k projects onto
+// the leading k left singular vectors of C = A Q_Y, Q_Y an orthonormal basis
+// of Y = (A^T A)^q A^T G(0) (after step 0, U's first b_0 columns are the panel
+// Q of C times the b x b SVD's U_S: C's left singular vectors; later steps
+// leave them alone).  With U_C = [U_1 U_2] (k and b_0 - k columns), singular
+// values d and lambda = d^2, the eigenprojector derivative of S = C C^T gives
+//   Abar  = P_k Gbar + L Q_Y^T + (the power chain reversed from Ybar),
+//   E     = sym(Gbar A^T) U_1,
+//   H     = U_2 F + 2 (I - U_C U_C^T) E Lambda_1^-1,  F_ji = 2 (U_2^T E)_ji / (lambda_i - lambda_j),
+//   L     = H (U_1^T C) + U_1 (H^T C),
+//   Ybar  = (I - Q_Y Q_Y^T) A^T [H (U_1^T D) + U_1 (H^T D)],  D = C R_Y^-T,
+// and the chain Z_j = A^T M_j, M_{j+1} = A Z_j (M_0 = G(0), Y = Z_q) reversed:
+// Abar += M_j Zbar_j^T, Mbar_j = A Zbar_j, Abar += Mbar_j Z_{j-1}^T,
+// Zbar_{j-1} = A^T Mbar_j.
+// With Ak non-null the call is the forward value instead: Ak = U_1 (U_1^T A).
+static int truncate_grad_k_impl(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                                int32_t q, uint64_t seed, int64_t k, const double* Gbar,
+                                int64_t ldg, double* Abar, int64_t ldab, double* Ak = nullptr,
+                                int64_t ldak = 0) {
+  if (m < 0) return -1;
+  if (n < 0 || n > m) return -2;
+  if (m == 0 || n == 0) return RANDUTV_OK;
+  if (!A) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (b < 1) return -5;
+  if (q < 0 || q > kGradMaxQ) return -6;
+  const i64 bb = std::min<i64>(b, n);
+  if (k < 1 || k > bb) return -8;
+  if (Ak) {
+    if (Ak == A) return -9;
+    if (ldak < std::max<int64_t>(1, m)) return -10;
+  } else {
+    if (!Gbar) return -9;
+    if (ldg < std::max<int64_t>(1, m)) return -10;
+    if (!Abar || Abar == A || Abar == Gbar) return -11;
+    if (ldab < std::max<int64_t>(1, m)) return -12;
+  }
+  if (bb > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(g_mu);
+  return drained(cx, [&]() -> int {
+  RUTV_CHECK(cx.init());
+  hipStream_t st = cx.st;
+  const i64 r2 = bb - k;  // columns of U_2
+  i64 sk = 0;
+  for (auto s3 : {std::array<i64, 3>{n, bb, m}, {m, bb, n}, {bb, bb, m}, {bb, bb, n}, {bb, bb, bb},
+                  {m, bb, bb}, {n, bb, bb}, {k, n, m}, {m, n, k}, {m, n, bb}, {n, k, m}, {m, k, n},
+                  {bb, k, m}, {m, k, bb}, {k, bb, m}, {m, bb, k}})
+    sk = std::max(sk, dgemm_work_elems(s3[0], s3[1], s3[2]));
+  std::vector<double*> Mj(q + 1), Zj(q + 1);
+  double *Qy, *Ry, *RyInv, *C, *Fp, *tau, *Wr, *Gram, *Tf, *X, *Rc, *Qc, *d, *lam, *Us, *Vs, *jw,
+      *Uc, *T1, *E, *H, *X1, *W1, *W2, *L, *D, *Yb, *Zb, *Mb, *Cn, *wk;
+  int* status;
+  unsigned long long* xch;
+  const i64 mx = std::max(m, n);
+  auto lay = [&](Carver& c) {
+    for (int j = 0; j <= q; ++j) Mj[j] = c.take<double>(m * bb);
+    for (int j = 0; j <= q; ++j) Zj[j] = c.take<double>(n * bb);
+    Qy = c.take<double>(n * bb);
+    Ry = c.take<double>(bb * bb);
+    RyInv = c.take<double>(bb * bb);
+    C = c.take<double>(m * bb);
+    Fp = c.take<double>(mx * bb);
+    tau = c.take<double>(bb);
+    Wr = c.take<double>(mx * bb);
+    Gram = c.take<double>(bb * bb);
+    Tf = c.take<double>(bb * bb);
+    X = c.take<double>(bb * bb);
+    Rc = c.take<double>(bb * bb);
+    Qc = c.take<double>(m * bb);
+    d = c.take<double>(bb);
+    lam = c.take<double>(bb);
+    Us = c.take<double>(bb * bb);
+    Vs = c.take<double>(bb * bb);
+    jw = c.take<double>(jacobi_work_elems(bb));
+    Uc = c.take<double>(m * bb);
+    T1 = c.take<double>(n * bb);
+    E = c.take<double>(m * k);
+    H = c.take<double>(m * k);
+    X1 = c.take<double>(bb * k);
+    W1 = c.take<double>(k * bb);
+    W2 = c.take<double>(k * bb);
+    L = c.take<double>(m * bb);
+    D = c.take<double>(m * bb);
+    Yb = c.take<double>(n * bb);
+    Zb = c.take<double>(n * bb);
+    Mb = c.take<double>(m * bb);
+    Cn = c.take<double>(k * n);
+    wk = c.take<double>(sk);
+    status = c.take<int>(8);
+    xch = c.take<unsigned long long>(panel_work_elems(mx));
+  };
+  Carver probe;
+  lay(probe);
+  RUTV_CHECK(cx.reserve(probe.off));
+  Carver real;
+  real.base = cx.ws;
+  lay(real);
+  set_launch_timer(nullptr);
+  auto mm = [&](bool ta, bool tb, i64 M_, i64 N_, i64 K_, double alpha, const double* A_, i64 la,
+                const double* B_, i64 lb, double beta, double* C_, i64 lc) {
+    return dgemm(st, ta, tb, M_, N_, K_, alpha, A_, la, B_, lb, beta, C_, lc, wk, sk);
+  };
+  PanelWork pw;
+  pw.xch = xch;
+  pw.err = &status[1];
+  // Householder QR of P (rows x bb, ld rows, copied to Fp) -> explicit Q (rows x bb), R
+  auto qr_explicit = [&](i64 rows, const double* P, double* Qo, double* Ro) -> int {
+    RUTV_CHECK(copy_matrix(st, rows, bb, P, rows, Fp, rows));
+    RUTV_CHECK(panel_qr(st, rows, bb, Fp, rows, tau, pw));
+    RUTV_CHECK(extract_reflectors(st, rows, bb, Fp, rows, Wr, rows, Ro, bb, false));
+    RUTV_CHECK(mm(true, false, bb, bb, rows, 1.0, Wr, rows, Wr, rows, 0.0, Gram, bb));
+    RUTV_CHECK(larft_from_gram(st, bb, Gram, bb, tau, Tf, bb));
+    RUTV_CHECK(mm(false, true, bb, bb, bb, 1.0, Tf, bb, Wr, rows, 0.0, X, bb));
+    RUTV_CHECK(set_eye(st, rows, bb, Qo, rows));
+    return mm(false, false, rows, bb, bb, -1.0, Wr, rows, X, bb, 1.0, Qo, rows);
+  };
+  RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(status), 8));
+  RUTV_CHECK(check_finite(st, m, n, A, lda, &status[0]));
+  if (!Ak) RUTV_CHECK(check_finite(st, m, n, Gbar, ldg, &status[0]));
+  // forward: M_0 = G(0), Z_j = A^T M_j, M_{j+1} = A Z_j; Y = Z_q
+  RUTV_CHECK(sketch(st, seed, 0, m, bb, Mj[0], m));
+  for (int j = 0; j <= q; ++j) {
+    RUTV_CHECK(mm(true, false, n, bb, m, 1.0, A, lda, Mj[j], m, 0.0, Zj[j], n));
+    if (j < q) RUTV_CHECK(mm(false, false, m, bb, n, 1.0, A, lda, Zj[j], n, 0.0, Mj[j + 1], m));
+  }
+  RUTV_CHECK(qr_explicit(n, Zj[q], Qy, Ry));
+  RUTV_CHECK(tri_inverse(st, bb, Ry, bb, RyInv, bb, &status[2]));
+  RUTV_CHECK(mm(false, false, m, bb, n, 1.0, A, lda, Qy, n, 0.0, C, m));
+  RUTV_CHECK(qr_explicit(m, C, Qc, Rc));
+  RUTV_CHECK(jacobi_svd(st, bb, Rc, bb, d, Us, Vs, jw, &status[4]));
+  RUTV_CHECK(square_vec(st, bb, d, lam));
+  RUTV_CHECK(mm(false, false, m, bb, bb, 1.0, Qc, m, Us, bb, 0.0, Uc, m));
+  const double* U1 = Uc;
+  const double* U2 = Uc + k * m;
+  auto finish = [&]() -> int {
+    int flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    RUTV_TRY(hipMemcpyAsync(flags, status, sizeof(flags), hipMemcpyDeviceToHost, st));
+    RUTV_TRY(hipStreamSynchronize(st));
+    if (flags[0]) return RANDUTV_ERR_NONFINITE;
+    if (flags[1] || flags[6]) return RANDUTV_ERR_SYNC;
+    if (!flags[5]) return RANDUTV_ERR_NOCONV;
+    if (!Ak && flags[2]) return RANDUTV_ERR_RANK;
+    return RANDUTV_OK;
+  };
+  if (Ak) {  // forward value: Ak = U_1 (U_1^T A)
+    RUTV_CHECK(mm(true, false, k, n, m, 1.0, U1, m, A, lda, 0.0, Cn, k));
+    RUTV_CHECK(mm(false, false, m, n, k, 1.0, U1, m, Cn, k, 0.0, Ak, ldak));
+    return finish();
+  }
+  // Abar = U_1 (U_1^T Gbar)
+  RUTV_CHECK(mm(true, false, k, n, m, 1.0, U1, m, Gbar, ldg, 0.0, Cn, k));
+  RUTV_CHECK(mm(false, false, m, n, k, 1.0, U1, m, Cn, k, 0.0, Abar, ldab));
+  // E = (Gbar (A^T U_1) + A (Gbar^T U_1)) / 2
+  RUTV_CHECK(mm(true, false, n, k, m, 1.0, A, lda, U1, m, 0.0, T1, n));
+  RUTV_CHECK(mm(false, false, m, k, n, 0.5, Gbar, ldg, T1, n, 0.0, E, m));
+  RUTV_CHECK(mm(true, false, n, k, m, 1.0, Gbar, ldg, U1, m, 0.0, T1, n));
+  RUTV_CHECK(mm(false, false, m, k, n, 0.5, A, lda, T1, n, 1.0, E, m));
+  // H = 2 (E - U_C (U_C^T E)) Lambda_1^-1 + U_2 F
+  RUTV_CHECK(mm(true, false, bb, k, m, 1.0, Uc, m, E, m, 0.0, X1, bb));
+  RUTV_CHECK(copy_matrix(st, m, k, E, m, H, m));
+  RUTV_CHECK(mm(false, false, m, k, bb, -1.0, Uc, m, X1, bb, 1.0, H, m));
+  RUTV_CHECK(scale_cols(st, m, k, H, m, lam, 2.0, &status[2]));
+  if (r2 > 0) {
+    RUTV_CHECK(gap_divide(st, r2, k, X1 + k, bb, d, &status[2]));
+    RUTV_CHECK(mm(false, false, m, k, r2, 1.0, U2, m, X1 + k, bb, 1.0, H, m));
+  }
+  // L = H (U_1^T C) + U_1 (H^T C);  Abar += L Q_Y^T
+  RUTV_CHECK(mm(true, false, k, bb, m, 1.0, U1, m, C, m, 0.0, W1, k));
+  RUTV_CHECK(mm(true, false, k, bb, m, 1.0, H, m, C, m, 0.0, W2, k));
+  RUTV_CHECK(mm(false, false, m, bb, k, 1.0, H, m, W1, k, 0.0, L, m));
+  RUTV_CHECK(mm(false, false, m, bb, k, 1.0, U1, m, W2, k, 1.0, L, m));
+  RUTV_CHECK(mm(false, true, m, n, bb, 1.0, L, m, Qy, n, 1.0, Abar, ldab));
+  // D = C R_Y^-T; L2 = H (U_1^T D) + U_1 (H^T D) (into L)
+  RUTV_CHECK(mm(false, true, m, bb, bb, 1.0, C, m, RyInv, bb, 0.0, D, m));
+  RUTV_CHECK(mm(true, false, k, bb, m, 1.0, U1, m, D, m, 0.0, W1, k));
+  RUTV_CHECK(mm(true, false, k, bb, m, 1.0, H, m, D, m, 0.0, W2, k));
+  RUTV_CHECK(mm(false, false, m, bb, k, 1.0, H, m, W1, k, 0.0, L, m));
+  RUTV_CHECK(mm(false, false, m, bb, k, 1.0, U1, m, W2, k, 1.0, L, m));
+  // Ybar = (I - Q_Y Q_Y^T) A^T L2
+  RUTV_CHECK(mm(true, false, n, bb, m, 1.0, A, lda, L, m, 0.0, Yb, n));
+  RUTV_CHECK(mm(true, false, bb, bb, n, 1.0, Qy, n, Yb, n, 0.0, X, bb));
+  RUTV_CHECK(mm(false, false, n, bb, bb, -1.0, Qy, n, X, bb, 1.0, Yb, n));
+  // the chain reversed: Zbar_q = Ybar
+  double* Zbar = Yb;
+  for (int j = q; j >= 0; --j) {
+    RUTV_CHECK(mm(false, true, m, n, bb, 1.0, Mj[j], m, Zbar, n, 1.0, Abar, ldab));
+    if (j == 0) break;
+    RUTV_CHECK(mm(false, false, m, bb, n, 1.0, A, lda, Zbar, n, 0.0, Mb, m));
+    RUTV_CHECK(mm(false, true, m, n, bb, 1.0, Mb, m, Zj[j - 1], n, 1.0, Abar, ldab));
+    double* next = Zbar == Yb ? Zb : Yb;
+    RUTV_CHECK(mm(true, false, n, bb, m, 1.0, A, lda, Mb, m, 0.0, next, n));
+    Zbar = next;
+  }
+  return finish();
+  });
+}
+
+int randutv_truncate_grad_k(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                            int32_t q, uint64_t seed, int64_t k, const double* Gbar, int64_t ldg,
+                            double* Abar, int64_t ldab) {
+  return guarded([&] {
+    return truncate_grad_k_impl(m, n, A, lda, b, q, seed, k, Gbar, ldg, Abar, ldab);
+  });
+}
+
+int randutv_truncate_first_block_k(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                                   int32_t q, uint64_t seed, int64_t k, double* Ak, int64_t ldak) {
+  if (!Ak) return -9;
+  return guarded([&] {
+    return truncate_grad_k_impl(m, n, A, lda, b, q, seed, k, nullptr, 0, nullptr, 0, Ak, ldak);
   });
 }
 

@@ -221,4 +221,69 @@ int copy_matrix(hipStream_t st, i64 rows, i64 cols, const double* Y, i64 ldy, do
   return RANDUTV_OK;
 }
 
+// X(:, i) *= c / lam[i] for i < cols (rows x cols, ld ldx); flag[0] |= 1 where
+// lam[i] is zero or the result is not finite
+__global__ __launch_bounds__(256) void scale_cols_kernel(i64 rows, i64 cols, double* __restrict__ X,
+                                                         i64 ldx, const double* __restrict__ lam,
+                                                         double c, int* __restrict__ flag) {
+  const i64 total = rows * cols;
+  int bad = 0;
+  for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
+    const i64 r = e % rows, i = e / rows;
+    const double l = lam[i];
+    const double v = X[r + i * ldx] * (c / l);
+    if (l == 0.0 || !isfinite(v)) bad = 1;
+    X[r + i * ldx] = v;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+int scale_cols(hipStream_t st, i64 rows, i64 cols, double* X, i64 ldx, const double* lam,
+               double c, int* flag) {
+  if (rows <= 0 || cols <= 0) return RANDUTV_OK;
+  const int blocks = (int)std::min<i64>(cdiv(rows * cols, 256), 16384);
+  scale_cols_kernel<<<blocks, 256, 0, st>>>(rows, cols, X, ldx, lam, c, flag);
+  RUTV_TRY(hipGetLastError());
+  return RANDUTV_OK;
+}
+
+// X (r x k, ld ldx): X[j, i] *= 2 / (d_i^2 - d_{k+j}^2), the eigenvalue gaps of
+// d (descending singular values); flag[0] |= 1 on a zero gap or a
+// non-finite result
+__global__ __launch_bounds__(256) void gap_divide_kernel(i64 r, i64 k, double* __restrict__ X,
+                                                         i64 ldx, const double* __restrict__ d,
+                                                         int* __restrict__ flag) {
+  const i64 total = r * k;
+  int bad = 0;
+  for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
+    const i64 j = e % r, i = e / r;
+    const double gap = d[i] * d[i] - d[k + j] * d[k + j];
+    const double v = X[j + i * ldx] * (2.0 / gap);
+    if (gap == 0.0 || !isfinite(v)) bad = 1;
+    X[j + i * ldx] = v;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+int gap_divide(hipStream_t st, i64 r, i64 k, double* X, i64 ldx, const double* d, int* flag) {
+  if (r <= 0 || k <= 0) return RANDUTV_OK;
+  const int blocks = (int)std::min<i64>(cdiv(r * k, 256), 16384);
+  gap_divide_kernel<<<blocks, 256, 0, st>>>(r, k, X, ldx, d, flag);
+  RUTV_TRY(hipGetLastError());
+  return RANDUTV_OK;
+}
+
+// lam[i] := d[i]^2
+__global__ void square_kernel(i64 n, const double* __restrict__ d, double* __restrict__ lam) {
+  const i64 i = (i64)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) lam[i] = d[i] * d[i];
+}
+
+int square_vec(hipStream_t st, i64 n, const double* d, double* lam) {
+  if (n <= 0) return RANDUTV_OK;
+  square_kernel<<<(int)cdiv(n, 256), 256, 0, st>>>(n, d, lam);
+  RUTV_TRY(hipGetLastError());
+  return RANDUTV_OK;
+}
+
 }  // namespace rutv

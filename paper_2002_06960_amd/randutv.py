@@ -40,6 +40,20 @@ class RandutvArgs(ctypes.Structure):
                 ("spin_limit", ctypes.c_uint32), ("max_workspace_bytes", ctypes.c_int64)]
 
 
+class RandutvOocStats(ctypes.Structure):
+    """struct randutv_ooc_stats of include/randutv.h (field for field)."""
+    _fields_ = [("struct_size", ctypes.c_int64), ("real_ms", ctypes.c_double),
+                ("compute_ms", ctypes.c_double), ("io_ms", ctypes.c_double),
+                ("h2d_ms", ctypes.c_double), ("d2h_ms", ctypes.c_double),
+                ("h2d_bytes", ctypes.c_int64), ("d2h_bytes", ctypes.c_int64),
+                ("tile_loads", ctypes.c_int64), ("tile_writebacks", ctypes.c_int64),
+                ("tile_hits", ctypes.c_int64), ("slots", ctypes.c_int64),
+                ("slot_bytes", ctypes.c_int64), ("fixed_bytes", ctypes.c_int64)]
+
+
+OOC_MODES = {"traditional": 0, "cached": 1, "overlapped": 2}
+
+
 def make_args(**kw) -> RandutvArgs:
     a = RandutvArgs()
     ctypes.memset(ctypes.byref(a), 0, ctypes.sizeof(a))
@@ -55,12 +69,18 @@ SIGNATURES = {
     "randutv_factor": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P]),
     "randutv_factor_ex": (ctypes.c_int, [ctypes.POINTER(RandutvArgs)]),
     "randutv_factor_noalloc": (ctypes.c_int, [ctypes.POINTER(RandutvArgs)]),
+    "randutv_factor_ooc": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64, _P, _I64,
+                                          _P, _I64, _I64, _I32, ctypes.c_void_p]),
     "randutv_sketch_host": (ctypes.c_int, [_U64, _I64, _I64, _I64, _P]),
     "randutv_sketch_words": (ctypes.c_int, [_U64, _U64, _U64, _I64, _P]),
     "randutv_finalize": (ctypes.c_int, []),
     "randutv_truncate": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _P]),
     "randutv_truncate_grad": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64, _P, _I64]),
     "randutv_truncate_first_block": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64]),
+    "randutv_truncate_grad_k": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _I64, _P, _I64,
+                                               _P, _I64]),
+    "randutv_truncate_first_block_k": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _I64, _P,
+                                                      _I64]),
     "randutv_hqrrp": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _U64, _P, _P]),
     "randutv_sketch": (ctypes.c_int, [_U64, _U64, _I64, _I64, _P, _I64]),
     "randutv_dgemm": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
@@ -249,6 +269,63 @@ def randutv_factor(A, b: int, q: int, seed: int = 0, build_u: bool = True,
     return U, T, V
 
 
+def host_colmajor_empty(rows: int, cols: int, pinned: bool = True):
+    """Column-major float64 host tensor (page-locked unless pinned=False)."""
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=torch.float64, pin_memory=pinned).t()
+
+
+def _host_colmajor(x, name):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or x.is_cuda:
+        raise TypeError(f"{name} must be a float64 host (CPU) tensor")
+    if x.dim() != 2 or x.stride(0) != 1 or (x.shape[1] > 1 and x.stride(1) < x.shape[0]):
+        raise ValueError(f"{name} must be column-major (stride (1, ld), ld >= rows)")
+    return x, max(1, x.stride(1) if x.shape[1] > 1 else x.shape[0])
+
+
+def randutv_factor_ooc(A, b: int, q: int, seed: int = 0, hbm_budget_bytes: int = 1 << 30,
+                       mode: str = "overlapped", build_u: bool = True, build_v: bool = True,
+                       in_place: bool = False, U=None, T=None, V=None):
+    """Out-of-core A = U T V^T with A, U, T, V in host memory and at most
+    hbm_budget_bytes of HBM for the tile cache (mode: traditional, cached or
+    overlapped).  A is a column-major float64 CPU tensor (page-locked for
+    overlapped copies).  Returns (U, T, V, stats) with page-locked
+    column-major CPU tensors (U/V None if not built) and the call's
+    statistics as a dict."""
+    lib = load()
+    A, lda = _host_colmajor(A, "A")
+    m, n = A.shape
+    if mode not in OOC_MODES:
+        raise ValueError(f"mode must be one of {sorted(OOC_MODES)}")
+    if in_place:
+        T, ldt = A, lda
+    else:
+        T = host_colmajor_empty(m, n) if T is None else T
+        T, ldt = _host_colmajor(T, "T")
+    if build_u:
+        U = host_colmajor_empty(m, m) if U is None else U
+        U, ldu = _host_colmajor(U, "U")
+    else:
+        U, ldu = None, m
+    if build_v:
+        V = host_colmajor_empty(n, n) if V is None else V
+        V, ldv = _host_colmajor(V, "V")
+    else:
+        V, ldv = None, n
+    for x, name, shape in ((T, "T", (m, n)), (U, "U", (m, m)), (V, "V", (n, n))):
+        if x is not None and tuple(x.shape) != shape:
+            raise ValueError(f"{name} must have shape {shape}")
+    st = RandutvOocStats()
+    st.struct_size = ctypes.sizeof(st)
+    _check("randutv_factor_ooc",
+           lib.randutv_factor_ooc(m, n, A.data_ptr(), lda, b, q, seed, _ptr(U), ldu, T.data_ptr(), ldt,
+                                  _ptr(V), ldv, int(hbm_budget_bytes), OOC_MODES[mode],
+                                  ctypes.byref(st)))
+    stats = {f: getattr(st, f) for f, _ in RandutvOocStats._fields_ if f != "struct_size"}
+    return U, T, V, stats
+
+
 def randutv_truncate(U, T, V, k: int):
     """A_k = U(:, :k) T(:k, :) V^T."""
     lib = load()
@@ -317,53 +394,110 @@ def randutv_truncate_grad(A, b: int, q: int, seed: int, Gbar):
     return Abar
 
 
+def randutv_truncate_grad_k(A, b: int, q: int, seed: int, k: int, Gbar):
+    """dL/dA for the truncation A_k (0 < k <= min(b, n)) of
+    randutv_factor(A, b, q, seed), given Gbar = dL/dA_k (sketch held fixed)."""
+    lib = load()
+    A, lda = as_colmajor(A)
+    Gbar, ldg = as_colmajor(Gbar)
+    m, n = A.shape
+    if tuple(Gbar.shape) != (m, n):
+        raise ValueError("Gbar must have the shape of A")
+    Abar = colmajor_empty(m, n, A.device)
+    _sync()
+    _check("randutv_truncate_grad_k",
+           lib.randutv_truncate_grad_k(m, n, _ptr(A), lda, b, q, seed & (2**64 - 1), k, _ptr(Gbar), ldg,
+                                       _ptr(Abar), max(1, m)))
+    return Abar
+
+
+def randutv_truncate_first_block_k(A, b: int, q: int, seed: int, k: int):
+    """A_k (0 < k <= min(b, n)) of randutv_factor(A, b, q, seed) from the first
+    step alone: the projection of A onto the leading k left singular vectors
+    of A orth((A^T A)^q A^T G(0))."""
+    lib = load()
+    A, lda = as_colmajor(A)
+    m, n = A.shape
+    Ak = colmajor_empty(m, n, A.device)
+    _sync()
+    _check("randutv_truncate_first_block_k",
+           lib.randutv_truncate_first_block_k(m, n, _ptr(A), lda, b, q, seed & (2**64 - 1), k, _ptr(Ak),
+                                              max(1, m)))
+    return Ak
+
+
 def _autograd_function():
     torch = _torch()
 
-    class FirstBlockTruncation(torch.autograd.Function):
-        """A -> A_k, k = min(b, n): randutv_factor then randutv_truncate on the
-        forward pass (or, with first_step_only, randutv_truncate_first_block),
-        randutv_truncate_grad on the reverse pass."""
+    class Truncation(torch.autograd.Function):
+        """A -> A_k (0 < k <= min(b, n)), the sketch G(0) held fixed.  Forward:
+        randutv_truncate_first_block(_k) (the first step fixes A_k), or with
+        full_factorization randutv_factor then randutv_truncate; reverse:
+        randutv_truncate_grad(_k) (the _k forms for k < min(b, n)).  The library computes in FP64; a float32
+        input is promoted and the results are returned as float32."""
 
         @staticmethod
-        def forward(ctx, A, b, q, seed, first_step_only):
-            def one(X):
-                if first_step_only:
-                    return randutv_truncate_first_block(X, b, q, seed)
-                U, T, V = randutv_factor(X, b, q, seed)
-                return randutv_truncate(U, T, V, min(b, X.shape[1]))
+        def forward(ctx, A, b, q, seed, k, full_factorization):
+            dtype = A.dtype
+            X64 = A.to(torch.float64)
 
-            Ak = torch.stack([one(X) for X in A]) if A.dim() == 3 else one(A)
-            ctx.save_for_backward(A)
-            ctx.b, ctx.q, ctx.seed = b, q, seed
-            return Ak
+            def one(X):
+                if full_factorization:
+                    U, T, V = randutv_factor(X, b, q, seed, build_u=True, build_v=True)
+                    return randutv_truncate(U, T, V, k)
+                if k == min(b, X.shape[1]):  # the whole first block: Q Q^T A
+                    return randutv_truncate_first_block(X, b, q, seed)
+                return randutv_truncate_first_block_k(X, b, q, seed, k)
+
+            Ak = torch.stack([one(X) for X in X64]) if A.dim() == 3 else one(X64)
+            ctx.save_for_backward(X64)
+            ctx.b, ctx.q, ctx.seed, ctx.k, ctx.dtype = b, q, seed, k, dtype
+            return Ak.to(dtype)
 
         @staticmethod
         def backward(ctx, gout):
             (A,) = ctx.saved_tensors
+            g64 = gout.to(torch.float64)
+            def one(X, G):
+                if ctx.k == min(ctx.b, X.shape[1]):
+                    return randutv_truncate_grad(X, ctx.b, ctx.q, ctx.seed, G)
+                return randutv_truncate_grad_k(X, ctx.b, ctx.q, ctx.seed, ctx.k, G)
+
             if A.dim() == 3:
-                g = torch.stack([randutv_truncate_grad(X, ctx.b, ctx.q, ctx.seed, G) for X, G in zip(A, gout)])
+                g = torch.stack([one(X, G) for X, G in zip(A, g64)])
             else:
-                g = randutv_truncate_grad(A, ctx.b, ctx.q, ctx.seed, gout)
-            return g, None, None, None, None
+                g = one(A, g64)
+            return g.to(ctx.dtype), None, None, None, None, None
 
-    return FirstBlockTruncation
+    return Truncation
 
 
-_first_block_fn = None
+_truncation_fn = None
+
+
+def truncation(A, b: int, q: int, seed: int = 0, k: Optional[int] = None,
+               full_factorization: bool = False):
+    """Differentiable rank-k truncation A_k = U_k T_k V^T of randutv_factor(A,
+    b, q, seed) for 0 < k <= min(b, n) (default k = min(b, n)), the sketch
+    G(0) held fixed.  The forward value comes from the first step alone by
+    default: the first step already fixes U's first min(b, n) columns, so the
+    later steps do not change A_k (full_factorization=True runs them anyway;
+    both agree to rounding amplified by the conditioning of the sketch).
+    A may be a batch (batch x m x n), float64 or float32 (computed in FP64)."""
+    global _truncation_fn
+    if _truncation_fn is None:
+        _truncation_fn = _autograd_function()
+    n = A.shape[-1]
+    kk = min(b, n) if k is None else int(k)
+    if not 0 < kk <= min(b, n):
+        raise ValueError(f"k must lie in 1..min(b, n) = {min(b, n)}")
+    return _truncation_fn.apply(A, b, q, seed, kk, full_factorization)
 
 
 def first_block_truncation(A, b: int, q: int, seed: int = 0, first_step_only: bool = False):
-    """Differentiable rank-k truncation of randUTV at k = min(b, n), the
-    sketch G(0) held fixed: returns A_k = U_k T_k V^T as a tensor that
-    torch.autograd differentiates through randutv_truncate_grad.  With
-    first_step_only the forward value comes from the first step alone
-    (the same A_k without factoring the rest of A).  A may be a batch
-    (batch x m x n): each matrix is factored with the same (b, q, seed)."""
-    global _first_block_fn
-    if _first_block_fn is None:
-        _first_block_fn = _autograd_function()
-    return _first_block_fn.apply(A, b, q, seed, first_step_only)
+    """truncation() at k = min(b, n); first_step_only=False runs the whole
+    factorization for the forward value."""
+    return truncation(A, b, q, seed, None, full_factorization=not first_step_only)
 
 
 def randutv_sketch(seed: int, step: int, rows: int, cols: int, device=None):

@@ -152,3 +152,108 @@ def test_grad_padded_leading_dimensions():
     got = to_host(pkg.randutv_truncate_grad(Av, b, q, 2, Gv))
     ref = tg.first_block_truncation_grad(A, b, q, 2, Gbar)
     assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def _cond_y(A, b, q, seed):
+    Y = A.T @ tg.first_block_sketch(A, b, seed)
+    for _ in range(q):
+        Y = A.T @ (A @ Y)
+    return np.linalg.cond(Y)
+
+
+@pytest.mark.parametrize("m,n,b,q,k,kind", [(512, 512, 64, 2, 32, "exp"), (600, 400, 32, 1, 7, "iid"),
+                                            (700, 500, 128, 2, 100, "exp98"), (257, 200, 48, 0, 48, "exp"),
+                                            (300, 300, 64, 1, 1, "exp")])
+def test_grad_k_matches_reference(m, n, b, q, k, kind):
+    """k <= b: the GPU reverse pass (randutv_truncate_grad_k) against torch's
+    reverse mode through the QR of Y and the SVD of A orth(Y) on the CPU.  Both
+    go through R_Y^{-1} and the eigenvalue gaps of the first block: bound
+    100 u cond(Y) times the largest d_1^2 / (d_k^2 - d_{k+1}^2)."""
+    A = make_matrix(kind, m, n, seed=6)
+    rng = np.random.default_rng(m + n + k)
+    Gbar = rng.standard_normal((m, n))
+    ref = tg.first_block_truncation_k_grad(A, b, q, 9, k, Gbar)
+    got = to_host(pkg.randutv_truncate_grad_k(to_dev(A), b, q, 9, k, to_dev(Gbar)))
+    Y = A.T @ tg.first_block_sketch(A, b, 9)
+    for _ in range(q):
+        Y = A.T @ (A @ Y)
+    Qy = np.linalg.qr(Y)[0]
+    d = np.linalg.svd(A @ Qy, compute_uv=False)
+    gap = d[0] ** 2 / (d[k - 1] ** 2 - d[k] ** 2) if k < min(b, n) else 1.0
+    tol = max(1e-12, 100 * 2.0 ** -52 * np.linalg.cond(Y) * gap)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"truncation grad k={k} {m}x{n} b={b} q={q} {kind}: max rel err {err:.2e} (bound {tol:.1e})")
+    assert err <= tol
+
+
+def test_grad_k_at_b_equals_grad():
+    A = make_matrix("exp", 400, 300, seed=8)
+    Gbar = np.random.default_rng(2).standard_normal((400, 300))
+    g1 = to_host(pkg.randutv_truncate_grad(to_dev(A), 64, 2, 3, to_dev(Gbar)))
+    g2 = to_host(pkg.randutv_truncate_grad_k(to_dev(A), 64, 2, 3, 64, to_dev(Gbar)))
+    tol = max(1e-12, 100 * 2.0 ** -52 * _cond_y(A, 64, 2, 3))
+    assert np.abs(g1 - g2).max() <= tol * np.abs(g1).max()
+
+
+@pytest.mark.parametrize("k", [16, 32])
+def test_grad_k_matches_finite_differences_of_the_gpu_forward(k):
+    """256 x 256, b = 32, q = 2: directional derivatives of <Gbar, A_k> with A_k
+    from the GPU's full factorization (randutv_factor + randutv_truncate) at
+    k = b/2 and k = b, against randutv_truncate_grad_k."""
+    m = n = 256
+    b, q = 32, 2
+    A = make_matrix("exp98", m, n, seed=3)
+    rng = np.random.default_rng(10 + k)
+    Gbar = rng.standard_normal((m, n))
+    Gd = to_dev(Gbar)
+    grad = to_host(pkg.randutv_truncate_grad_k(to_dev(A), b, q, 4, k, Gd))
+
+    def L(X):
+        U, T, V = pkg.randutv_factor(to_dev(X), b, q, 4)
+        return float((pkg.randutv_truncate(U, T, V, k) * Gd).sum())
+
+    h = 1e-6
+    for _ in range(3):
+        E = rng.standard_normal((m, n))
+        fd = (L(A + h * E) - L(A - h * E)) / (2 * h)
+        an = float(np.sum(grad * E))
+        print(f"fd k={k}: {fd:.10e} analytic {an:.10e}")
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+def test_grad_k_errors():
+    A = to_dev(make_matrix("exp", 64, 48, seed=1))
+    G = to_dev(np.ones((64, 48)))
+    lib = pkg.load()
+    assert lib.randutv_truncate_grad_k(64, 48, A.data_ptr(), 64, 16, 1, 0, 0, G.data_ptr(), 64,
+                                       G.data_ptr() + 8, 64) == -8          # k < 1
+    assert lib.randutv_truncate_grad_k(64, 48, A.data_ptr(), 64, 16, 1, 0, 17, G.data_ptr(), 64,
+                                       G.data_ptr() + 8, 64) == -8          # k > b
+    Z = to_dev(np.zeros((64, 48)))
+    with pytest.raises(pkg.RandUTVError) as e:
+        pkg.randutv_truncate_grad_k(Z, 16, 1, 0, 8, G)
+    assert e.value.code == 7  # RANDUTV_ERR_RANK: Y = 0 has no range to project on
+
+
+def test_truncation_autograd_k_fp32_and_batch():
+    """truncation(): k < b, float32 input (computed in FP64, returned in
+    float32), a batch of two, forward from the first step against the full
+    factorization's truncation, and A.grad against the CPU reference."""
+    m, n, b, q, k = 320, 256, 64, 2, 24
+    A = np.stack([make_matrix("exp98", m, n, seed=s) for s in (11, 12)])
+    B = np.random.default_rng(4).standard_normal((2, m, n))
+    Ad = torch.from_numpy(A).cuda().to(torch.float32).requires_grad_(True)
+    Ak = pkg.truncation(Ad, b, q, 5, k)
+    assert Ak.dtype == torch.float32 and Ak.shape == (2, m, n)
+    loss = ((Ak - torch.from_numpy(B).cuda().to(torch.float32)) ** 2).sum()
+    loss.backward()
+    A32 = A.astype(np.float32).astype(np.float64)  # the values the library saw
+    for t in range(2):
+        ref_ak = tg.first_block_truncation_k(A32[t], b, q, 5, k)
+        full = pkg.truncation(torch.from_numpy(A32[t]).cuda(), b, q, 5, k, full_factorization=True)
+        assert np.abs(to_host(Ak.detach()[t]).astype(np.float64) - ref_ak).max() <= 1e-6 * np.abs(A32[t]).max()
+        assert np.abs(to_host(full) - ref_ak).max() <= 1e-9 * np.abs(A32[t]).max()
+        gbar = 2.0 * (to_host(Ak.detach()[t]).astype(np.float64) - B[t].astype(np.float32).astype(np.float64))
+        ref = tg.first_block_truncation_k_grad(A32[t], b, q, 5, k, gbar)
+        got = to_host(Ad.grad[t]).astype(np.float64)
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()

@@ -62,3 +62,51 @@ def test_gradient_has_the_subspace_term():
     Q = np.linalg.qr(Ak)[0][:, :8]
     naive = Q @ (Q.T @ Gbar)
     assert np.linalg.norm(grad - naive) > 0.1 * np.linalg.norm(grad)
+
+
+def _algorithm_truncation_k(A, b, q, seed, k):
+    U, T, V = ro.randutv(A, b, q, seed)
+    return ro.truncate(U, T, V, k)
+
+
+@pytest.mark.parametrize("m,n,b,q,k", [(60, 40, 8, 1, 3), (50, 50, 10, 2, 5), (45, 30, 6, 0, 1),
+                                       (40, 40, 12, 1, 12), (30, 20, 25, 1, 7)])
+def test_closed_form_k_is_the_algorithms_truncation(m, n, b, q, k):
+    """For k <= b the step loop's A_k equals the projection onto the leading k
+    left singular vectors of A orth(Y); at k = b it is Q Q^T A as before."""
+    A = _matrix(m, n, seed=m + 3 * n)
+    ref = _algorithm_truncation_k(A, b, q, 3, k)
+    got = tg.first_block_truncation_k(A, b, q, 3, k)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(A).max()
+    if k == min(b, n):
+        assert np.abs(got - tg.first_block_truncation(A, b, q, 3)).max() <= 1e-12 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("m,n,b,q,k", [(40, 30, 8, 1, 4), (36, 36, 6, 2, 3), (30, 24, 10, 0, 9)])
+def test_gradient_k_matches_finite_differences_of_the_algorithm(m, n, b, q, k):
+    """k < b: the reference gradient (reverse mode through the QR of Y and the
+    SVD of A orth(Y)) against central differences of the step loop's A_k."""
+    A = _matrix(m, n, seed=5 * m + n, decay=0.8)
+    rng = np.random.default_rng(13)
+    Gbar = rng.standard_normal((m, n))
+    grad = tg.first_block_truncation_k_grad(A, b, q, 5, k, Gbar)
+    h = 1e-6
+    for t in range(3):
+        E = rng.standard_normal((m, n))
+        fp = np.sum(Gbar * _algorithm_truncation_k(A + h * E, b, q, 5, k))
+        fm = np.sum(Gbar * _algorithm_truncation_k(A - h * E, b, q, 5, k))
+        fd = (fp - fm) / (2 * h)
+        an = np.sum(grad * E)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (t, fd, an)
+
+
+def test_gradient_k_has_the_in_block_term():
+    """For k < b the singular-subspace rotation inside the first block
+    contributes: the k = b formula's gradient (projector onto the whole block)
+    misses the k < b one by far."""
+    A = _matrix(40, 30, seed=2, decay=0.8)
+    rng = np.random.default_rng(3)
+    Gbar = rng.standard_normal((40, 30))
+    gk = tg.first_block_truncation_k_grad(A, 8, 1, 5, 4, Gbar)
+    gb = tg.first_block_truncation_grad(A, 8, 1, 5, Gbar)
+    assert np.linalg.norm(gk - gb) > 0.1 * np.linalg.norm(gk)
