@@ -338,22 +338,31 @@ int randutv_truncate_grad(int64_t m, int64_t n, const double* A, int64_t lda,
 
 /*
  * randutv_truncate_grad_k -- reverse pass of the truncation A_k of
- * randutv_factor(m, n, A, lda, b, q, seed, ...) for any 0 < k <= min(b, n),
- * with the sketch G(0) held fixed (Section 1.1 for A_k, Section 3.1 for the
- * first step).  After step 0, U's first min(b, n) columns are the leading
- * left singular vectors of C = A Q_Y, Q_Y an orthonormal basis of
- * Y = (A^T A)^q A^T G(0) (the panel Q of C times the b x b SVD's left
- * factor), so A_k = U_k U_k^T A projects A onto C's leading k left singular
- * vectors; the reverse pass differentiates that projector (the eigenvalue
- * gaps d_i^2 - d_j^2 of the first block enter for i < k <= j) and the power
- * chain.  k = min(b, n) gives randutv_truncate_grad's value.
+ * randutv_factor(m, n, A, lda, b, q, seed, ...) for any
+ * 0 < k <= b_0 + b_1 (b_0 = min(b, n), b_1 = min(b, n - b_0): the first two
+ * blocks of U), with the sketches G(0) and G(1) held fixed (Section 1.1 for
+ * A_k, Section 3.1 for the steps).
+ * k <= b_0: after step 0, U's first b_0 columns are the leading left singular
+ * vectors of C = A Q_Y, Q_Y an orthonormal basis of Y = (A^T A)^q A^T G(0)
+ * (the panel Q of C times the b x b SVD's left factor), so A_k = U_k U_k^T A
+ * projects A onto C's leading k left singular vectors; the reverse pass
+ * differentiates that projector (the eigenvalue gaps d_i^2 - d_j^2 of the
+ * first block enter for i < k <= j) and the power chain.  k = b_0 gives
+ * randutv_truncate_grad's value.
+ * b_0 < k <= b_0 + b_1: A_k = Q_H Q_H^T A + U_2 U_2^T A with Q_H step 0's
+ * panel Q and U_2 the leading k - b_0 left singular vectors of step 1's
+ * C_1 = (I - Q_H Q_H^T) A Q_t, Q_t orthonormal for step 1's powered sketch of
+ * the trailing matrix; that sketch is drawn in the coordinates of step 0's
+ * Householder complements, so the reverse pass also runs through the
+ * reflectors (an unpivoted LU of [I; 0] - Q_H) and both thin QRs of step 0.
  *   Gbar : m x n (ld ldg), dL/dA_k.   Abar : m x n (ld ldab) output, dL/dA.
  * Device pointers, column-major FP64, synchronous.  Errors: -1 m, -2 n,
  * -3 A, -4 lda, -5 b, -6 q (q < 0 or q > 64), -8 k, -9 Gbar, -10 ldg,
  * -11 Abar (NULL or aliasing), -12 ldab; RANDUTV_ERR_TOO_LARGE for
- * min(b, n) > 256; RANDUTV_ERR_NONFINITE; RANDUTV_ERR_RANK when C's leading
- * k singular values include zero or d_k = d_{k+1} (no derivative there);
- * RANDUTV_ERR_NOCONV / RANDUTV_ERR_SYNC from the b x b SVD.
+ * min(b, n) > 256; RANDUTV_ERR_NONFINITE; RANDUTV_ERR_RANK when a singular
+ * value that enters is zero, a gap d_k = d_{k+1} is zero (no derivative
+ * there) or a triangular factor is singular; RANDUTV_ERR_NOCONV /
+ * RANDUTV_ERR_SYNC from a b x b SVD.
  */
 int randutv_truncate_grad_k(int64_t m, int64_t n, const double* A, int64_t lda,
                             int64_t b, int32_t q, uint64_t seed, int64_t k,
@@ -361,10 +370,11 @@ int randutv_truncate_grad_k(int64_t m, int64_t n, const double* A, int64_t lda,
 
 /*
  * randutv_truncate_first_block_k -- the forward value of the truncation A_k,
- * 0 < k <= min(b, n), of randutv_factor(m, n, A, lda, b, q, seed, ...) from
- * the first step alone: A_k = U_1 U_1^T A with U_1 the leading k left
- * singular vectors of C = A Q_Y (see randutv_truncate_grad_k; Section 1.1,
- * Section 3.1).  Ak: m x n output (ld ldak), must not alias A.  Device
+ * 0 < k <= b_0 + b_1 (b_0 = min(b, n), b_1 = min(b, n - b_0)), of
+ * randutv_factor(m, n, A, lda, b, q, seed, ...) from its first step (k <= b_0)
+ * or first two steps alone: A_k = U_k U_k^T A as described at
+ * randutv_truncate_grad_k (Section 1.1, Section 3.1).  Ak: m x n output
+ * (ld ldak), must not alias A.  Device
  * pointers, column-major FP64, synchronous.  Errors: -1 m, -2 n, -3 A,
  * -4 lda, -5 b, -6 q, -8 k, -9 Ak, -10 ldak; RANDUTV_ERR_TOO_LARGE,
  * RANDUTV_ERR_NONFINITE, RANDUTV_ERR_NOCONV, RANDUTV_ERR_SYNC.
@@ -372,6 +382,27 @@ int randutv_truncate_grad_k(int64_t m, int64_t n, const double* A, int64_t lda,
 int randutv_truncate_first_block_k(int64_t m, int64_t n, const double* A, int64_t lda,
                                    int64_t b, int32_t q, uint64_t seed, int64_t k,
                                    double* Ak, int64_t ldak);
+
+/*
+ * randutv_truncate_batched -- randutv_truncate_first_block_k (reverse == 0)
+ * or randutv_truncate_grad_k (reverse == 1) for `batch` matrices of the same
+ * shape and the same (b, q, seed, k) in one call (Section 1.1, Section 3.1):
+ * matrix t is A + t stride_a (ld lda), its Gbar is Gbar + t stride_g (ld ldg,
+ * reverse only), and its result goes to out + t stride_o (ld ldo).  The
+ * matrices are spread over the library's streams, each with a workspace of
+ * its own, so that their launches overlap; every result equals the
+ * single-matrix call's bit for bit.  Device pointers, column-major FP64,
+ * synchronous.  Errors: -1 batch, -2 reverse, -3 m, -4 n, -5 A, -6 lda,
+ * -7 stride_a (< lda n with batch > 1), -8 b, -9 q, -11 k, -12 Gbar, -13 ldg,
+ * -14 stride_g, -15 out (NULL or aliasing A or Gbar), -16 ldo, -17 stride_o;
+ * then the run-time errors of the single calls (the first one met, in batch
+ * order).
+ */
+int randutv_truncate_batched(int64_t batch, int32_t reverse, int64_t m, int64_t n,
+                             const double* A, int64_t lda, int64_t stride_a, int64_t b,
+                             int32_t q, uint64_t seed, int64_t k, const double* Gbar,
+                             int64_t ldg, int64_t stride_g, double* out, int64_t ldo,
+                             int64_t stride_o);
 
 /*
  * randutv_sketch -- write the sketch G(step) (rows x cols, ld = ldg) that

@@ -89,3 +89,102 @@ def first_block_truncation_grad(A: np.ndarray, b: int, q: int, seed: int, Gbar: 
     Ak = _closed_form(At, G, q)
     (Ak * torch.from_numpy(np.asarray(Gbar, dtype=np.float64))).sum().backward()
     return At.grad.numpy()
+
+
+def _lu_unpivoted(M):
+    """M = L U for an m x b matrix (m >= b) without pivoting: L unit lower
+    trapezoidal (m x b), U upper triangular (b x b).  Column-by-column
+    Doolittle in torch ops (differentiable)."""
+    m, b = M.shape
+    Lcols, Urows = [], []
+    for j in range(b):
+        # row j of U: M[j, j:] - L[j, :j] U[:j, j:]
+        u = M[j, :]
+        for t in range(j):
+            u = u - Lcols[t][j] * Urows[t]
+        u = torch.cat([torch.zeros(j, dtype=M.dtype), u[j:]])
+        Urows.append(u)
+        # column j of L: (M[:, j] - sum_t L[:, t] U[t, j]) / U[j, j], unit at row j, zero above
+        l_ = M[:, j]
+        for t in range(j):
+            l_ = l_ - Lcols[t] * Urows[t][j]
+        l_ = l_ / u[j]
+        l_ = torch.cat([torch.zeros(j, dtype=M.dtype), torch.ones(1, dtype=M.dtype), l_[j + 1:]])
+        Lcols.append(l_)
+    return torch.stack(Lcols, dim=1), torch.stack(Urows, dim=0)
+
+
+def _closed_form_two_blocks(At, G0, G1, q: int, k: int):
+    """A_k for b_0 < k <= b_0 + b_1 (the first two blocks of U).
+
+    Step 0 (Section 3.1): Q_V = Householder Q of Y_0 = (A^T A)^q A^T G(0), and
+    U's first block spans C_0 = A Q_V, whose Householder QR gives the thin Q_H
+    and the full reflector product H.  Step 1 sketches the trailing matrix
+    B_1 = U_perp^T A V_perp in the coordinates of the complement columns
+    U_perp = H(:, b_0:), V_perp of those Householder products; lifted back to A's
+    space, its sketch is Gamma = U_perp G(1), its powered sketch spans
+    Pi_V (A^T Pi_U A Pi_V)^q A^T Gamma (Pi_U = I - Q_H Q_H^T, Pi_V = I - Q_V Q_V^T),
+    and U's second block holds the left singular vectors of
+    C_1 = Pi_U A orth(that sketch).  Everything but U_perp depends on subspaces
+    only; U_perp comes from the reflectors: with M = [I; 0] - Q_H = W (T W_1^T)
+    (an LU factorization without pivoting: W unit lower trapezoidal, T W_1^T upper
+    triangular), U_perp = [0; I] - M W_1^{-T} W_2^T.  So
+    A_k = Q_H Q_H^T A + U_2 U_2^T A, U_2 the leading k - b_0 left singular
+    vectors of C_1."""
+    m, n = At.shape
+    b0 = G0.shape[1]
+    Y0 = At.T @ G0
+    for _ in range(q):
+        Y0 = At.T @ (At @ Y0)
+    Qv, _ = torch.linalg.qr(Y0, mode="reduced")
+    C0 = At @ Qv
+    Qh, _ = torch.linalg.qr(C0, mode="reduced")
+    I0 = torch.zeros((m, b0), dtype=At.dtype)
+    I0[:b0, :b0] = torch.eye(b0, dtype=At.dtype)
+    M = I0 - Qh
+    W, _ = _lu_unpivoted(M)
+    W1, W2 = W[:b0], W[b0:]
+    # Gamma = [0; G(1)] - M W_1^{-T} (W_2^T G(1))
+    X = torch.linalg.solve_triangular(W1.T, W2.T @ G1, upper=True, unitriangular=True)
+    Gam = torch.cat([torch.zeros((b0, G1.shape[1]), dtype=At.dtype), G1], dim=0) - M @ X
+
+    def pi_u(Z):
+        return Z - Qh @ (Qh.T @ Z)
+
+    def pi_v(Z):
+        return Z - Qv @ (Qv.T @ Z)
+
+    Yt = pi_v(At.T @ Gam)
+    for _ in range(q):
+        Yt = pi_v(At.T @ pi_u(At @ Yt))
+    Qt, _ = torch.linalg.qr(Yt, mode="reduced")
+    C1 = pi_u(At @ Qt)
+    U1c, _, _ = torch.linalg.svd(C1, full_matrices=False)
+    U2 = U1c[:, : k - b0]
+    return Qh @ (Qh.T @ At) + U2 @ (U2.T @ At)
+
+
+def _two_block_sketches(A: np.ndarray, b: int, seed: int):
+    m, n = A.shape
+    b0 = min(b, n)
+    b1 = min(b, n - b0)
+    return sketch_block(seed, 0, m, b0), sketch_block(seed, 1, m - b0, b1)
+
+
+def two_block_truncation(A: np.ndarray, b: int, q: int, seed: int, k: int) -> np.ndarray:
+    """A_k for b_0 < k <= b_0 + b_1 (b_0 = min(b, n), b_1 = min(b, n - b_0))."""
+    At = torch.from_numpy(np.asarray(A, dtype=np.float64))
+    G0, G1 = (torch.from_numpy(g) for g in _two_block_sketches(A, b, seed))
+    return _closed_form_two_blocks(At, G0, G1, q, k).numpy()
+
+
+def two_block_truncation_grad(A: np.ndarray, b: int, q: int, seed: int, k: int,
+                              Gbar: np.ndarray) -> np.ndarray:
+    """d<Gbar, A_k>/dA for b_0 < k <= b_0 + b_1, G(0) and G(1) fixed, by torch's
+    reverse mode through the closed form (the QRs, the unpivoted LU of the
+    reflector block and the SVD)."""
+    At = torch.from_numpy(np.array(A, dtype=np.float64)).requires_grad_(True)
+    G0, G1 = (torch.from_numpy(g) for g in _two_block_sketches(A, b, seed))
+    Ak = _closed_form_two_blocks(At, G0, G1, q, k)
+    (Ak * torch.from_numpy(np.asarray(Gbar, dtype=np.float64))).sum().backward()
+    return At.grad.numpy()

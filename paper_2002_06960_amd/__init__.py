@@ -31,6 +31,7 @@ from .randutv import (  # noqa: F401
     randutv_truncate,
     randutv_truncate_first_block,
     randutv_truncate_first_block_k,
+    randutv_truncate_batched,
     randutv_truncate_grad,
     randutv_truncate_grad_k,
 )

@@ -130,6 +130,35 @@ int scale_cols(hipStream_t st, i64 rows, i64 cols, double* X, i64 ldx, const dou
 int gap_divide(hipStream_t st, i64 r, i64 k, double* X, i64 ldx, const double* d, int* flag);
 // lam[i] := d[i]^2
 int square_vec(hipStream_t st, i64 n, const double* d, double* lam);
+// k x k (ld k): mode 0 out = P_L(X - X^T), mode 1 out = P_L(X) - triu(Y), mode 2
+// out = P_L(X), with P_L the strictly lower part and triu the upper part
+int tri_combine(hipStream_t st, i64 k, const double* X, const double* Y, double* out, int mode);
+// X (k x k, ld k) := Y^T
+int transpose_square(hipStream_t st, i64 k, const double* Y, double* X);
+// X (rows x cols, ld ldx) := 0
+int zero_matrix(hipStream_t st, i64 rows, i64 cols, double* X, i64 ldx);
+// Y += alpha X (rows x cols)
+int axpy_matrix(hipStream_t st, i64 rows, i64 cols, double alpha, const double* X, i64 ldx, double* Y,
+                i64 ldy);
+
+// ---- truncation of the first block and its reverse pass (truncation.hip) ----
+struct TruncJob {
+  i64 m = 0, n = 0, lda = 0, b = 0, k = 0;  // 0 < k <= min(b, n)
+  int q = 0;
+  uint64_t seed = 0;
+  const double* A = nullptr;
+  const double* Gbar = nullptr;  // reverse pass only
+  i64 ldg = 0;
+  double* out = nullptr;         // A_k (forward) or dL/dA (reverse)
+  i64 ldo = 0;
+  bool reverse = false;
+};
+// device workspace (bytes) of one job
+size_t trunc_ws_bytes(const TruncJob& j);
+// enqueue one job on st with its workspace at base; status: 8 device ints
+int trunc_enqueue(const TruncJob& j, hipStream_t st, char* base, int* status);
+// the job's status code from its 8 status ints (copied to the host)
+int trunc_status(const int* flags, const TruncJob& j);
 
 // ---- out-of-core factorization (ooc.hip) -------------------------------------
 struct OocCfg {

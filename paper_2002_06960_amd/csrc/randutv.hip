@@ -962,437 +962,155 @@ int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint6
   });
 }
 
-// Forward value of the first-block truncation without the rest of the
-// factorization: A_k = Q Q^T A, Q an orthonormal basis of the range of
-// M = (A A^T)^(q+1) G(0) (k = min(b, n); the identity is explained at
-// randutv_truncate_grad below).
-int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
-                                 int32_t q, uint64_t seed, double* Ak, int64_t ldak) {
-  if (m < 0) return -1;
-  if (n < 0 || n > m) return -2;
-  if (m == 0 || n == 0) return RANDUTV_OK;
-  if (!A) return -3;
-  if (lda < std::max<int64_t>(1, m)) return -4;
-  if (b < 1) return -5;
-  if (q < 0) return -6;
-  if (!Ak || Ak == A) return -8;
-  if (ldak < std::max<int64_t>(1, m)) return -9;
-  const i64 k = std::min<i64>(b, n);
-  if (k > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
-  Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(g_mu);
-  return drained(cx, [&]() -> int {
-  RUTV_CHECK(cx.init());
-  hipStream_t st = cx.st;
-  i64 sk = 0;
-  for (auto s3 : {std::array<i64, 3>{n, k, m}, {m, k, n}, {k, k, m}, {k, k, k}, {m, k, k},
-                  {k, n, m}, {m, n, k}})
-    sk = std::max(sk, dgemm_work_elems(s3[0], s3[1], s3[2]));
-  double *M, *Z, *tau, *Wr, *Gram, *Tf, *X, *Q, *Cn, *wk;
-  int* status;
-  unsigned long long* xch;
-  auto lay = [&](Carver& c) {
-    M = c.take<double>(m * k);
-    Z = c.take<double>(n * k);
-    tau = c.take<double>(k);
-    Wr = c.take<double>(m * k);
-    Gram = c.take<double>(k * k);
-    Tf = c.take<double>(k * k);
-    X = c.take<double>(k * k);
-    Q = c.take<double>(m * k);
-    Cn = c.take<double>(k * n);
-    wk = c.take<double>(sk);
-    status = c.take<int>(4);
-    xch = c.take<unsigned long long>(panel_work_elems(m));
-  };
-  Carver probe;
-  lay(probe);
-  RUTV_CHECK(cx.reserve(probe.off));
-  Carver real;
-  real.base = cx.ws;
-  lay(real);
+// Truncation jobs (forward value or reverse pass of A_k, see truncation.hip):
+// job t runs on stream t mod S with a workspace slice of its own, so that the
+// matrices of a batch overlap; the call waits for all of them.
+static int run_trunc(Context& cx, const std::vector<TruncJob>& jobs) {
+  const int S = (int)std::min<size_t>(jobs.size(), NSTREAMS);
+  size_t slice = 0;
+  for (const auto& j : jobs) slice = std::max(slice, trunc_ws_bytes(j));
+  slice = (slice + 255) & ~size_t(255);
+  RUTV_CHECK(cx.reserve(slice * (size_t)S + sizeof(int) * 8 * jobs.size()));
+  int* status = reinterpret_cast<int*>(cx.ws + slice * (size_t)S);
   set_launch_timer(nullptr);
-  auto mm = [&](bool ta, bool tb, i64 M_, i64 N_, i64 K_, double alpha, const double* A_, i64 la,
-                const double* B_, i64 lb, double beta, double* C_, i64 lc) {
-    return dgemm(st, ta, tb, M_, N_, K_, alpha, A_, la, B_, lb, beta, C_, lc, wk, sk);
-  };
-  RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(status), 4));
-  RUTV_CHECK(check_finite(st, m, n, A, lda, &status[0]));
-  RUTV_CHECK(sketch(st, seed, 0, m, k, M, m));
-  for (int j = 0; j <= q; ++j) {
-    RUTV_CHECK(mm(true, false, n, k, m, 1.0, A, lda, M, m, 0.0, Z, n));
-    RUTV_CHECK(mm(false, false, m, k, n, 1.0, A, lda, Z, n, 0.0, M, m));
+  for (size_t t = 0; t < jobs.size(); ++t) {
+    const int s = (int)(t % (size_t)S);
+    RUTV_CHECK(trunc_enqueue(jobs[t], cx.streams[s], cx.ws + slice * (size_t)s, status + 8 * t));
   }
-  PanelWork pw;
-  pw.xch = xch;
-  pw.err = &status[1];
-  RUTV_CHECK(panel_qr(st, m, k, M, m, tau, pw));
-  RUTV_CHECK(extract_reflectors(st, m, k, M, m, Wr, m, nullptr, 0, false));
-  RUTV_CHECK(mm(true, false, k, k, m, 1.0, Wr, m, Wr, m, 0.0, Gram, k));
-  RUTV_CHECK(larft_from_gram(st, k, Gram, k, tau, Tf, k));
-  RUTV_CHECK(mm(false, true, k, k, k, 1.0, Tf, k, Wr, m, 0.0, X, k));
-  RUTV_CHECK(set_eye(st, m, k, Q, m));
-  RUTV_CHECK(mm(false, false, m, k, k, -1.0, Wr, m, X, k, 1.0, Q, m));
-  RUTV_CHECK(mm(true, false, k, n, m, 1.0, Q, m, A, lda, 0.0, Cn, k));
-  RUTV_CHECK(mm(false, false, m, n, k, 1.0, Q, m, Cn, k, 0.0, Ak, ldak));
-  int flags[4] = {0, 0, 0, 0};
-  RUTV_TRY(hipMemcpyAsync(flags, status, sizeof(flags), hipMemcpyDeviceToHost, st));
-  RUTV_TRY(hipStreamSynchronize(st));
-  if (flags[0]) return RANDUTV_ERR_NONFINITE;
-  if (flags[1]) return RANDUTV_ERR_SYNC;
+  for (int s = 0; s < S; ++s) RUTV_TRY(hipStreamSynchronize(cx.streams[s]));
+  std::vector<int> flags(8 * jobs.size());
+  RUTV_TRY(hipMemcpy(flags.data(), status, sizeof(int) * flags.size(), hipMemcpyDeviceToHost));
+  for (size_t t = 0; t < jobs.size(); ++t) RUTV_CHECK(trunc_status(&flags[8 * t], jobs[t]));
   return RANDUTV_OK;
+}
+
+static int run_trunc_entry(const std::vector<TruncJob>& jobs) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context& cx = ctx();
+  return drained(cx, [&]() -> int {
+    RUTV_CHECK(cx.init());
+    return run_trunc(cx, jobs);
   });
 }
 
 constexpr int32_t kGradMaxQ = 64;
 
-// Reverse pass of the first-block truncation A_k = U_k U_k^T A, k = min(b, n)
-// (T(0:k, :) V^T = U_k^T A since T = U^T A V).  Step 0 of the method makes
-// range(U_k) = range(M), M = (A A^T)^(q+1) G(0) (Section 3.1: the sketch and
-// power iteration choose V's first block, A times that block spans range(M),
-// and the panel QR and the b x b SVD only rotate within it).  With
-// P = Q Q^T the projector onto range(M) and M = Q R:
-//   dP = (I - P) dM M^+ + (M^+)^T dM^T (I - P),  M^+ = R^{-1} Q^T,
-// so for L(A_k) with Gbar = dL/dA_k and W = Gbar A^T:
-//   dL/dA = P Gbar + [chain of M] applied to Mbar = (I - P)(W + W^T) Q R^{-T}.
-// The chain M_{j+1} = A (A^T M_j), M_0 = G(0), is recomputed and reversed:
-//   Abar += Mbar_{j+1} Z_j^T + M_j (A^T Mbar_{j+1})^T,  Mbar_j = A A^T Mbar_{j+1}.
-static int truncate_grad_impl(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
-                              int32_t q, uint64_t seed, const double* Gbar, int64_t ldg,
-                              double* Abar, int64_t ldab) {
+// argument checks shared by the truncation entry points (positions 1..6)
+static int check_trunc_args(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                            int32_t q, bool reverse) {
   if (m < 0) return -1;
   if (n < 0 || n > m) return -2;
   if (m == 0 || n == 0) return RANDUTV_OK;
   if (!A) return -3;
   if (lda < std::max<int64_t>(1, m)) return -4;
   if (b < 1) return -5;
-  if (q < 0 || q > kGradMaxQ) return -6;  // the reverse pass keeps every power-iteration product
-  if (!Gbar) return -8;
-  if (ldg < std::max<int64_t>(1, m)) return -9;
-  if (!Abar || Abar == A || Abar == Gbar) return -10;
-  if (ldab < std::max<int64_t>(1, m)) return -11;
+  if (q < 0 || (reverse && q > kGradMaxQ)) return -6;  // the reverse pass keeps every product
+  return RANDUTV_OK;
+}
+
+static TruncJob make_job(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                         uint64_t seed, int64_t k, const double* Gbar, int64_t ldg, double* out,
+                         int64_t ldo, bool reverse) {
+  TruncJob j;
+  j.m = m, j.n = n, j.A = A, j.lda = lda, j.b = b, j.q = q, j.seed = seed, j.k = k;
+  j.Gbar = Gbar, j.ldg = ldg, j.out = out, j.ldo = ldo, j.reverse = reverse;
+  return j;
+}
+
+int randutv_truncate_first_block(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                                 int32_t q, uint64_t seed, double* Ak, int64_t ldak) {
+  int rc = check_trunc_args(m, n, A, lda, b, q, false);
+  if (rc != RANDUTV_OK || m == 0 || n == 0) return rc;
+  if (!Ak || Ak == A) return -8;
+  if (ldak < std::max<int64_t>(1, m)) return -9;
   const i64 k = std::min<i64>(b, n);
   if (k > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
-  Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(g_mu);
-  return drained(cx, [&]() -> int {
-  RUTV_CHECK(cx.init());
-  hipStream_t st = cx.st;
-  i64 sk = 0;
-  for (auto s3 : {std::array<i64, 3>{n, k, m}, {m, k, n}, {k, k, m}, {k, k, k}, {m, k, k},
-                  {k, n, m}, {m, n, k}})
-    sk = std::max(sk, dgemm_work_elems(s3[0], s3[1], s3[2]));
-  auto layout_grad = [&](Carver& c, double** Mj, double** Zj, double** F, double** tau,
-                         double** Wr, double** Rk, double** Gram, double** Tf, double** X,
-                         double** Q, double** Rinv, double** Qt, double** T1, double** S,
-                         double** Ck, double** Cn, double** Zb, double** wk, int** status,
-                         unsigned long long** xch) {
-    for (int j = 0; j < q + 2; ++j) Mj[j] = c.take<double>(m * k);
-    for (int j = 0; j < q + 1; ++j) Zj[j] = c.take<double>(n * k);
-    *F = c.take<double>(m * k);
-    *tau = c.take<double>(k);
-    *Wr = c.take<double>(m * k);
-    *Rk = c.take<double>(k * k);
-    *Gram = c.take<double>(k * k);
-    *Tf = c.take<double>(k * k);
-    *X = c.take<double>(k * k);
-    *Q = c.take<double>(m * k);
-    *Rinv = c.take<double>(k * k);
-    *Qt = c.take<double>(m * k);
-    *T1 = c.take<double>(n * k);
-    *S = c.take<double>(m * k);
-    *Ck = c.take<double>(k * k);
-    *Cn = c.take<double>(k * n);
-    *Zb = c.take<double>(n * k);
-    *wk = c.take<double>(sk);
-    *status = c.take<int>(4);
-    *xch = c.take<unsigned long long>(panel_work_elems(m));
-  };
-  std::vector<double*> Mj(q + 2), Zj(q + 1);
-  double *F, *tau, *Wr, *Rk, *Gram, *Tf, *X, *Q, *Rinv, *Qt, *T1, *S, *Ck, *Cn, *Zb, *wk;
-  int* status;
-  unsigned long long* xch;
-  Carver probe;
-  layout_grad(probe, Mj.data(), Zj.data(), &F, &tau, &Wr, &Rk, &Gram, &Tf, &X, &Q, &Rinv, &Qt,
-              &T1, &S, &Ck, &Cn, &Zb, &wk, &status, &xch);
-  RUTV_CHECK(cx.reserve(probe.off));
-  Carver real;
-  real.base = cx.ws;
-  layout_grad(real, Mj.data(), Zj.data(), &F, &tau, &Wr, &Rk, &Gram, &Tf, &X, &Q, &Rinv, &Qt,
-              &T1, &S, &Ck, &Cn, &Zb, &wk, &status, &xch);
-  set_launch_timer(nullptr);
-  auto mm = [&](bool ta, bool tb, i64 M_, i64 N_, i64 K_, double alpha, const double* A_, i64 la,
-                const double* B_, i64 lb, double beta, double* C_, i64 lc) {
-    return dgemm(st, ta, tb, M_, N_, K_, alpha, A_, la, B_, lb, beta, C_, lc, wk, sk);
-  };
-  RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(status), 4));
-  RUTV_CHECK(check_finite(st, m, n, A, lda, &status[0]));
-  RUTV_CHECK(check_finite(st, m, n, Gbar, ldg, &status[0]));
-  // M_0 = G(0); Z_j = A^T M_j; M_{j+1} = A Z_j
-  RUTV_CHECK(sketch(st, seed, 0, m, k, Mj[0], m));
-  for (int j = 0; j <= q; ++j) {
-    RUTV_CHECK(mm(true, false, n, k, m, 1.0, A, lda, Mj[j], m, 0.0, Zj[j], n));
-    RUTV_CHECK(mm(false, false, m, k, n, 1.0, A, lda, Zj[j], n, 0.0, Mj[j + 1], m));
-  }
-  // M = Q R: Householder QR, Q = (I - W Tf W^T) [I; 0] = [I; 0] - W (Tf W_1^T)
-  RUTV_CHECK(copy_matrix(st, m, k, Mj[q + 1], m, F, m));
-  PanelWork pw;
-  pw.xch = xch;
-  pw.err = &status[1];
-  RUTV_CHECK(panel_qr(st, m, k, F, m, tau, pw));
-  RUTV_CHECK(extract_reflectors(st, m, k, F, m, Wr, m, Rk, k, false));
-  RUTV_CHECK(mm(true, false, k, k, m, 1.0, Wr, m, Wr, m, 0.0, Gram, k));
-  RUTV_CHECK(larft_from_gram(st, k, Gram, k, tau, Tf, k));
-  RUTV_CHECK(mm(false, true, k, k, k, 1.0, Tf, k, Wr, m, 0.0, X, k));
-  RUTV_CHECK(set_eye(st, m, k, Q, m));
-  RUTV_CHECK(mm(false, false, m, k, k, -1.0, Wr, m, X, k, 1.0, Q, m));
-  // Qt = Q R^{-T} = (M^+)^T
-  RUTV_CHECK(tri_inverse(st, k, Rk, k, Rinv, k, &status[2]));
-  RUTV_CHECK(mm(false, true, m, k, k, 1.0, Q, m, Rinv, k, 0.0, Qt, m));
-  // S = (W + W^T) Qt = Gbar (A^T Qt) + A (Gbar^T Qt); Mbar = S - Q (Q^T S)
-  RUTV_CHECK(mm(true, false, n, k, m, 1.0, A, lda, Qt, m, 0.0, T1, n));
-  RUTV_CHECK(mm(false, false, m, k, n, 1.0, Gbar, ldg, T1, n, 0.0, S, m));
-  RUTV_CHECK(mm(true, false, n, k, m, 1.0, Gbar, ldg, Qt, m, 0.0, T1, n));
-  RUTV_CHECK(mm(false, false, m, k, n, 1.0, A, lda, T1, n, 1.0, S, m));
-  RUTV_CHECK(mm(true, false, k, k, m, 1.0, Q, m, S, m, 0.0, Ck, k));
-  RUTV_CHECK(mm(false, false, m, k, k, -1.0, Q, m, Ck, k, 1.0, S, m));
-  // Abar = P Gbar, then the chain of M in reverse
-  RUTV_CHECK(mm(true, false, k, n, m, 1.0, Q, m, Gbar, ldg, 0.0, Cn, k));
-  RUTV_CHECK(mm(false, false, m, n, k, 1.0, Q, m, Cn, k, 0.0, Abar, ldab));
-  for (int j = q; j >= 0; --j) {
-    RUTV_CHECK(mm(false, true, m, n, k, 1.0, S, m, Zj[j], n, 1.0, Abar, ldab));
-    RUTV_CHECK(mm(true, false, n, k, m, 1.0, A, lda, S, m, 0.0, Zb, n));
-    RUTV_CHECK(mm(false, true, m, n, k, 1.0, Mj[j], m, Zb, n, 1.0, Abar, ldab));
-    if (j > 0) RUTV_CHECK(mm(false, false, m, k, n, 1.0, A, lda, Zb, n, 0.0, S, m));
-  }
-  int flags[4] = {0, 0, 0, 0};
-  RUTV_TRY(hipMemcpyAsync(flags, status, sizeof(flags), hipMemcpyDeviceToHost, st));
-  RUTV_TRY(hipStreamSynchronize(st));
-  if (flags[0]) return RANDUTV_ERR_NONFINITE;
-  if (flags[1]) return RANDUTV_ERR_SYNC;
-  if (flags[2]) return RANDUTV_ERR_RANK;
-  return RANDUTV_OK;
-  });
-}
-
-// Reverse pass of A_k = P_k A for 0 < k <= b_0 = min(b, n): P_k projects onto
-// the leading k left singular vectors of C = A Q_Y, Q_Y an orthonormal basis
-// of Y = (A^T A)^q A^T G(0) (after step 0, U's first b_0 columns are the panel
-// Q of C times the b x b SVD's U_S: C's left singular vectors; later steps
-// leave them alone).  With U_C = [U_1 U_2] (k and b_0 - k columns), singular
-// values d and lambda = d^2, the eigenprojector derivative of S = C C^T gives
-//   Abar  = P_k Gbar + L Q_Y^T + (the power chain reversed from Ybar),
-//   E     = sym(Gbar A^T) U_1,
-//   H     = U_2 F + 2 (I - U_C U_C^T) E Lambda_1^-1,  F_ji = 2 (U_2^T E)_ji / (lambda_i - lambda_j),
-//   L     = H (U_1^T C) + U_1 (H^T C),
-//   Ybar  = (I - Q_Y Q_Y^T) A^T [H (U_1^T D) + U_1 (H^T D)],  D = C R_Y^-T,
-// and the chain Z_j = A^T M_j, M_{j+1} = A Z_j (M_0 = G(0), Y = Z_q) reversed:
-// Abar += M_j Zbar_j^T, Mbar_j = A Zbar_j, Abar += Mbar_j Z_{j-1}^T,
-// Zbar_{j-1} = A^T Mbar_j.
-// With Ak non-null the call is the forward value instead: Ak = U_1 (U_1^T A).
-static int truncate_grad_k_impl(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
-                                int32_t q, uint64_t seed, int64_t k, const double* Gbar,
-                                int64_t ldg, double* Abar, int64_t ldab, double* Ak = nullptr,
-                                int64_t ldak = 0) {
-  if (m < 0) return -1;
-  if (n < 0 || n > m) return -2;
-  if (m == 0 || n == 0) return RANDUTV_OK;
-  if (!A) return -3;
-  if (lda < std::max<int64_t>(1, m)) return -4;
-  if (b < 1) return -5;
-  if (q < 0 || q > kGradMaxQ) return -6;
-  const i64 bb = std::min<i64>(b, n);
-  if (k < 1 || k > bb) return -8;
-  if (Ak) {
-    if (Ak == A) return -9;
-    if (ldak < std::max<int64_t>(1, m)) return -10;
-  } else {
-    if (!Gbar) return -9;
-    if (ldg < std::max<int64_t>(1, m)) return -10;
-    if (!Abar || Abar == A || Abar == Gbar) return -11;
-    if (ldab < std::max<int64_t>(1, m)) return -12;
-  }
-  if (bb > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
-  Context& cx = ctx();
-  std::lock_guard<std::mutex> lk(g_mu);
-  return drained(cx, [&]() -> int {
-  RUTV_CHECK(cx.init());
-  hipStream_t st = cx.st;
-  const i64 r2 = bb - k;  // columns of U_2
-  i64 sk = 0;
-  for (auto s3 : {std::array<i64, 3>{n, bb, m}, {m, bb, n}, {bb, bb, m}, {bb, bb, n}, {bb, bb, bb},
-                  {m, bb, bb}, {n, bb, bb}, {k, n, m}, {m, n, k}, {m, n, bb}, {n, k, m}, {m, k, n},
-                  {bb, k, m}, {m, k, bb}, {k, bb, m}, {m, bb, k}})
-    sk = std::max(sk, dgemm_work_elems(s3[0], s3[1], s3[2]));
-  std::vector<double*> Mj(q + 1), Zj(q + 1);
-  double *Qy, *Ry, *RyInv, *C, *Fp, *tau, *Wr, *Gram, *Tf, *X, *Rc, *Qc, *d, *lam, *Us, *Vs, *jw,
-      *Uc, *T1, *E, *H, *X1, *W1, *W2, *L, *D, *Yb, *Zb, *Mb, *Cn, *wk;
-  int* status;
-  unsigned long long* xch;
-  const i64 mx = std::max(m, n);
-  auto lay = [&](Carver& c) {
-    for (int j = 0; j <= q; ++j) Mj[j] = c.take<double>(m * bb);
-    for (int j = 0; j <= q; ++j) Zj[j] = c.take<double>(n * bb);
-    Qy = c.take<double>(n * bb);
-    Ry = c.take<double>(bb * bb);
-    RyInv = c.take<double>(bb * bb);
-    C = c.take<double>(m * bb);
-    Fp = c.take<double>(mx * bb);
-    tau = c.take<double>(bb);
-    Wr = c.take<double>(mx * bb);
-    Gram = c.take<double>(bb * bb);
-    Tf = c.take<double>(bb * bb);
-    X = c.take<double>(bb * bb);
-    Rc = c.take<double>(bb * bb);
-    Qc = c.take<double>(m * bb);
-    d = c.take<double>(bb);
-    lam = c.take<double>(bb);
-    Us = c.take<double>(bb * bb);
-    Vs = c.take<double>(bb * bb);
-    jw = c.take<double>(jacobi_work_elems(bb));
-    Uc = c.take<double>(m * bb);
-    T1 = c.take<double>(n * bb);
-    E = c.take<double>(m * k);
-    H = c.take<double>(m * k);
-    X1 = c.take<double>(bb * k);
-    W1 = c.take<double>(k * bb);
-    W2 = c.take<double>(k * bb);
-    L = c.take<double>(m * bb);
-    D = c.take<double>(m * bb);
-    Yb = c.take<double>(n * bb);
-    Zb = c.take<double>(n * bb);
-    Mb = c.take<double>(m * bb);
-    Cn = c.take<double>(k * n);
-    wk = c.take<double>(sk);
-    status = c.take<int>(8);
-    xch = c.take<unsigned long long>(panel_work_elems(mx));
-  };
-  Carver probe;
-  lay(probe);
-  RUTV_CHECK(cx.reserve(probe.off));
-  Carver real;
-  real.base = cx.ws;
-  lay(real);
-  set_launch_timer(nullptr);
-  auto mm = [&](bool ta, bool tb, i64 M_, i64 N_, i64 K_, double alpha, const double* A_, i64 la,
-                const double* B_, i64 lb, double beta, double* C_, i64 lc) {
-    return dgemm(st, ta, tb, M_, N_, K_, alpha, A_, la, B_, lb, beta, C_, lc, wk, sk);
-  };
-  PanelWork pw;
-  pw.xch = xch;
-  pw.err = &status[1];
-  // Householder QR of P (rows x bb, ld rows, copied to Fp) -> explicit Q (rows x bb), R
-  auto qr_explicit = [&](i64 rows, const double* P, double* Qo, double* Ro) -> int {
-    RUTV_CHECK(copy_matrix(st, rows, bb, P, rows, Fp, rows));
-    RUTV_CHECK(panel_qr(st, rows, bb, Fp, rows, tau, pw));
-    RUTV_CHECK(extract_reflectors(st, rows, bb, Fp, rows, Wr, rows, Ro, bb, false));
-    RUTV_CHECK(mm(true, false, bb, bb, rows, 1.0, Wr, rows, Wr, rows, 0.0, Gram, bb));
-    RUTV_CHECK(larft_from_gram(st, bb, Gram, bb, tau, Tf, bb));
-    RUTV_CHECK(mm(false, true, bb, bb, bb, 1.0, Tf, bb, Wr, rows, 0.0, X, bb));
-    RUTV_CHECK(set_eye(st, rows, bb, Qo, rows));
-    return mm(false, false, rows, bb, bb, -1.0, Wr, rows, X, bb, 1.0, Qo, rows);
-  };
-  RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(status), 8));
-  RUTV_CHECK(check_finite(st, m, n, A, lda, &status[0]));
-  if (!Ak) RUTV_CHECK(check_finite(st, m, n, Gbar, ldg, &status[0]));
-  // forward: M_0 = G(0), Z_j = A^T M_j, M_{j+1} = A Z_j; Y = Z_q
-  RUTV_CHECK(sketch(st, seed, 0, m, bb, Mj[0], m));
-  for (int j = 0; j <= q; ++j) {
-    RUTV_CHECK(mm(true, false, n, bb, m, 1.0, A, lda, Mj[j], m, 0.0, Zj[j], n));
-    if (j < q) RUTV_CHECK(mm(false, false, m, bb, n, 1.0, A, lda, Zj[j], n, 0.0, Mj[j + 1], m));
-  }
-  RUTV_CHECK(qr_explicit(n, Zj[q], Qy, Ry));
-  RUTV_CHECK(tri_inverse(st, bb, Ry, bb, RyInv, bb, &status[2]));
-  RUTV_CHECK(mm(false, false, m, bb, n, 1.0, A, lda, Qy, n, 0.0, C, m));
-  RUTV_CHECK(qr_explicit(m, C, Qc, Rc));
-  RUTV_CHECK(jacobi_svd(st, bb, Rc, bb, d, Us, Vs, jw, &status[4]));
-  RUTV_CHECK(square_vec(st, bb, d, lam));
-  RUTV_CHECK(mm(false, false, m, bb, bb, 1.0, Qc, m, Us, bb, 0.0, Uc, m));
-  const double* U1 = Uc;
-  const double* U2 = Uc + k * m;
-  auto finish = [&]() -> int {
-    int flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    RUTV_TRY(hipMemcpyAsync(flags, status, sizeof(flags), hipMemcpyDeviceToHost, st));
-    RUTV_TRY(hipStreamSynchronize(st));
-    if (flags[0]) return RANDUTV_ERR_NONFINITE;
-    if (flags[1] || flags[6]) return RANDUTV_ERR_SYNC;
-    if (!flags[5]) return RANDUTV_ERR_NOCONV;
-    if (!Ak && flags[2]) return RANDUTV_ERR_RANK;
-    return RANDUTV_OK;
-  };
-  if (Ak) {  // forward value: Ak = U_1 (U_1^T A)
-    RUTV_CHECK(mm(true, false, k, n, m, 1.0, U1, m, A, lda, 0.0, Cn, k));
-    RUTV_CHECK(mm(false, false, m, n, k, 1.0, U1, m, Cn, k, 0.0, Ak, ldak));
-    return finish();
-  }
-  // Abar = U_1 (U_1^T Gbar)
-  RUTV_CHECK(mm(true, false, k, n, m, 1.0, U1, m, Gbar, ldg, 0.0, Cn, k));
-  RUTV_CHECK(mm(false, false, m, n, k, 1.0, U1, m, Cn, k, 0.0, Abar, ldab));
-  // E = (Gbar (A^T U_1) + A (Gbar^T U_1)) / 2
-  RUTV_CHECK(mm(true, false, n, k, m, 1.0, A, lda, U1, m, 0.0, T1, n));
-  RUTV_CHECK(mm(false, false, m, k, n, 0.5, Gbar, ldg, T1, n, 0.0, E, m));
-  RUTV_CHECK(mm(true, false, n, k, m, 1.0, Gbar, ldg, U1, m, 0.0, T1, n));
-  RUTV_CHECK(mm(false, false, m, k, n, 0.5, A, lda, T1, n, 1.0, E, m));
-  // H = 2 (E - U_C (U_C^T E)) Lambda_1^-1 + U_2 F
-  RUTV_CHECK(mm(true, false, bb, k, m, 1.0, Uc, m, E, m, 0.0, X1, bb));
-  RUTV_CHECK(copy_matrix(st, m, k, E, m, H, m));
-  RUTV_CHECK(mm(false, false, m, k, bb, -1.0, Uc, m, X1, bb, 1.0, H, m));
-  RUTV_CHECK(scale_cols(st, m, k, H, m, lam, 2.0, &status[2]));
-  if (r2 > 0) {
-    RUTV_CHECK(gap_divide(st, r2, k, X1 + k, bb, d, &status[2]));
-    RUTV_CHECK(mm(false, false, m, k, r2, 1.0, U2, m, X1 + k, bb, 1.0, H, m));
-  }
-  // L = H (U_1^T C) + U_1 (H^T C);  Abar += L Q_Y^T
-  RUTV_CHECK(mm(true, false, k, bb, m, 1.0, U1, m, C, m, 0.0, W1, k));
-  RUTV_CHECK(mm(true, false, k, bb, m, 1.0, H, m, C, m, 0.0, W2, k));
-  RUTV_CHECK(mm(false, false, m, bb, k, 1.0, H, m, W1, k, 0.0, L, m));
-  RUTV_CHECK(mm(false, false, m, bb, k, 1.0, U1, m, W2, k, 1.0, L, m));
-  RUTV_CHECK(mm(false, true, m, n, bb, 1.0, L, m, Qy, n, 1.0, Abar, ldab));
-  // D = C R_Y^-T; L2 = H (U_1^T D) + U_1 (H^T D) (into L)
-  RUTV_CHECK(mm(false, true, m, bb, bb, 1.0, C, m, RyInv, bb, 0.0, D, m));
-  RUTV_CHECK(mm(true, false, k, bb, m, 1.0, U1, m, D, m, 0.0, W1, k));
-  RUTV_CHECK(mm(true, false, k, bb, m, 1.0, H, m, D, m, 0.0, W2, k));
-  RUTV_CHECK(mm(false, false, m, bb, k, 1.0, H, m, W1, k, 0.0, L, m));
-  RUTV_CHECK(mm(false, false, m, bb, k, 1.0, U1, m, W2, k, 1.0, L, m));
-  // Ybar = (I - Q_Y Q_Y^T) A^T L2
-  RUTV_CHECK(mm(true, false, n, bb, m, 1.0, A, lda, L, m, 0.0, Yb, n));
-  RUTV_CHECK(mm(true, false, bb, bb, n, 1.0, Qy, n, Yb, n, 0.0, X, bb));
-  RUTV_CHECK(mm(false, false, n, bb, bb, -1.0, Qy, n, X, bb, 1.0, Yb, n));
-  // the chain reversed: Zbar_q = Ybar
-  double* Zbar = Yb;
-  for (int j = q; j >= 0; --j) {
-    RUTV_CHECK(mm(false, true, m, n, bb, 1.0, Mj[j], m, Zbar, n, 1.0, Abar, ldab));
-    if (j == 0) break;
-    RUTV_CHECK(mm(false, false, m, bb, n, 1.0, A, lda, Zbar, n, 0.0, Mb, m));
-    RUTV_CHECK(mm(false, true, m, n, bb, 1.0, Mb, m, Zj[j - 1], n, 1.0, Abar, ldab));
-    double* next = Zbar == Yb ? Zb : Yb;
-    RUTV_CHECK(mm(true, false, n, bb, m, 1.0, A, lda, Mb, m, 0.0, next, n));
-    Zbar = next;
-  }
-  return finish();
-  });
-}
-
-int randutv_truncate_grad_k(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
-                            int32_t q, uint64_t seed, int64_t k, const double* Gbar, int64_t ldg,
-                            double* Abar, int64_t ldab) {
   return guarded([&] {
-    return truncate_grad_k_impl(m, n, A, lda, b, q, seed, k, Gbar, ldg, Abar, ldab);
+    return run_trunc_entry({make_job(m, n, A, lda, b, q, seed, k, nullptr, 0, Ak, ldak, false)});
   });
 }
 
 int randutv_truncate_first_block_k(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                                    int32_t q, uint64_t seed, int64_t k, double* Ak, int64_t ldak) {
-  if (!Ak) return -9;
+  int rc = check_trunc_args(m, n, A, lda, b, q, false);
+  if (rc != RANDUTV_OK || m == 0 || n == 0) return rc;
+  const i64 bb = std::min<i64>(b, n);
+  if (k < 1 || k > bb + std::min<i64>(b, n - bb)) return -8;
+  if (!Ak || Ak == A) return -9;
+  if (ldak < std::max<int64_t>(1, m)) return -10;
+  if (bb > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
   return guarded([&] {
-    return truncate_grad_k_impl(m, n, A, lda, b, q, seed, k, nullptr, 0, nullptr, 0, Ak, ldak);
+    return run_trunc_entry({make_job(m, n, A, lda, b, q, seed, k, nullptr, 0, Ak, ldak, false)});
   });
 }
 
 int randutv_truncate_grad(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                           int32_t q, uint64_t seed, const double* Gbar, int64_t ldg,
                           double* Abar, int64_t ldab) {
-  return guarded([&] { return truncate_grad_impl(m, n, A, lda, b, q, seed, Gbar, ldg, Abar, ldab); });
+  int rc = check_trunc_args(m, n, A, lda, b, q, true);
+  if (rc != RANDUTV_OK || m == 0 || n == 0) return rc;
+  if (!Gbar) return -8;
+  if (ldg < std::max<int64_t>(1, m)) return -9;
+  if (!Abar || Abar == A || Abar == Gbar) return -10;
+  if (ldab < std::max<int64_t>(1, m)) return -11;
+  const i64 k = std::min<i64>(b, n);
+  if (k > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
+  return guarded([&] {
+    return run_trunc_entry({make_job(m, n, A, lda, b, q, seed, k, Gbar, ldg, Abar, ldab, true)});
+  });
+}
+
+int randutv_truncate_grad_k(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                            int32_t q, uint64_t seed, int64_t k, const double* Gbar, int64_t ldg,
+                            double* Abar, int64_t ldab) {
+  int rc = check_trunc_args(m, n, A, lda, b, q, true);
+  if (rc != RANDUTV_OK || m == 0 || n == 0) return rc;
+  const i64 bb = std::min<i64>(b, n);
+  if (k < 1 || k > bb + std::min<i64>(b, n - bb)) return -8;
+  if (!Gbar) return -9;
+  if (ldg < std::max<int64_t>(1, m)) return -10;
+  if (!Abar || Abar == A || Abar == Gbar) return -11;
+  if (ldab < std::max<int64_t>(1, m)) return -12;
+  if (bb > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
+  return guarded([&] {
+    return run_trunc_entry({make_job(m, n, A, lda, b, q, seed, k, Gbar, ldg, Abar, ldab, true)});
+  });
+}
+
+int randutv_truncate_batched(int64_t batch, int32_t reverse, int64_t m, int64_t n, const double* A,
+                             int64_t lda, int64_t stride_a, int64_t b, int32_t q, uint64_t seed,
+                             int64_t k, const double* Gbar, int64_t ldg, int64_t stride_g,
+                             double* out, int64_t ldo, int64_t stride_o) {
+  if (batch < 0) return -1;
+  if (reverse != 0 && reverse != 1) return -2;
+  if (m < 0) return -3;
+  if (n < 0 || n > m) return -4;
+  if (batch == 0 || m == 0 || n == 0) return RANDUTV_OK;
+  if (!A) return -5;
+  if (lda < std::max<int64_t>(1, m)) return -6;
+  if (batch > 1 && stride_a < lda * n) return -7;
+  if (b < 1) return -8;
+  if (q < 0 || (reverse && q > kGradMaxQ)) return -9;
+  const i64 bb = std::min<i64>(b, n);
+  if (k < 1 || k > bb + std::min<i64>(b, n - bb)) return -11;
+  if (reverse) {
+    if (!Gbar) return -12;
+    if (ldg < std::max<int64_t>(1, m)) return -13;
+    if (batch > 1 && stride_g < ldg * n) return -14;
+  }
+  if (!out || out == A || (reverse && out == Gbar)) return -15;
+  if (ldo < std::max<int64_t>(1, m)) return -16;
+  if (batch > 1 && stride_o < ldo * n) return -17;
+  if (bb > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
+  return guarded([&] {
+    std::vector<TruncJob> jobs;
+    jobs.reserve((size_t)batch);
+    for (int64_t t = 0; t < batch; ++t)
+      jobs.push_back(make_job(m, n, A + t * stride_a, lda, b, q, seed, k,
+                              reverse ? Gbar + t * stride_g : nullptr, ldg, out + t * stride_o, ldo,
+                              reverse != 0));
+    return run_trunc_entry(jobs);
+  });
 }
 
 int randutv_sketch(uint64_t seed, uint64_t step, int64_t rows, int64_t cols, double* G,

@@ -286,4 +286,89 @@ int square_vec(hipStream_t st, i64 n, const double* d, double* lam) {
   return RANDUTV_OK;
 }
 
+// Triangular combinations of k x k matrices (ld k), for the reverse passes of
+// QR and LU factorizations:
+//   mode 0: out = P_L(X - X^T)                  (P_L: strictly lower part)
+//   mode 1: out = P_L(X) - triu(Y)               (triu: upper part with the diagonal)
+//   mode 2: out = P_L(X)
+__global__ __launch_bounds__(256) void tri_combine_kernel(int k, const double* __restrict__ X,
+                                                          const double* __restrict__ Y,
+                                                          double* __restrict__ out, int mode) {
+  const int total = k * k;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+    const int i = e % k, j = e / k;
+    double v = 0.0;
+    if (mode == 0) {
+      v = i > j ? X[i + j * k] - X[j + i * k] : 0.0;
+    } else if (mode == 1) {
+      v = i > j ? X[i + j * k] : -Y[i + j * k];
+    } else {
+      v = i > j ? X[i + j * k] : 0.0;
+    }
+    out[i + j * k] = v;
+  }
+}
+
+int tri_combine(hipStream_t st, i64 k, const double* X, const double* Y, double* out, int mode) {
+  if (k <= 0) return RANDUTV_OK;
+  const int blocks = (int)std::min<i64>(cdiv(k * k, 256), 1024);
+  tri_combine_kernel<<<blocks, 256, 0, st>>>((int)k, X, Y, out, mode);
+  RUTV_TRY(hipGetLastError());
+  return RANDUTV_OK;
+}
+
+// X (k x k, ld k) := Y^T
+__global__ __launch_bounds__(256) void transpose_kernel(int k, const double* __restrict__ Y,
+                                                        double* __restrict__ X) {
+  const int total = k * k;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+    const int i = e % k, j = e / k;
+    X[i + j * k] = Y[j + i * k];
+  }
+}
+
+int transpose_square(hipStream_t st, i64 k, const double* Y, double* X) {
+  if (k <= 0) return RANDUTV_OK;
+  const int blocks = (int)std::min<i64>(cdiv(k * k, 256), 1024);
+  transpose_kernel<<<blocks, 256, 0, st>>>((int)k, Y, X);
+  RUTV_TRY(hipGetLastError());
+  return RANDUTV_OK;
+}
+
+// X (rows x cols, ld ldx) := 0
+__global__ __launch_bounds__(256) void zero_matrix_kernel(i64 rows, i64 cols, double* __restrict__ X,
+                                                          i64 ldx) {
+  const i64 total = rows * cols;
+  for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256)
+    X[e % rows + (e / rows) * ldx] = 0.0;
+}
+
+int zero_matrix(hipStream_t st, i64 rows, i64 cols, double* X, i64 ldx) {
+  if (rows <= 0 || cols <= 0) return RANDUTV_OK;
+  const int blocks = (int)std::min<i64>(cdiv(rows * cols, 256), 16384);
+  zero_matrix_kernel<<<blocks, 256, 0, st>>>(rows, cols, X, ldx);
+  RUTV_TRY(hipGetLastError());
+  return RANDUTV_OK;
+}
+
+// Y += alpha X (rows x cols)
+__global__ __launch_bounds__(256) void axpy_matrix_kernel(i64 rows, i64 cols, double alpha,
+                                                          const double* __restrict__ X, i64 ldx,
+                                                          double* __restrict__ Y, i64 ldy) {
+  const i64 total = rows * cols;
+  for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
+    const i64 r = e % rows, c = e / rows;
+    Y[r + c * ldy] += alpha * X[r + c * ldx];
+  }
+}
+
+int axpy_matrix(hipStream_t st, i64 rows, i64 cols, double alpha, const double* X, i64 ldx, double* Y,
+                i64 ldy) {
+  if (rows <= 0 || cols <= 0) return RANDUTV_OK;
+  const int blocks = (int)std::min<i64>(cdiv(rows * cols, 256), 16384);
+  axpy_matrix_kernel<<<blocks, 256, 0, st>>>(rows, cols, alpha, X, ldx, Y, ldy);
+  RUTV_TRY(hipGetLastError());
+  return RANDUTV_OK;
+}
+
 }  // namespace rutv

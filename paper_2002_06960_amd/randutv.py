@@ -81,6 +81,8 @@ SIGNATURES = {
                                                _P, _I64]),
     "randutv_truncate_first_block_k": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _I64, _P,
                                                       _I64]),
+    "randutv_truncate_batched": (ctypes.c_int, [_I64, _I32, _I64, _I64, _P, _I64, _I64, _I64, _I32, _U64,
+                                                _I64, _P, _I64, _I64, _P, _I64, _I64]),
     "randutv_hqrrp": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _U64, _P, _P]),
     "randutv_sketch": (ctypes.c_int, [_U64, _U64, _I64, _I64, _P, _I64]),
     "randutv_dgemm": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
@@ -395,8 +397,9 @@ def randutv_truncate_grad(A, b: int, q: int, seed: int, Gbar):
 
 
 def randutv_truncate_grad_k(A, b: int, q: int, seed: int, k: int, Gbar):
-    """dL/dA for the truncation A_k (0 < k <= min(b, n)) of
-    randutv_factor(A, b, q, seed), given Gbar = dL/dA_k (sketch held fixed)."""
+    """dL/dA for the truncation A_k (0 < k <= b_0 + b_1, b_0 = min(b, n),
+    b_1 = min(b, n - b_0): the first two blocks of U) of
+    randutv_factor(A, b, q, seed), given Gbar = dL/dA_k (sketches held fixed)."""
     lib = load()
     A, lda = as_colmajor(A)
     Gbar, ldg = as_colmajor(Gbar)
@@ -412,9 +415,9 @@ def randutv_truncate_grad_k(A, b: int, q: int, seed: int, k: int, Gbar):
 
 
 def randutv_truncate_first_block_k(A, b: int, q: int, seed: int, k: int):
-    """A_k (0 < k <= min(b, n)) of randutv_factor(A, b, q, seed) from the first
-    step alone: the projection of A onto the leading k left singular vectors
-    of A orth((A^T A)^q A^T G(0))."""
+    """A_k (0 < k <= b_0 + b_1) of randutv_factor(A, b, q, seed) from its first
+    step (k <= b_0: the projection of A onto the leading k left singular
+    vectors of A orth((A^T A)^q A^T G(0))) or first two steps alone."""
     lib = load()
     A, lda = as_colmajor(A)
     m, n = A.shape
@@ -426,14 +429,42 @@ def randutv_truncate_first_block_k(A, b: int, q: int, seed: int, k: int):
     return Ak
 
 
+def randutv_truncate_batched(A, b: int, q: int, seed: int, k: int, Gbar=None):
+    """For a batch A (batch x m x n, float64 CUDA): A_k of every matrix
+    (Gbar None) or dL/dA given Gbar = dL/dA_k (same shape), in one call that
+    spreads the matrices over the library's streams."""
+    torch = _torch()
+    lib = load()
+    if A.dim() != 3 or A.dtype != torch.float64 or not A.is_cuda:
+        raise TypeError("A must be a float64 CUDA tensor of shape (batch, m, n)")
+    B_, m, n = A.shape
+    # column-major matrices, one after the other: (batch, n, m) contiguous, transposed
+    Ac = A.transpose(1, 2).contiguous().transpose(1, 2)
+    out = torch.empty((B_, n, m), dtype=torch.float64, device=A.device).transpose(1, 2)
+    gptr, stride_g = 0, m * n
+    if Gbar is not None:
+        if tuple(Gbar.shape) != (B_, m, n) or Gbar.dtype != torch.float64 or not Gbar.is_cuda:
+            raise ValueError("Gbar must be a float64 CUDA tensor shaped like A")
+        Gc = Gbar.transpose(1, 2).contiguous().transpose(1, 2)
+        gptr = Gc.data_ptr()
+    _sync()
+    _check("randutv_truncate_batched",
+           lib.randutv_truncate_batched(B_, 1 if Gbar is not None else 0, m, n, Ac.data_ptr(), max(1, m),
+                                        m * n, b, q, seed & (2**64 - 1), k, gptr, max(1, m), stride_g,
+                                        out.data_ptr(), max(1, m), m * n))
+    return out
+
+
 def _autograd_function():
     torch = _torch()
 
     class Truncation(torch.autograd.Function):
-        """A -> A_k (0 < k <= min(b, n)), the sketch G(0) held fixed.  Forward:
-        randutv_truncate_first_block(_k) (the first step fixes A_k), or with
+        """A -> A_k (0 < k <= b_0 + b_1), the sketches held fixed.  Forward:
+        randutv_truncate_first_block(_k) (the first one or two steps fix A_k), or with
         full_factorization randutv_factor then randutv_truncate; reverse:
-        randutv_truncate_grad(_k) (the _k forms for k < min(b, n)).  The library computes in FP64; a float32
+        randutv_truncate_grad(_k) (the _k forms for k < min(b, n)); a batch goes
+        through randutv_truncate_batched (one call, the matrices spread over
+        the library's streams).  The library computes in FP64; a float32
         input is promoted and the results are returned as float32."""
 
         @staticmethod
@@ -449,7 +480,10 @@ def _autograd_function():
                     return randutv_truncate_first_block(X, b, q, seed)
                 return randutv_truncate_first_block_k(X, b, q, seed, k)
 
-            Ak = torch.stack([one(X) for X in X64]) if A.dim() == 3 else one(X64)
+            if A.dim() == 3 and not full_factorization:
+                Ak = randutv_truncate_batched(X64, b, q, seed, k)
+            else:
+                Ak = torch.stack([one(X) for X in X64]) if A.dim() == 3 else one(X64)
             ctx.save_for_backward(X64)
             ctx.b, ctx.q, ctx.seed, ctx.k, ctx.dtype = b, q, seed, k, dtype
             return Ak.to(dtype)
@@ -464,7 +498,7 @@ def _autograd_function():
                 return randutv_truncate_grad_k(X, ctx.b, ctx.q, ctx.seed, ctx.k, G)
 
             if A.dim() == 3:
-                g = torch.stack([one(X, G) for X, G in zip(A, g64)])
+                g = randutv_truncate_batched(A, ctx.b, ctx.q, ctx.seed, ctx.k, g64)
             else:
                 g = one(A, g64)
             return g.to(ctx.dtype), None, None, None, None, None
@@ -478,9 +512,10 @@ _truncation_fn = None
 def truncation(A, b: int, q: int, seed: int = 0, k: Optional[int] = None,
                full_factorization: bool = False):
     """Differentiable rank-k truncation A_k = U_k T_k V^T of randutv_factor(A,
-    b, q, seed) for 0 < k <= min(b, n) (default k = min(b, n)), the sketch
-    G(0) held fixed.  The forward value comes from the first step alone by
-    default: the first step already fixes U's first min(b, n) columns, so the
+    b, q, seed) for 0 < k <= b_0 + b_1 (b_0 = min(b, n), b_1 = min(b, n - b_0);
+    default k = b_0), the sketches G(0) and G(1) held fixed.  The forward value
+    comes from the first step (k <= b_0) or the first two steps alone by
+    default: they already fix U's first b_0 or b_0 + b_1 columns, so the
     later steps do not change A_k (full_factorization=True runs them anyway;
     both agree to rounding amplified by the conditioning of the sketch).
     A may be a batch (batch x m x n), float64 or float32 (computed in FP64)."""
@@ -488,9 +523,11 @@ def truncation(A, b: int, q: int, seed: int = 0, k: Optional[int] = None,
     if _truncation_fn is None:
         _truncation_fn = _autograd_function()
     n = A.shape[-1]
-    kk = min(b, n) if k is None else int(k)
-    if not 0 < kk <= min(b, n):
-        raise ValueError(f"k must lie in 1..min(b, n) = {min(b, n)}")
+    b0 = min(b, n)
+    kmax = b0 + min(b, n - b0)
+    kk = b0 if k is None else int(k)
+    if not 0 < kk <= kmax:
+        raise ValueError(f"k must lie in 1..b_0 + b_1 = {kmax}")
     return _truncation_fn.apply(A, b, q, seed, kk, full_factorization)
 
 

@@ -222,3 +222,36 @@ def test_noalloc_argument_validation_without_device_work():
     a = rb.make_args(m=5, n=3, A=0x1000, lda=5, b=2, T=0x2000, sketch_bits=7)
     assert na(ctypes.byref(a)) == -11
     assert na(None) == -15
+
+
+def test_truncate_batched_argument_validation_without_device_work():
+    lib = pkg.load()
+    P, P2, P3 = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    tb = lib.randutv_truncate_batched
+
+    def call(batch=2, rev=1, m=5, n=3, A=P, lda=5, sa=15, b=2, q=0, k=2, G=P2, ldg=5, sg=15, out=P3, ldo=5,
+             so=15):
+        return tb(batch, rev, m, n, A, lda, sa, b, q, 0, k, G, ldg, sg, out, ldo, so)
+
+    assert call(batch=-1) == -1
+    assert call(rev=2) == -2
+    assert call(m=-1) == -3
+    assert call(m=3, n=5) == -4
+    assert call(A=None) == -5
+    assert call(lda=4) == -6
+    assert call(sa=14) == -7                 # matrices would overlap
+    assert call(b=0) == -8
+    assert call(q=-1) == -9
+    assert call(q=65) == -9                  # the reverse pass keeps every power product
+    assert call(k=0) == -11
+    assert call(k=4) == -11                  # k > b_0 + b_1 = 2 + 1
+    assert call(G=None) == -12
+    assert call(ldg=4) == -13
+    assert call(sg=10) == -14
+    assert call(out=P) == -15                # aliases A
+    assert call(out=P2) == -15               # aliases Gbar
+    assert call(ldo=4) == -16
+    assert call(so=14) == -17
+    assert call(batch=0) == 0
+    assert call(m=600, n=600, lda=600, sa=360000, b=300, k=1, ldg=600, sg=360000, ldo=600,
+                so=360000) == rb.ERR_TOO_LARGE

@@ -227,8 +227,8 @@ def test_grad_k_errors():
     lib = pkg.load()
     assert lib.randutv_truncate_grad_k(64, 48, A.data_ptr(), 64, 16, 1, 0, 0, G.data_ptr(), 64,
                                        G.data_ptr() + 8, 64) == -8          # k < 1
-    assert lib.randutv_truncate_grad_k(64, 48, A.data_ptr(), 64, 16, 1, 0, 17, G.data_ptr(), 64,
-                                       G.data_ptr() + 8, 64) == -8          # k > b
+    assert lib.randutv_truncate_grad_k(64, 48, A.data_ptr(), 64, 16, 1, 0, 33, G.data_ptr(), 64,
+                                       G.data_ptr() + 8, 64) == -8          # k > b_0 + b_1
     Z = to_dev(np.zeros((64, 48)))
     with pytest.raises(pkg.RandUTVError) as e:
         pkg.randutv_truncate_grad_k(Z, 16, 1, 0, 8, G)
@@ -257,3 +257,24 @@ def test_truncation_autograd_k_fp32_and_batch():
         ref = tg.first_block_truncation_k_grad(A32[t], b, q, 5, k, gbar)
         got = to_host(Ad.grad[t]).astype(np.float64)
         assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k", [48, 20])
+def test_truncate_batched_equals_single_calls(k):
+    """randutv_truncate_batched (matrices spread over the library's streams)
+    gives every matrix's forward value and reverse pass bit for bit as the
+    single-matrix calls do, at k = b and k < b."""
+    m, n, b, q = 300, 240, 48, 2
+    A = np.stack([make_matrix("exp98", m, n, seed=s) for s in range(5)])
+    G = np.random.default_rng(8).standard_normal((5, m, n))
+    Ad = torch.from_numpy(A).cuda()
+    Gd = torch.from_numpy(G).cuda()
+    fwd = pkg.randutv_truncate_batched(Ad, b, q, 3, k)
+    rev = pkg.randutv_truncate_batched(Ad, b, q, 3, k, Gd)
+    for t in range(5):
+        Xd = to_dev(A[t])
+        f1 = (pkg.randutv_truncate_first_block(Xd, b, q, 3) if k == b
+              else pkg.randutv_truncate_first_block_k(Xd, b, q, 3, k))
+        r1 = (pkg.randutv_truncate_grad(Xd, b, q, 3, to_dev(G[t])) if k == b
+              else pkg.randutv_truncate_grad_k(Xd, b, q, 3, k, to_dev(G[t])))
+        assert torch.equal(fwd[t], f1) and torch.equal(rev[t], r1), t

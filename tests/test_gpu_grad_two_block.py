@@ -1,0 +1,156 @@
+"""The truncation A_k for b_0 < k <= b_0 + b_1 (U's first two blocks; A_k as
+in Section 1.1, the two steps as in Section 3.1) on the GPU: the forward value
+and the reverse pass against the oracle's closed form (torch reverse mode
+through both thin QRs of step 0, the unpivoted LU that ties Q_H to its
+Householder reflectors, step 1's power chain and the SVD), and the reverse
+pass against central differences of the GPU's full factorization.
+
+Tolerances come from the oracle's own last-bit sensitivity: the oracle is run
+again on A with every entry moved by about one unit in the last place, and
+the GPU may differ from the oracle by 100 times that spread (never less than
+1e-11 relative): both sides round differently, and the second block goes
+through R_V^{-1}, R_H^{-1}, the LU's triangular factors and the eigenvalue
+gaps of C_1, whose conditioning the spread measures."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2002_06960_amd as pkg
+from oracle import truncation_grad as tg
+from randutv_inputs import make_matrix
+from gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _perturbed(A, seed=321):
+    rng = np.random.default_rng(seed)
+    return A * (1.0 + 2.0 ** -52 * rng.standard_normal(A.shape))
+
+
+def _tol(ref, ref_p):
+    spread = np.abs(ref - ref_p).max() / np.abs(ref).max()
+    return max(1e-11, 100.0 * spread), spread
+
+
+CASES = [
+    (256, 256, 32, 2, 64, "exp98"),    # k = 2b
+    (256, 256, 32, 2, 45, "exp98"),    # b < k < 2b
+    (300, 240, 48, 1, 49, "exp"),      # k = b + 1
+    (400, 300, 64, 0, 100, "iid"),     # no power iteration
+    (257, 100, 64, 2, 100, "exp98"),   # ragged second block: b_1 = n - b = 36
+]
+
+
+@pytest.mark.parametrize("m,n,b,q,k,kind", CASES)
+def test_two_block_forward_matches_oracle(m, n, b, q, k, kind):
+    A = make_matrix(kind, m, n, seed=5)
+    ref = tg.two_block_truncation(A, b, q, 7, k)
+    ref_p = tg.two_block_truncation(_perturbed(A), b, q, 7, k)
+    tol, spread = _tol(ref, ref_p)
+    got = to_host(pkg.randutv_truncate_first_block_k(to_dev(A), b, q, 7, k))
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"two-block A_k k={k} {m}x{n} b={b} q={q} {kind}: rel err {err:.2e}, oracle spread {spread:.1e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("m,n,b,q,k,kind", CASES)
+def test_two_block_grad_matches_oracle(m, n, b, q, k, kind):
+    A = make_matrix(kind, m, n, seed=6)
+    Gbar = np.random.default_rng(m + k).standard_normal((m, n))
+    ref = tg.two_block_truncation_grad(A, b, q, 9, k, Gbar)
+    ref_p = tg.two_block_truncation_grad(_perturbed(A), b, q, 9, k, Gbar)
+    tol, spread = _tol(ref, ref_p)
+    got = to_host(pkg.randutv_truncate_grad_k(to_dev(A), b, q, 9, k, to_dev(Gbar)))
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"two-block grad k={k} {m}x{n} b={b} q={q} {kind}: rel err {err:.2e}, oracle spread {spread:.1e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("k", [64, 40])
+def test_two_block_grad_matches_finite_differences_of_the_gpu_factorization(k):
+    """256 x 256, b = 32, q = 2: directional derivatives of <Gbar, A_k> with A_k
+    from the GPU's whole step loop (randutv_factor + randutv_truncate), at
+    k = 2b and between b and 2b, against randutv_truncate_grad_k.  The second
+    block's sketch passes through step 0's reflectors and curves enough that
+    plain central differences at h = 1e-6 are off by ~3e-6 relative; the
+    fourth-order central difference is used instead."""
+    m = n = 256
+    b, q = 32, 2
+    A = make_matrix("exp98", m, n, seed=3)
+    rng = np.random.default_rng(20 + k)
+    Gbar = rng.standard_normal((m, n))
+    Gd = to_dev(Gbar)
+    grad = to_host(pkg.randutv_truncate_grad_k(to_dev(A), b, q, 4, k, Gd))
+
+    def L(X):
+        U, T, V = pkg.randutv_factor(to_dev(X), b, q, 4)
+        return float((pkg.randutv_truncate(U, T, V, k) * Gd).sum())
+
+    h = 1e-6
+    for _ in range(3):
+        E = rng.standard_normal((m, n))
+        fd = (8.0 * (L(A + h * E) - L(A - h * E)) - (L(A + 2 * h * E) - L(A - 2 * h * E))) / (12 * h)
+        an = float(np.sum(grad * E))
+        print(f"fd k={k}: {fd:.10e} analytic {an:.10e}")
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+def test_two_block_forward_equals_the_factorizations_truncation():
+    """The forward value from the first two steps equals U_k T(0:k, :) V^T of
+    the whole factorization: the later steps leave U's first 2b columns."""
+    m, n, b, q, k = 320, 288, 48, 2, 80
+    A = make_matrix("exp98", m, n, seed=12)
+    Ad = to_dev(A)
+    U, T, V = pkg.randutv_factor(Ad, b, q, 2)
+    full = to_host(pkg.randutv_truncate(U, T, V, k))
+    two = to_host(pkg.randutv_truncate_first_block_k(Ad, b, q, 2, k))
+    ref = tg.two_block_truncation(A, b, q, 2, k)
+    ref_p = tg.two_block_truncation(_perturbed(A), b, q, 2, k)
+    tol, _ = _tol(ref, ref_p)
+    assert np.abs(full - two).max() <= tol * np.abs(two).max()
+
+
+def test_two_block_k_range_and_batch():
+    """k up to b_0 + b_1 is accepted, one more is not; a batch at k > b gives
+    the single calls' results bit for bit."""
+    m, n, b, q = 200, 150, 64, 1
+    A = np.stack([make_matrix("exp98", m, n, seed=s) for s in range(3)])
+    G = np.random.default_rng(5).standard_normal((3, m, n))
+    lib = pkg.load()
+    Ad = to_dev(A[0])
+    Gd = to_dev(G[0])
+    out = torch.empty_like(Ad)
+    kmax = 64 + 64
+    assert lib.randutv_truncate_grad_k(m, n, Ad.data_ptr(), m, b, q, 0, kmax + 1, Gd.data_ptr(), m,
+                                       out.data_ptr(), m) == -8
+    assert lib.randutv_truncate_first_block_k(m, n, Ad.data_ptr(), m, b, q, 0, kmax + 1,
+                                              out.data_ptr(), m) == -8
+    k = 100
+    At = torch.from_numpy(A).cuda()
+    Gt = torch.from_numpy(G).cuda()
+    fwd = pkg.randutv_truncate_batched(At, b, q, 3, k)
+    rev = pkg.randutv_truncate_batched(At, b, q, 3, k, Gt)
+    for t in range(3):
+        Xd = to_dev(A[t])
+        assert torch.equal(fwd[t], pkg.randutv_truncate_first_block_k(Xd, b, q, 3, k)), t
+        assert torch.equal(rev[t], pkg.randutv_truncate_grad_k(Xd, b, q, 3, k, to_dev(G[t]))), t
+
+
+def test_two_block_truncation_autograd():
+    """truncation() at b < k <= 2b: A.grad against the oracle's reverse mode."""
+    m, n, b, q, k = 256, 224, 32, 1, 50
+    A = make_matrix("exp98", m, n, seed=14)
+    B = np.random.default_rng(6).standard_normal((m, n))
+    Ad = torch.from_numpy(np.ascontiguousarray(A)).cuda().requires_grad_(True)
+    Ak = pkg.truncation(Ad, b, q, 8, k)
+    loss = ((Ak - torch.from_numpy(B).cuda()) ** 2).sum()
+    loss.backward()
+    gbar = 2.0 * (to_host(Ak.detach()) - B)
+    ref = tg.two_block_truncation_grad(A, b, q, 8, k, gbar)
+    ref_p = tg.two_block_truncation_grad(_perturbed(A), b, q, 8, k, gbar)
+    tol, _ = _tol(ref, ref_p)
+    got = to_host(Ad.grad)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    with pytest.raises(ValueError):
+        pkg.truncation(Ad, b, q, 8, 2 * b + 1)
