@@ -3,8 +3,11 @@
 // Every product of the randUTV step loop (sketch, power iteration, the X = A W
 // products of the compact-WY updates and the rank-b updates A -= X Z^T) goes
 // through this kernel.  Tiles of BM x BN are staged through LDS in BK-deep
-// slices (double buffered, next slice prefetched into registers while the
-// current one feeds the matrix cores).  Eight waves per workgroup, a 2 x 4 grid,
+// slices, double buffered: global loads run two slices ahead of the matrix
+// cores and the LDS stores one slice ahead, at the top of each iteration.
+// Tiles wholly inside C with a K range of whole slices (nearly all of them)
+// take a loop without clamps or masks whose load addresses are a scalar base
+// plus a per-thread offset.  Eight waves per workgroup, a 2 x 4 grid,
 // each own a (BM/2) x (BN/4) sub-tile built from 16x16 blocks of
 // v_mfma_f64_16x16x4; with two workgroups per CU every SIMD interleaves four
 // waves, which hides the LDS and barrier latency of the matrix-core work.
@@ -35,21 +38,34 @@ struct Mfma;
 template <>
 struct Mfma<double> {
   using V4 = dbl4;
+  // NEG = 1: D += (-A) B, the matrix core's negate modifier on the first
+  // operand (exact, so the result equals that of negated inputs bit for bit)
+  template <int NEG = 0>
   __device__ __forceinline__ static V4 mma(double a, double b, V4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, NEG);
   }
   __device__ __forceinline__ static int row(int r, int lane) { return 4 * r + (lane >> 4); }
 };
 template <>
 struct Mfma<float> {
   using V4 = flt4;
+  template <int NEG = 0>
   __device__ __forceinline__ static V4 mma(float a, float b, V4 c) {
+    static_assert(NEG == 0, "no negate modifier on the FP32 matrix-core step");
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   __device__ __forceinline__ static int row(int r, int lane) { return 4 * (lane >> 4) + r; }
 };
 
 constexpr int kWavesM = 2, kWavesN = 4;  // wave grid of a workgroup
+#ifndef RUTV_GEMM_PIPE
+#define RUTV_GEMM_PIPE 1
+#endif
+constexpr bool kGemmPipe2 = RUTV_GEMM_PIPE != 0;
+#ifndef RUTV_GEMM_FAST
+#define RUTV_GEMM_FAST 1
+#endif
+constexpr bool kGemmFast = RUTV_GEMM_FAST != 0;
 constexpr int kGemmThreads = 64 * kWavesM * kWavesN;
 
 // Global -> register loads of one operand slice.  An operand is either
@@ -106,6 +122,22 @@ struct SliceLoader {
         v[r] = p[(i64)min(k, kend - 1) * ld];
         keep[r] = eok && k < kend;
       }
+    }
+  }
+  // slice [k0, k0 + BK) of a tile wholly inside the matrix with k0 + BK <=
+  // kend: no clamps and no masks; the address of value r is a base that is
+  // the same for every lane plus this thread's byte offset (below 2^32: at
+  // most NT / BK edge steps or NT / BX k steps of ld), so the loads take the
+  // scalar-base form and need no per-slice vector arithmetic
+  __device__ __forceinline__ unsigned fast_offset() const {
+    return (unsigned)(8 * (KMAJOR ? (i64)k_off + (i64)e0 * ld : (i64)e0 + (i64)k_off * ld));
+  }
+  __device__ __forceinline__ void load_fast(double (&v)[BE_], int k0, unsigned voff) const {
+#pragma unroll
+    for (int r = 0; r < BE_; ++r) {
+      const double* sb = KMAJOR ? base + k0 + (i64)(tile0 + kStride * r) * ld
+                                : base + tile0 + (i64)(k0 + kStride * r) * ld;
+      v[r] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(sb) + voff);
     }
   }
   // LDS position (k, edge) of value r
@@ -171,73 +203,135 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB * WGM * WGN / 4) void dgemm_mf
   double ra[AE], rb[BE];
   bool ka[AE], kb[BE];
   // cinit (FP64 only, one K split, beta = 1, alpha = +-1): the accumulators
-  // start from C and op(A) enters with the sign of alpha, so the result
-  // C + alpha op(A) op(B) needs no read of C after the K loop; the C loads
-  // are issued with the first slice's and share its latency
-  constexpr unsigned long long sgnA = cinit == 1 ? 0x8000000000000000ull : 0ull;
-  auto sstore = [&](int buf) {
+  // start from C and the products enter with the sign of alpha (the negate
+  // modifier of the matrix-core step for alpha = -1), so the result
+  // C + alpha op(A) op(B) needs no read of C after the K loop
+  constexpr int kNegB = cinit == 1 ? 1 : 0;
+  auto sstore = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int r = 0; r < AE; ++r)
-      As[buf][la.lds_k(r) * LDAS + la.lds_e(r)] = static_cast<CT>(__longlong_as_double(
-          __double_as_longlong(keep_or_zero(ra[r], ka[r])) ^ (long long)sgnA));
+      As[buf][la.lds_k(r) * LDAS + la.lds_e(r)] = static_cast<CT>(keep_or_zero(ra[r], ka[r]));
 #pragma unroll
     for (int r = 0; r < BE; ++r)
       Bs[buf][lb.lds_k(r) * LDBS + lb.lds_e(r)] = static_cast<CT>(keep_or_zero(rb[r], kb[r]));
   };
-
+  auto sstore_fast = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < AE; ++r)
+      As[buf][la.lds_k(r) * LDAS + la.lds_e(r)] = static_cast<CT>(ra[r]);
+#pragma unroll
+    for (int r = 0; r < BE; ++r) Bs[buf][lb.lds_k(r) * LDBS + lb.lds_e(r)] = static_cast<CT>(rb[r]);
+  };
   V4 acc[MI][NJ];
-  if constexpr (cinit != 0) {
-    const int cm = lane & 15;
+  // interior: C addresses need no clamps (a different instruction sequence
+  // per kind also keeps the loads inside their branch)
+  auto init_acc = [&](auto interiorc) __attribute__((always_inline)) {
+    constexpr bool I = decltype(interiorc)::value;
+    if constexpr (cinit != 0) {
+      const int cm = lane & 15;
 #pragma unroll
-    for (int i = 0; i < MI; ++i) {
-      const int gmc = min(m0 + wm0 + 16 * i + cm, M - 1);
+      for (int i = 0; i < MI; ++i) {
+        const int gm = m0 + wm0 + 16 * i + cm;
+        const int gmc = I ? gm : min(gm, M - 1);
 #pragma unroll
-      for (int j = 0; j < NJ; ++j)
+        for (int j = 0; j < NJ; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int gnc = min(n0 + wn0 + 16 * j + MT::row(r, lane), N - 1);
-          acc[i][j][r] = static_cast<CT>(C[gmc + (i64)gnc * ldc]);
-        }
+          for (int r = 0; r < 4; ++r) {
+            const int gn = n0 + wn0 + 16 * j + MT::row(r, lane);
+            const int gnc = I ? gn : min(gn, N - 1);
+            acc[i][j][r] = static_cast<CT>(C[gmc + (i64)gnc * ldc]);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = V4{0, 0, 0, 0};
     }
-  } else {
-#pragma unroll
-    for (int i = 0; i < MI; ++i)
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) acc[i][j] = V4{0, 0, 0, 0};
-  }
+  };
 
+  // tiles wholly inside C whose K range is whole slices take unmasked loads
+  // with scalar bases (a uniform branch: the loop is compiled once per kind)
+  // (the per-thread byte offsets stay below 2^32 for ld < 2^24)
+  const bool fast = kGemmFast && m0 + BM <= M && n0 + BN <= N && (kend - kbeg) % BK == 0 &&
+                    lda < (i64(1) << 24) && ldb < (i64(1) << 24);
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-  if (nk > 0) {
-    la.load(ra, ka, kbeg, kend);
-    lb.load(rb, kb, kbeg, kend);
-    sstore(0);
-    __syncthreads();
-    for (int t = 0; t < nk; ++t) {
-      const int cur = t & 1;
-      if (t + 1 < nk) {
-        la.load(ra, ka, kbeg + (t + 1) * BK, kend);
-        lb.load(rb, kb, kbeg + (t + 1) * BK, kend);
-      }
-      const CT* as = As[cur];
-      const CT* bs = Bs[cur];
+  auto compute = [&](int cur) __attribute__((always_inline)) {
+    const CT* as = As[cur];
+    const CT* bs = Bs[cur];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        const int kr = kk + (lane >> 4), cl = lane & 15;
-        CT af[MI], bf[NJ];
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4), cl = lane & 15;
+      CT af[MI], bf[NJ];
 #pragma unroll
-        for (int i = 0; i < MI; ++i) af[i] = as[kr * LDAS + wm0 + 16 * i + cl];
+      for (int i = 0; i < MI; ++i) af[i] = as[kr * LDAS + wm0 + 16 * i + cl];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) bf[j] = bs[kr * LDBS + wn0 + 16 * j + cl];
+      for (int j = 0; j < NJ; ++j) bf[j] = bs[kr * LDBS + wn0 + 16 * j + cl];
 #pragma unroll
-        for (int i = 0; i < MI; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int j = 0; j < NJ; ++j)
-            acc[i][j] = MT::mma(bf[j], af[i], acc[i][j]);
-      }
-      if (t + 1 < nk) sstore(cur ^ 1);
-      __syncthreads();
+        for (int j = 0; j < NJ; ++j)
+          acc[i][j] = MT::template mma<kNegB>(bf[j], af[i], acc[i][j]);
     }
-  }
+  };
+  auto kloop = [&](auto fastc) __attribute__((always_inline)) {
+    constexpr bool F = decltype(fastc)::value;
+    unsigned voa = 0, vob = 0;
+    if constexpr (F) {
+      voa = la.fast_offset();
+      vob = lb.fast_offset();
+    }
+    auto load_slice = [&](int t) __attribute__((always_inline)) {
+      if constexpr (F) {
+        la.load_fast(ra, kbeg + t * BK, voa);
+        lb.load_fast(rb, kbeg + t * BK, vob);
+      } else {
+        la.load(ra, ka, kbeg + t * BK, kend);
+        lb.load(rb, kb, kbeg + t * BK, kend);
+      }
+    };
+    auto store_slice = [&](int buf) __attribute__((always_inline)) {
+      if constexpr (F)
+        sstore_fast(buf);
+      else
+        sstore(buf);
+    };
+    init_acc(fastc);
+    if (nk == 0) return;
+    load_slice(0);
+    store_slice(0);
+    if constexpr (kGemmPipe2) {
+      // loads run two slices ahead of the matrix cores and LDS stores one:
+      // slice t + 1 goes to the free buffer at the top of iteration t (its
+      // previous contents were read before the barrier that ended t - 1), so
+      // a load has a whole iteration to arrive and the stores overlap the
+      // other waves' matrix-core work instead of preceding the barrier
+      if (nk > 1) load_slice(1);
+      __syncthreads();
+      for (int t = 0; t < nk; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < nk) {
+          store_slice(cur ^ 1);
+          if (t + 2 < nk) load_slice(t + 2);
+        }
+        compute(cur);
+        __syncthreads();
+      }
+    } else {
+      __syncthreads();
+      for (int t = 0; t < nk; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < nk) load_slice(t + 1);
+        compute(cur);
+        if (t + 1 < nk) store_slice(cur ^ 1);
+        __syncthreads();
+      }
+    }
+  };
+  if (fast)
+    kloop(std::true_type{});
+  else
+    kloop(std::false_type{});
 
   // register r of a lane holds D(MT::row(r, lane), lane % 16); with the swapped
   // operands D is the transposed C block, so the lane holds
