@@ -126,6 +126,11 @@ struct EventTimer final : LaunchTimer {
 // ---------------------------------------------------------------------------
 enum { ST_T = 0, ST_P, ST_UV, ST_S, NSTREAMS };
 constexpr int kEvRing = 4;  // events of a kind are reused every kEvRing steps
+#ifndef RUTV_TOP_ON_UV
+#define RUTV_TOP_ON_UV 1
+#endif
+// the right transform of the rows above the current block row on stream UV
+constexpr bool kTopOnUV = RUTV_TOP_ON_UV != 0;
 // reflector buffers (W, Z of V^ and of U^) by step: stream T may run this many
 // steps ahead of the U/V updates that read them
 #ifndef RUTV_WY_BUFFERS
@@ -133,7 +138,7 @@ constexpr int kEvRing = 4;  // events of a kind are reused every kEvRing steps
 #endif
 constexpr int kWyBuf = RUTV_WY_BUFFERS;
 static_assert(kWyBuf >= 2 && kWyBuf - 2 < kEvRing, "an awaited event must not be re-recorded first");
-enum { EV_V = 0, EV_COLS, EV_U, EV_UV, EV_PRE, EV_WV, EV_WU, EV_KINDS };
+enum { EV_V = 0, EV_COLS, EV_U, EV_UV, EV_PRE, EV_WV, EV_WU, EV_LEFT, EV_TOP, EV_KINDS };
 
 // Device scratch of the allocation-free factorization entry point: file-scope
 // device memory, one copy per GPU, resolved to a device address per device
@@ -266,7 +271,7 @@ struct StreamWS {
 // trailing update beside it is at least this wide (below that the GEMMs leave
 // CUs free and the faster exclusive variant gets them)
 #ifndef RUTV_SHARED_PANEL_MIN_COLS
-#define RUTV_SHARED_PANEL_MIN_COLS 3000
+#define RUTV_SHARED_PANEL_MIN_COLS 6000
 #endif
 #ifndef RUTV_SVD_GROUP
 #define RUTV_SVD_GROUP 8
@@ -297,6 +302,13 @@ static i64 splitk_need(i64 m, i64 n, i64 b, int q, bool wantU, bool wantV) {
     upd(m, bi, ni);
     upd(m, bi, bi);
     upd(m, ni - bi, bi);
+    if (s > 0) {  // rows s.. on stream T, rows ..s on stream UV
+      upd(m - s, bi, ni);
+      upd(m - s, bi, bi);
+      upd(m - s, ni - bi, bi);
+      upd(s, bi, ni);
+      upd(s, ni, bi);
+    }
     if (wantV) {
       upd(n, bi, ni);
       upd(n, ni, bi);
@@ -517,6 +529,9 @@ static int factor_run(const FactorCfg& c, Context& cx) {
     if ((j + 1 - g0) != kSvdGroup && !last) return RANDUTV_OK;
     const int cnt = (int)(j + 1 - g0);
     RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_U, j), 0));
+    // the rows above each block of the group have had their last right
+    // transform (stream UV) before V_S is applied to them
+    if (kTopOnUV && j >= 1) RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_TOP, j), 0));
     RUTV_CHECK(jacobi_svd_batched(sS, cnt, b, last ? b_last : b, w.Rall + g0 * b * b, b, b * b,
                                   w.dall + g0 * b, b, w.Usall + g0 * b * b, w.Vsall + g0 * b * b,
                                   b * b, w.jwork, &w.status[2 + 3 * g0], c.max_sweeps,
@@ -585,17 +600,28 @@ static int factor_run(const FactorCfg& c, Context& cx) {
     if (i >= kWyBuf) RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_UV, i - kWyBuf), 0));  // ZV/WU/ZU[buf] free
     RUTV_CHECK(t_factor(sP, xP, ni, bi, w.WV[buf], w.tauV, w.ZV[buf]));
     RUTV_TRY(hipEventRecord(ev(EV_V, i), sP));
-    // right transform of all m rows, T <- T - (T W) Z^T: first the
-    // current column block (it feeds the panel QR on stream P), then the rest
-    RUTV_CHECK(gemm(sT, xT, false, false, m, bi, ni, 1.0, T + s * ldt, ldt, w.WV[buf], ni, 0.0, xT.X, m,
-                    update_prec));
+    // right transform, T <- T - (T W) Z^T.  Stream T transforms rows s..m-1
+    // (the trailing matrix the next steps sketch): first the current column
+    // block (it feeds the panel QR on stream P), then the rest.  Rows 0..s-1
+    // are read by no later step, only transformed again from the right: their
+    // transform runs on stream UV, after the left transform of step i - 1
+    // (which last wrote block row i - 1 there)
+    const i64 r0 = kTopOnUV ? s : 0, mr = m - r0;
+    RUTV_CHECK(gemm(sT, xT, false, false, mr, bi, ni, 1.0, T + r0 + s * ldt, ldt, w.WV[buf], ni, 0.0,
+                    xT.X, m, update_prec));
     RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_V, i), 0));
-    RUTV_CHECK(gemm(sT, xT, false, true, m, bi, bi, -1.0, xT.X, m, w.ZV[buf], ni, 1.0, T + s * ldt, ldt,
-                    update_prec));
+    RUTV_CHECK(gemm(sT, xT, false, true, mr, bi, bi, -1.0, xT.X, m, w.ZV[buf], ni, 1.0, T + r0 + s * ldt,
+                    ldt, update_prec));
     RUTV_TRY(hipEventRecord(ev(EV_COLS, i), sT));
     if (e < n)
-      RUTV_CHECK(gemm(sT, xT, false, true, m, ni - bi, bi, -1.0, xT.X, m, w.ZV[buf] + bi, ni, 1.0,
-                      T + e * ldt, ldt, update_prec));
+      RUTV_CHECK(gemm(sT, xT, false, true, mr, ni - bi, bi, -1.0, xT.X, m, w.ZV[buf] + bi, ni, 1.0,
+                      T + r0 + e * ldt, ldt, update_prec));
+    if (kTopOnUV && s > 0) {
+      RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_V, i), 0));
+      RUTV_TRY(hipStreamWaitEvent(sUV, ev(EV_LEFT, i - 1), 0));
+      RUTV_CHECK(right_apply(sUV, xUV, s, ni, bi, T + s * ldt, ldt, w.WV[buf], w.ZV[buf], update_prec));
+      RUTV_TRY(hipEventRecord(ev(EV_TOP, i), sUV));
+    }
     // ---- stream P: panel QR of the column block, its reflectors, then their
     // block factor while stream T forms W^T C
     RUTV_TRY(hipStreamWaitEvent(sP, ev(EV_COLS, i), 0));
@@ -620,6 +646,7 @@ static int factor_run(const FactorCfg& c, Context& cx) {
     } else {
       RUTV_TRY(hipStreamWaitEvent(sT, ev(EV_U, i), 0));
     }
+    RUTV_TRY(hipEventRecord(ev(EV_LEFT, i), sT));
     s = e;
   }
   RUTV_CHECK(uv_updates(nsteps - 1, false));
