@@ -156,6 +156,7 @@ struct Context {
   hipStream_t streams[NSTREAMS] = {};
   hipEvent_t ev[EV_KINDS][kEvRing] = {};
   hipEvent_t ev_misc[4] = {};
+  hipEvent_t ev_tail[2][NSTREAMS] = {};  // the end of the factorization: two joins of all streams
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool timing = false;
@@ -188,6 +189,8 @@ struct Context {
     for (auto& kind : ev)
       for (auto& e : kind) RUTV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (auto& e : ev_misc) RUTV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& row : ev_tail)
+      for (auto& e : row) RUTV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     st = streams[ST_T];
     return RANDUTV_OK;
   }
@@ -200,6 +203,8 @@ struct Context {
     for (auto& kind : ev)
       for (auto& e : kind) (void)hipEventDestroy(e);
     for (auto& e : ev_misc) (void)hipEventDestroy(e);
+    for (auto& row : ev_tail)
+      for (auto& e : row) (void)hipEventDestroy(e);
     timer.destroy();
     if (ws) (void)hipFree(ws);
     ws = nullptr;
@@ -484,7 +489,7 @@ static int factor_run(const FactorCfg& c, Context& cx) {
     x.pw.err = &w.status[1];
     x.pw.spin_limit = c.spin_limit;
   }
-  const StreamWS &xT = w.sw[ST_T], &xP = w.sw[ST_P], &xUV = w.sw[ST_UV], &xS = w.sw[ST_S];
+  const StreamWS &xT = w.sw[ST_T], &xP = w.sw[ST_P], &xUV = w.sw[ST_UV];
   // the caller's sketch of step i: offset of G(i) in the concatenation
   auto g_offset = [&](i64 i) {
     i64 off = 0;
@@ -536,16 +541,25 @@ static int factor_run(const FactorCfg& c, Context& cx) {
                                   w.dall + g0 * b, b, w.Usall + g0 * b * b, w.Vsall + g0 * b * b,
                                   b * b, w.jwork, &w.status[2 + 3 * g0], c.max_sweeps,
                                   c.spin_limit));
+    // the right factors of each block (its columns of T, V and U).  After the
+    // last group every stream is free: the blocks are spread over all four
+    // (they touch disjoint columns), each stream with its own buffers
+    if (last) RUTV_TRY(hipEventRecord(cx.ev_misc[0], sS));
     for (i64 t = g0; t <= j; ++t) {
+      const int sx = last ? (int)((t - g0 + ST_S) % NSTREAMS) : ST_S;
+      hipStream_t sa = cx.streams[sx];
+      const StreamWS& xa = w.sw[sx];
+      if (last && t - g0 < NSTREAMS && sx != ST_S)
+        RUTV_TRY(hipStreamWaitEvent(sa, cx.ev_misc[0], 0));
       const i64 st_ = t * b, bt = std::min(b, n - st_);
       const double* d = w.dall + t * b;
       const double* Vs = w.Vsall + t * b * b;
       const double* Us = w.Usall + t * b * b;
-      RUTV_CHECK(set_diag_block(sS, bt, d, T + st_ + st_ * ldt, ldt));
-      RUTV_CHECK(right_mul_small(sS, xS, st_, bt, T + st_ * ldt, ldt, Vs));
-      RUTV_TRY(hipStreamWaitEvent(sS, ev(EV_UV, t), 0));
-      if (wantV) RUTV_CHECK(right_mul_small(sS, xS, n, bt, V + st_ * ldv, ldv, Vs));
-      if (wantU) RUTV_CHECK(right_mul_small(sS, xS, m, bt, U + st_ * ldu, ldu, Us));
+      RUTV_CHECK(set_diag_block(sa, bt, d, T + st_ + st_ * ldt, ldt));
+      RUTV_CHECK(right_mul_small(sa, xa, st_, bt, T + st_ * ldt, ldt, Vs));
+      RUTV_TRY(hipStreamWaitEvent(sa, ev(EV_UV, t), 0));
+      if (wantV) RUTV_CHECK(right_mul_small(sa, xa, n, bt, V + st_ * ldv, ldv, Vs));
+      if (wantU) RUTV_CHECK(right_mul_small(sa, xa, m, bt, U + st_ * ldu, ldu, Us));
     }
     g0 = j + 1;
     return RANDUTV_OK;
@@ -650,24 +664,34 @@ static int factor_run(const FactorCfg& c, Context& cx) {
     s = e;
   }
   RUTV_CHECK(uv_updates(nsteps - 1, false));
-  // ---- join, then the deferred left factors: T(s:e, e:n) <- U_S^T T(s:e, e:n)
-  RUTV_TRY(hipEventRecord(cx.ev_misc[0], sS));
-  RUTV_TRY(hipEventRecord(cx.ev_misc[1], sUV));
-  RUTV_TRY(hipEventRecord(cx.ev_misc[2], sP));
-  RUTV_TRY(hipStreamWaitEvent(sT, cx.ev_misc[0], 0));
-  RUTV_TRY(hipStreamWaitEvent(sT, cx.ev_misc[1], 0));
-  RUTV_TRY(hipStreamWaitEvent(sT, cx.ev_misc[2], 0));
+  // ---- join all streams (the right factors of the last blocks act on
+  // columns that every block row's left factor touches), then the deferred
+  // left factors T(s:e, e:n) <- U_S^T T(s:e, e:n), block rows spread over the
+  // four streams (disjoint rows), then join on stream T
+  auto join = [&](int k) -> int {
+    for (int x = 0; x < NSTREAMS; ++x) RUTV_TRY(hipEventRecord(cx.ev_tail[k][x], cx.streams[x]));
+    return RANDUTV_OK;
+  };
+  RUTV_CHECK(join(1));
+  for (int x = 0; x < NSTREAMS; ++x)
+    for (int y = 0; y < NSTREAMS; ++y)
+      if (x != y) RUTV_TRY(hipStreamWaitEvent(cx.streams[x], cx.ev_tail[1][y], 0));
   s = 0;
   for (i64 i = 0; s < n; ++i) {
     const i64 bi = std::min(b, n - s), e = s + bi;
     if (e < n) {
+      const int sx = (int)(i % NSTREAMS);
       const double* Us = w.Usall + i * b * b;
       double* C = T + s + e * ldt;
-      RUTV_CHECK(gemm(sT, xT, true, false, bi, n - e, bi, 1.0, Us, bi, C, ldt, 0.0, w.X3, bi));
-      RUTV_CHECK(copy_matrix(sT, bi, n - e, w.X3, bi, C, ldt));
+      double* X = w.sw[sx].X;
+      RUTV_CHECK(gemm(cx.streams[sx], w.sw[sx], true, false, bi, n - e, bi, 1.0, Us, bi, C, ldt, 0.0, X, bi));
+      RUTV_CHECK(copy_matrix(cx.streams[sx], bi, n - e, X, bi, C, ldt));
     }
     s = e;
   }
+  RUTV_CHECK(join(0));
+  for (int x = 0; x < NSTREAMS; ++x)
+    if (x != ST_T) RUTV_TRY(hipStreamWaitEvent(sT, cx.ev_tail[0][x], 0));
   if (c.has_caller) {
     RUTV_TRY(hipEventRecord(cx.ev_misc[3], sT));
     RUTV_TRY(hipStreamWaitEvent(c.caller, cx.ev_misc[3], 0));
