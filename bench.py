@@ -86,9 +86,10 @@ MODE_TEXT = {32: "fp32 matrix cores", 48: "bf16 matrix cores, split operands hi*
              16: "bf16 matrix cores", 64: "fp64 matrix cores"}
 
 
-def traffic_entry(kernel: str):
+def traffic_entry(kernel: str, launches: int):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
-    summary, if one exists for the current kernel source (else None)."""
+    summary, if one exists for the current kernel source and the same launch
+    list (launches per factorization; else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -100,6 +101,8 @@ def traffic_entry(kernel: str):
         src = os.path.join(ROOT, "paper_2002_06960_amd", "csrc", rec["source"])
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
         if digest != rec["sha256"] or rec.get("kernel") != kernel:
+            return None
+        if rec.get("launches_per_factorization") != launches:
             return None
         return rec["bytes_per_launch"]
     except Exception:
@@ -173,10 +176,12 @@ def main():
         factor()
         torch.cuda.synchronize()
         st = pkg.randutv_kernel_stats()
+        by = pkg.randutv_kernel_bytes()
         pkg.randutv_set_timing(False)
         la, ms, fl = gemm_totals(st)
+        gb = sum(v for k, v in by.items() if k.startswith("dgemm_"))
         log(f"# GEMM launches run alone: {la} launches, {ms:.3f} ms, {ms / la:.4f} ms per launch, "
-            f"{fl / (ms * 1e-3) / 1e12:.3f} TFLOP/s")
+            f"{fl / (ms * 1e-3) / 1e12:.3f} TFLOP/s, algorithmic bytes {gb / la:.4g} per launch")
         return
 
     # ---- timed region: the factorizations alone
@@ -192,7 +197,7 @@ def main():
     # ---- kernel timing, after the timed region: (1) HIP events around every
     # GEMM launch with the streams overlapping as in the timed steps; (2) every
     # GEMM launch alone on the chip; (3) every kernel class (per-class table)
-    stats_inplace = stats_alone = cls_stats = {}
+    stats_inplace = stats_alone = cls_stats = bytes_alone = {}
     if not args.no_kernel_timing:
         pkg.randutv_set_timing(True, gemm_only=True)
         factor()
@@ -204,6 +209,7 @@ def main():
         torch.cuda.synchronize()
         log(f"# factorization with every GEMM launch alone: {time.perf_counter() - t1:.3f} s")
         stats_alone = pkg.randutv_kernel_stats()
+        bytes_alone = pkg.randutv_kernel_bytes()
         pkg.randutv_set_timing(True)
         factor()
         torch.cuda.synchronize()
@@ -276,8 +282,10 @@ def main():
             roofline = {"bound": "mfma", "kernel": "dgemm_mfma_kernel", "achieved": round(achieved, 3),
                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                        "traffic": traffic_entry("dgemm_mfma_kernel"),
+                        "traffic": traffic_entry("dgemm_mfma_kernel", la),
                         "avg_launch_ms": ms_alone / la, "launches": la, "flops_per_launch": fl / la,
+                        "algorithmic_bytes_per_launch": sum(v for k, v in bytes_alone.items()
+                                                            if k.startswith("dgemm_")) / la,
                         "timing": "every GEMM launch of one factorization run alone (HIP events on "
                                   "the launching stream)",
                         "gemm_ms_alone_per_step": round(ms_alone, 3),

@@ -486,6 +486,12 @@ int randutv_gesvj(int64_t k, const double* R, int64_t ldr, double* d,
 int randutv_set_timing(int32_t enable);
 int randutv_kernel_stats(int32_t cap, const char** names, int64_t* launches,
                          double* ms, double* flops);
+/* The algorithmic memory traffic per kernel class, in the class order of
+ * randutv_kernel_stats, accumulated over the same launches: for the GEMM
+ * classes 8 (M K + K N + M N) bytes per launch, plus 8 M N when beta != 0 (C
+ * read as well as written); 0 for classes that do not count it.  Returns the
+ * number of classes written (at most cap); bytes: host array of cap doubles. */
+int randutv_kernel_bytes(int32_t cap, double* bytes);
 
 /* Jacobi sweep counts of each step of the last randutv_factor call (host
  * array of cap entries); returns the number of steps. */

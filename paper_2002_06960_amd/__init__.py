@@ -23,6 +23,7 @@ from .randutv import (  # noqa: F401
     randutv_gesvj,
     randutv_hqrrp,
     randutv_kernel_stats,
+    randutv_kernel_bytes,
     randutv_larft,
     randutv_last_sweeps,
     randutv_set_timing,

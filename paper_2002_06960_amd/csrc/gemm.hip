@@ -759,14 +759,18 @@ int dgemm(hipStream_t st, bool ta, bool tb, i64 M, i64 N, i64 K, double alpha, c
     go(0.0);
   }
   RUTV_TRY(hipGetLastError());
-  if (tm) tm->end(st, cls, 2.0 * (double)M * (double)N * (double)K);
+  // algorithmic bytes: op(A) and op(B) read, C read when beta != 0 (or
+  // accumulated onto), C written
+  if (tm)
+    tm->end(st, cls, 2.0 * (double)M * (double)N * (double)K,
+            8.0 * ((double)M * K + (double)K * N + (beta != 0.0 ? 2.0 : 1.0) * (double)M * N));
   if (part) {
     const i64 MN = M * N;
     const int blocks = (int)std::min<i64>(cdiv(MN, 256), 4096);
     if (tm) tm->begin(st, K_SPLITK);
     splitk_reduce_kernel<<<blocks, 256, 0, st>>>((int)M, (int)N, p.splits, part, beta, C, ldc);
     RUTV_TRY(hipGetLastError());
-    if (tm) tm->end(st, K_SPLITK, 0.0);
+    if (tm) tm->end(st, K_SPLITK, 0.0, 0.0);
   }
   return RANDUTV_OK;
 }

@@ -690,7 +690,7 @@ int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau, cons
   else
     panel_qr_kernel<512><<<P, 512, 0, st>>>((int)m, (int)k, A, lda, tau, w.xch, w.err, lim);
   RUTV_TRY(hipGetLastError());
-  if (tm) tm->end(st, K_PANEL, 2.0 * m * k * k - 2.0 * k * k * k / 3.0);
+  if (tm) tm->end(st, K_PANEL, 2.0 * m * k * k - 2.0 * k * k * k / 3.0, 0.0);
   return RANDUTV_OK;
 }
 
@@ -718,7 +718,7 @@ int extract_reflectors(hipStream_t st, i64 m, i64 k, double* P, i64 ldp, double*
   if (tm) tm->begin(st, K_EXTRACT);
   extract_kernel<<<blocks, 256, 0, st>>>((int)m, (int)k, P, ldp, W, ldw, R, ldr, zero_panel ? 1 : 0);
   RUTV_TRY(hipGetLastError());
-  if (tm) tm->end(st, K_EXTRACT, 0.0);
+  if (tm) tm->end(st, K_EXTRACT, 0.0, 0.0);
   return RANDUTV_OK;
 }
 
@@ -808,7 +808,7 @@ int larft_from_gram(hipStream_t st, i64 k, const double* G, i64 ldg, const doubl
   if (tm) tm->begin(st, K_LARFT);
   larft_rows_kernel<<<nblk, 256, 0, st>>>((int)k, G, ldg, tau, Tf, ldt);
   RUTV_TRY(hipGetLastError());
-  if (tm) tm->end(st, K_LARFT, (double)k * k * k / 3.0);
+  if (tm) tm->end(st, K_LARFT, (double)k * k * k / 3.0, 0.0);
   return RANDUTV_OK;
 }
 

@@ -445,7 +445,7 @@ int jacobi_svd_batched(hipStream_t st, int count, i64 k, i64 k_last, const doubl
       (int)k, (int)k_last, P, R, ldr, rs, d, ds, Us, Vs, us, work, ws, status,
       max_sweeps > 0 ? max_sweeps : kJacobiMaxSweeps, spin_limit ? spin_limit : kSpinLimit);
   RUTV_TRY(hipGetLastError());
-  if (tm) tm->end(st, K_JACOBI, 0.0);
+  if (tm) tm->end(st, K_JACOBI, 0.0, 0.0);
   return RANDUTV_OK;
 }
 

@@ -8,7 +8,10 @@ namespace rutv {
 // Per-launch accounting hook (kernel timing); implemented by the driver.
 struct LaunchTimer {
   virtual void begin(hipStream_t st, int cls) = 0;
-  virtual void end(hipStream_t st, int cls, double flops) = 0;
+  // flops: algorithmic flops of the launch; bytes: its algorithmic memory
+  // traffic (every operand read once, every result written once; 0 where not
+  // counted)
+  virtual void end(hipStream_t st, int cls, double flops, double bytes) = 0;
   virtual ~LaunchTimer() = default;
 };
 void set_launch_timer(LaunchTimer* t);

@@ -53,7 +53,7 @@ struct EventTimer final : LaunchTimer {
   struct Rec {
     hipEvent_t a, b;
     int cls;
-    double flops;
+    double flops, bytes;
   };
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -66,6 +66,7 @@ struct EventTimer final : LaunchTimer {
   int64_t launches[K_NUM_CLASSES] = {};
   double ms[K_NUM_CLASSES] = {};
   double flops[K_NUM_CLASSES] = {};
+  double bytes[K_NUM_CLASSES] = {};
 
   hipEvent_t take() {
     if (used == pool.size()) {
@@ -81,7 +82,7 @@ struct EventTimer final : LaunchTimer {
     open.clear();
   }
   void clear_counts() {
-    for (int c = 0; c < K_NUM_CLASSES; ++c) launches[c] = 0, ms[c] = 0.0, flops[c] = 0.0;
+    for (int c = 0; c < K_NUM_CLASSES; ++c) launches[c] = 0, ms[c] = 0.0, flops[c] = 0.0, bytes[c] = 0.0;
   }
   void destroy() {
     for (auto e : pool) (void)hipEventDestroy(e);
@@ -97,13 +98,13 @@ struct EventTimer final : LaunchTimer {
     if (e) (void)hipEventRecord(e, st);
     open.push_back(e);
   }
-  void end(hipStream_t st, int cls, double f) override {
+  void end(hipStream_t st, int cls, double f, double by) override {
     hipEvent_t a = open.empty() ? nullptr : open.back();
     if (!open.empty()) open.pop_back();
     hipEvent_t b = a ? take() : nullptr;
     if (a && b) {
       (void)hipEventRecord(b, st);
-      recs.push_back({a, b, cls, f});
+      recs.push_back({a, b, cls, f, by});
     }
     if (serialize && is_gemm(cls)) (void)hipStreamSynchronize(st);
   }
@@ -114,6 +115,7 @@ struct EventTimer final : LaunchTimer {
         ms[r.cls] += t;
         launches[r.cls] += 1;
         flops[r.cls] += r.flops;
+        bytes[r.cls] += r.bytes;
       }
     }
     recs.clear();
@@ -1427,6 +1429,17 @@ int randutv_kernel_stats(int32_t cap, const char** names, int64_t* launches, dou
     if (launches) launches[nout] = cx.timer.launches[c];
     if (ms) ms[nout] = cx.timer.ms[c];
     if (flops) flops[nout] = cx.timer.flops[c];
+    ++nout;
+  }
+  return nout;
+}
+
+int randutv_kernel_bytes(int32_t cap, double* bytes) {
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(g_mu);
+  int nout = 0;
+  for (int c = 0; c < K_NUM_CLASSES && nout < cap; ++c) {
+    if (bytes) bytes[nout] = cx.timer.bytes[c];
     ++nout;
   }
   return nout;

@@ -73,7 +73,7 @@ int sketch(hipStream_t st, uint64_t seed, uint64_t step, i64 rows, i64 cols, dou
   if (tm) tm->begin(st, K_SKETCH);
   sketch_kernel<<<blocks, 256, 0, st>>>(seed, step, rows, cols, G, ldg);
   RUTV_TRY(hipGetLastError());
-  if (tm) tm->end(st, K_SKETCH, 0.0);
+  if (tm) tm->end(st, K_SKETCH, 0.0, 0.0);
   return RANDUTV_OK;
 }
 

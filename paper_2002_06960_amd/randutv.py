@@ -96,6 +96,7 @@ SIGNATURES = {
     "randutv_kernel_stats": (ctypes.c_int, [_I32, ctypes.POINTER(ctypes.c_char_p),
                                             ctypes.POINTER(_I64), ctypes.POINTER(_D),
                                             ctypes.POINTER(_D)]),
+    "randutv_kernel_bytes": (ctypes.c_int, [_I32, ctypes.POINTER(_D)]),
     "randutv_last_sweeps": (ctypes.c_int, [_I32, ctypes.POINTER(_I32)]),
     "randutv_last_hip_error": (ctypes.c_char_p, []),
     "randutv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -660,6 +661,17 @@ def randutv_kernel_stats():
     fl = (_D * cap)()
     n = lib.randutv_kernel_stats(cap, names, la, ms, fl)
     return {names[i].decode(): (la[i], ms[i], fl[i]) for i in range(n)}
+
+
+def randutv_kernel_bytes():
+    """{kernel class: algorithmic bytes} over the same launches as randutv_kernel_stats."""
+    lib = load()
+    cap = 32
+    names = (ctypes.c_char_p * cap)()
+    by = (_D * cap)()
+    n = lib.randutv_kernel_stats(cap, names, None, None, None)
+    lib.randutv_kernel_bytes(cap, by)
+    return {names[i].decode(): by[i] for i in range(n)}
 
 
 def randutv_last_sweeps():
