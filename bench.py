@@ -124,6 +124,28 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def stream_summary(trace):
+    """Busy and idle time of each library stream in one factorization, from
+    the per-launch record (overlapping launches of a stream counted once)."""
+    if not trace:
+        return None
+    span = max(t0 + d for _, _, t0, d in trace) - min(t0 for _, _, t0, _ in trace)
+    out = {"span_ms": round(span, 3)}
+    for name in ("T", "P", "UV", "S"):
+        iv = sorted((t0, t0 + d) for _, sname, t0, d in trace if sname == name)
+        busy, end = 0.0, None
+        for a, b in iv:
+            if end is None or a >= end:
+                busy += b - a
+                end = b
+            elif b > end:
+                busy += b - end
+                end = b
+        out[name] = {"launches": len(iv), "busy_ms": round(busy, 3),
+                     "idle_ms": round((iv[-1][1] - iv[0][0] - busy) if iv else 0.0, 3)}
+    return out
+
+
 def gemm_totals(stats):
     gemm = [k for k in stats if k.startswith("dgemm_") and stats[k][0]]
     return (sum(stats[k][0] for k in gemm), sum(stats[k][1] for k in gemm),
@@ -198,6 +220,7 @@ def main():
     # GEMM launch with the streams overlapping as in the timed steps; (2) every
     # GEMM launch alone on the chip; (3) every kernel class (per-class table)
     stats_inplace = stats_alone = cls_stats = bytes_alone = {}
+    trace = []
     if not args.no_kernel_timing:
         pkg.randutv_set_timing(True, gemm_only=True)
         factor()
@@ -214,6 +237,7 @@ def main():
         factor()
         torch.cuda.synchronize()
         cls_stats = pkg.randutv_kernel_stats()
+        trace = pkg.randutv_kernel_trace()
         pkg.randutv_set_timing(False)
 
     F = pkg.flops_std(m, n, q)
@@ -302,6 +326,10 @@ def main():
             l_, t_, f_ = stats_alone[name]
             if name.startswith("dgemm_") and l_:
                 log(f"#   alone {name}: {l_} launches {t_:.1f} ms {f_ / (t_ * 1e-3) / 1e12:.2f} TFLOP/s")
+        ss = stream_summary(trace)
+        if ss:
+            log("# streams (busy / idle ms within a " + f"{ss['span_ms']:.1f} ms factorization): " +
+                ", ".join(f"{k} {ss[k]['busy_ms']:.1f} / {ss[k]['idle_ms']:.1f}" for k in ("T", "P", "UV", "S")))
         log("# kernel classes (ms/step, launches/step, TFLOP/s):")
         for name, kv in sorted(kern.items(), key=lambda x: -x[1]["ms_per_step"]):
             log(f"#   {name:20s} {kv['ms_per_step']:9.3f} {kv['launches']:6d} {kv['tflops']}")
@@ -354,6 +382,7 @@ def main():
         "hqrrp": hq,
         "ooc": ooc,
         "kernels": kern,
+        "streams": stream_summary(trace),
     }
     print(json.dumps(out), flush=True)
 

@@ -492,6 +492,19 @@ int randutv_kernel_stats(int32_t cap, const char** names, int64_t* launches,
  * read as well as written); 0 for classes that do not count it.  Returns the
  * number of classes written (at most cap); bytes: host array of cap doubles. */
 int randutv_kernel_bytes(int32_t cap, double* bytes);
+/* The per-launch record of the last randutv_factor call made with timing on
+ * (the library's counterpart of a task-by-task execution trace): for launch i,
+ * in the order the host enqueued them, its kernel class (index in
+ * randutv_kernel_stats' order), the library stream it ran on (0: the critical
+ * chain of sketch, power iteration, sketch panel, right and left transforms;
+ * 1: block factors and the column-block panel; 2: the U and V updates and the
+ * rows above the block row; 3: the b x b SVDs and their factors), its start
+ * in ms after the call's first work was enqueued, and its duration in ms.
+ * With GEMM-only timing only the GEMM launches are recorded.  Host arrays of
+ * cap entries (any may be NULL); returns the number of records (at most cap
+ * are written), -1 for cap < 0. */
+int randutv_kernel_trace(int32_t cap, int32_t* cls, int32_t* stream, double* start_ms,
+                         double* dur_ms);
 
 /* Jacobi sweep counts of each step of the last randutv_factor call (host
  * array of cap entries); returns the number of steps. */

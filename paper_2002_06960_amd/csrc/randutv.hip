@@ -54,7 +54,17 @@ struct EventTimer final : LaunchTimer {
     hipEvent_t a, b;
     int cls;
     double flops, bytes;
+    hipStream_t st;
   };
+  // per-launch record of the last timed call: class, stream, start after the
+  // call's reference event, duration
+  struct TraceRec {
+    int cls;
+    hipStream_t st;
+    float start, dur;
+  };
+  std::vector<TraceRec> trace;
+  hipEvent_t ref = nullptr;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<Rec> recs;
@@ -80,6 +90,14 @@ struct EventTimer final : LaunchTimer {
     used = 0;
     recs.clear();
     open.clear();
+    trace.clear();
+    ref = nullptr;
+  }
+  // the reference event of the per-launch starts, on stream st before the
+  // call's first work
+  void mark(hipStream_t st) {
+    ref = take();
+    if (ref) (void)hipEventRecord(ref, st);
   }
   void clear_counts() {
     for (int c = 0; c < K_NUM_CLASSES; ++c) launches[c] = 0, ms[c] = 0.0, flops[c] = 0.0, bytes[c] = 0.0;
@@ -104,7 +122,7 @@ struct EventTimer final : LaunchTimer {
     hipEvent_t b = a ? take() : nullptr;
     if (a && b) {
       (void)hipEventRecord(b, st);
-      recs.push_back({a, b, cls, f, by});
+      recs.push_back({a, b, cls, f, by, st});
     }
     if (serialize && is_gemm(cls)) (void)hipStreamSynchronize(st);
   }
@@ -116,6 +134,8 @@ struct EventTimer final : LaunchTimer {
         launches[r.cls] += 1;
         flops[r.cls] += r.flops;
         bytes[r.cls] += r.bytes;
+        float t0 = 0.f;
+        if (ref && hipEventElapsedTime(&t0, ref, r.a) == hipSuccess) trace.push_back({r.cls, r.st, t0, t});
       }
     }
     recs.clear();
@@ -512,6 +532,7 @@ static int factor_run(const FactorCfg& c, Context& cx) {
     RUTV_TRY(hipEventRecord(cx.ev_misc[3], c.caller));
     for (auto x : cx.streams) RUTV_TRY(hipStreamWaitEvent(x, cx.ev_misc[3], 0));
   }
+  if (cx.timing) cx.timer.mark(sT);
   // ---- prologue (stream T): status, T := A with a finiteness check
   RUTV_CHECK(fill_zero_u32(sT, reinterpret_cast<unsigned*>(w.status), 2 + 3 * nsteps));
   if (T != A)
@@ -1432,6 +1453,25 @@ int randutv_kernel_stats(int32_t cap, const char** names, int64_t* launches, dou
     ++nout;
   }
   return nout;
+}
+
+int randutv_kernel_trace(int32_t cap, int32_t* cls, int32_t* stream, double* start_ms,
+                         double* dur_ms) {
+  if (cap < 0) return -1;
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(g_mu);
+  const auto& tr = cx.timer.trace;
+  const int n = (int)std::min<size_t>(tr.size(), (size_t)cap);
+  for (int i = 0; i < n; ++i) {
+    int sx = -1;
+    for (int x = 0; x < NSTREAMS; ++x)
+      if (cx.streams[x] == tr[i].st) sx = x;
+    if (cls) cls[i] = tr[i].cls;
+    if (stream) stream[i] = sx;
+    if (start_ms) start_ms[i] = tr[i].start;
+    if (dur_ms) dur_ms[i] = tr[i].dur;
+  }
+  return (int)tr.size();
 }
 
 int randutv_kernel_bytes(int32_t cap, double* bytes) {

@@ -97,6 +97,8 @@ SIGNATURES = {
                                             ctypes.POINTER(_I64), ctypes.POINTER(_D),
                                             ctypes.POINTER(_D)]),
     "randutv_kernel_bytes": (ctypes.c_int, [_I32, ctypes.POINTER(_D)]),
+    "randutv_kernel_trace": (ctypes.c_int, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                            ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "randutv_last_sweeps": (ctypes.c_int, [_I32, ctypes.POINTER(_I32)]),
     "randutv_last_hip_error": (ctypes.c_char_p, []),
     "randutv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -661,6 +663,29 @@ def randutv_kernel_stats():
     fl = (_D * cap)()
     n = lib.randutv_kernel_stats(cap, names, la, ms, fl)
     return {names[i].decode(): (la[i], ms[i], fl[i]) for i in range(n)}
+
+
+STREAM_NAMES = ("T", "P", "UV", "S")
+
+
+def randutv_kernel_trace():
+    """Per-launch record of the last timed randutv_factor call: a list of
+    (kernel class, stream name, start ms, duration ms) in enqueue order."""
+    lib = load()
+    n = lib.randutv_kernel_trace(0, None, None, None, None)
+    if n <= 0:
+        return []
+    cls = (_I32 * n)()
+    st = (_I32 * n)()
+    t0 = (_D * n)()
+    dt = (_D * n)()
+    n = min(n, lib.randutv_kernel_trace(n, cls, st, t0, dt))
+    cap = 32
+    names = (ctypes.c_char_p * cap)()
+    k = lib.randutv_kernel_stats(cap, names, None, None, None)
+    cname = [names[i].decode() for i in range(k)]
+    return [(cname[cls[i]] if 0 <= cls[i] < k else "?", STREAM_NAMES[st[i]] if 0 <= st[i] < 4 else "?",
+             t0[i], dt[i]) for i in range(n)]
 
 
 def randutv_kernel_bytes():

@@ -159,3 +159,35 @@ def test_no_finite_check_flag_same_result():
     _, T0, _ = pkg.randutv_factor(A, 64, 1, 0)
     _, T1, _ = pkg.randutv_factor(A, 64, 1, 0, finite_check=False)
     assert torch.equal(T0, T1)
+
+
+def test_kernel_trace_matches_the_class_totals():
+    """randutv_kernel_trace: one record per timed launch of the last call, on
+    the library's four streams, whose durations add up to the per-class
+    totals of randutv_kernel_stats; the critical stream (T) runs the sketch
+    and the sketch's panel QR, stream P the column-block panels, stream S the
+    SVD batches."""
+    m = n = 2000
+    b, q = 128, 2
+    A = to_dev(make_matrix("exp", m, n, seed=2))
+    try:
+        pkg.randutv_set_timing(True)
+        pkg.randutv_factor(A, b, q, 0)
+        tr = pkg.randutv_kernel_trace()
+        stats = pkg.randutv_kernel_stats()
+    finally:
+        pkg.randutv_set_timing(False)
+    steps = -(-n // b)
+    assert len(tr) == sum(v[0] for v in stats.values())
+    assert {s for _, s, _, _ in tr} <= {"T", "P", "UV", "S"}
+    for cls, (launches, ms, _) in stats.items():
+        recs = [d for c, _, _, d in tr if c == cls]
+        assert len(recs) == launches, cls
+        assert abs(sum(recs) - ms) <= 1e-3 * max(ms, 1e-3), (cls, sum(recs), ms)
+    assert all(t0 >= -1e-3 and d >= 0.0 for _, _, t0, d in tr)
+    by = lambda cls: {s for c, s, _, _ in tr if c == cls}
+    assert by("sketch") == {"T"} and by("jacobi_svd") == {"S"}
+    panels = [s for c, s, _, _ in tr if c == "panel_qr"]
+    assert panels.count("T") == steps and panels.count("P") == steps
+    end = max(t0 + d for _, _, t0, d in tr)
+    assert 0.0 < end < 5e3
