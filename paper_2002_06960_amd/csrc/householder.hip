@@ -1,7 +1,7 @@
 // Householder QR of a tall panel (m x k, k <= 256) and the compact-WY factor.
 //
-// "unpivoted_QR" of Figure 2 (used for the sketch Y and for the current
-// column block of T) with LAPACK dgeqr2 conventions: reflector H_j =
+// The unpivoted Householder QR of Figure 2 (of the sketch Y and of the
+// current column block of T) with LAPACK dgeqr2 conventions: reflector H_j =
 // I - tau_j v_j v_j^T, v_j(j) = 1, beta_j = -sign(alpha_j) ||x_j||,
 // tau_j = (beta_j - alpha_j)/beta_j, sign(0) = +1, tau_j = 0 when the part
 // below the diagonal is exactly zero.

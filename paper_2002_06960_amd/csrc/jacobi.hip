@@ -1,4 +1,4 @@
-// SVD of the b x b diagonal block (Figure 2, "[A11, U_SVD, V_SVD] := SVD(A11)")
+// SVD of the b x b diagonal block that each step of Figure 2 diagonalizes,
 // by one-sided Jacobi, spread over P <= 8 workgroups.
 //
 // W := R, V := I.  The k columns are split into 2P blocks of up to 16
