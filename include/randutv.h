@@ -116,7 +116,16 @@ int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda,
  *            RANDUTV_FLAG_G_HOST       G is in host memory;
  *            RANDUTV_FLAG_NO_FINITE_CHECK  skip the NaN/Inf scan of A (one
  *            read of A and one host round trip fewer; outputs are then
- *            undefined for such an A).
+ *            undefined for such an A);
+ *            RANDUTV_FLAG_ASYNC (with RANDUTV_FLAG_STREAM only) return as
+ *            soon as the work is enqueued, with no host synchronization
+ *            (the caller's host thread goes on while the GPU works); the
+ *            run-time outcome (a non-finite A included: the kernels then run
+ *            on it) is read afterwards by randutv_factor_status.
+ *            Consecutive calls share the workspace and must be ordered
+ *            through the caller's stream (or events on it); a call is not
+ *            timed.  Capturing such a call into a HIP graph is not
+ *            supported (ending the capture crashed in the runtime).
  *   jacobi_max_sweeps : sweep cap of each b x b Jacobi SVD (0 means 30);
  *            exceeding it returns RANDUTV_ERR_NOCONV.
  *   spin_limit : polls before a multi-workgroup kernel gives up a wait and
@@ -141,6 +150,7 @@ int randutv_factor(int64_t m, int64_t n, const double* A, int64_t lda,
 #define RANDUTV_FLAG_G_HOST 1u
 #define RANDUTV_FLAG_NO_FINITE_CHECK 2u
 #define RANDUTV_FLAG_STREAM 4u
+#define RANDUTV_FLAG_ASYNC 8u
 struct ihipStream_t;
 typedef struct randutv_args {
   int64_t struct_size;
@@ -166,6 +176,18 @@ typedef struct randutv_args {
   int64_t max_workspace_bytes;
 } randutv_args;
 int randutv_factor_ex(const randutv_args* args);
+
+/*
+ * randutv_factor_status -- waits for all work on the current device and
+ * returns the run-time outcome of the library's last factorization
+ * (randutv_factor_ex or randutv_factor_noalloc with RANDUTV_FLAG_ASYNC; for a
+ * synchronous call the value it already returned): RANDUTV_OK,
+ * RANDUTV_ERR_NONFINITE (only if
+ * the call checked A), RANDUTV_ERR_SYNC or RANDUTV_ERR_NOCONV, read from
+ * the status words in the library's workspace; RANDUTV_OK when another
+ * library call has used the workspace since (its words are gone).
+ */
+int randutv_factor_status(void);
 
 /*
  * randutv_factor_noalloc -- randutv_factor_ex for callers that cannot

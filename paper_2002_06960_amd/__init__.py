@@ -25,6 +25,7 @@ from .randutv import (  # noqa: F401
     randutv_kernel_stats,
     randutv_kernel_bytes,
     randutv_kernel_trace,
+    randutv_factor_status,
     randutv_larft,
     randutv_last_sweeps,
     randutv_set_timing,

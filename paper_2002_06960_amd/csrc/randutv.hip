@@ -179,6 +179,9 @@ struct Context {
   hipEvent_t ev[EV_KINDS][kEvRing] = {};
   hipEvent_t ev_misc[4] = {};
   hipEvent_t ev_tail[2][NSTREAMS] = {};  // the end of the factorization: two joins of all streams
+  int* last_status = nullptr;  // status words of the last factorization (in the workspace)
+  i64 last_nsteps = 0;
+  bool last_finite_check = false;
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool timing = false;
@@ -231,6 +234,7 @@ struct Context {
     if (ws) (void)hipFree(ws);
     ws = nullptr;
     ws_bytes = 0;
+    last_status = nullptr;
     st = nullptr;
     for (auto& x : streams) x = nullptr;
     device = -1;
@@ -243,6 +247,7 @@ struct Context {
       if (x) (void)hipStreamSynchronize(x);
   }
   int reserve(size_t bytes) {
+    last_status = nullptr;  // every call that takes the workspace may overwrite it
     if (bytes <= ws_bytes) return RANDUTV_OK;
     if (ws) {
       RUTV_TRY(hipDeviceSynchronize());
@@ -456,9 +461,29 @@ struct FactorCfg {
   unsigned spin_limit = 0;       // bounded waits (0: default)
   size_t max_ws = 0;             // workspace cap (0: none)
   bool noalloc = false;          // carve the workspace out of the device's `scratch`
+  bool async = false;            // return once enqueued (status: randutv_factor_status)
 };
 
 static int factor_run(const FactorCfg& c, Context& cx);
+
+// the outcome of the last factorization from its device status words (after
+// its work has finished): [0] non-finite input, [1] panel sync error, then
+// per step sweeps, converged, Jacobi sync error
+static int read_status(Context& cx, bool check_finite) {
+  if (!cx.last_status) return RANDUTV_OK;
+  const i64 nsteps = cx.last_nsteps;
+  std::vector<int> stat(2 + 3 * nsteps);
+  RUTV_TRY(hipMemcpy(stat.data(), cx.last_status, sizeof(int) * stat.size(), hipMemcpyDeviceToHost));
+  cx.sweeps.assign(nsteps, 0);
+  for (i64 i = 0; i < nsteps; ++i) cx.sweeps[i] = stat[2 + 3 * i];
+  if (check_finite && stat[0]) return RANDUTV_ERR_NONFINITE;
+  if (stat[1]) return RANDUTV_ERR_SYNC;
+  for (i64 i = 0; i < nsteps; ++i)
+    if (stat[4 + 3 * i]) return RANDUTV_ERR_SYNC;
+  for (i64 i = 0; i < nsteps; ++i)
+    if (!stat[3 + 3 * i]) return RANDUTV_ERR_NOCONV;
+  return RANDUTV_OK;
+}
 
 static int factor_impl(const FactorCfg& c) {
   Context& cx = ctx();
@@ -520,7 +545,8 @@ static int factor_run(const FactorCfg& c, Context& cx) {
   };
 
   cx.timer.start_call();
-  set_launch_timer(cx.timing ? &cx.timer : nullptr);
+  const bool timed = cx.timing && !c.async;  // an asynchronous call is not timed
+  set_launch_timer(timed ? &cx.timer : nullptr);
   struct Reset {
     ~Reset() { set_launch_timer(nullptr); }
   } reset_timer;
@@ -532,14 +558,14 @@ static int factor_run(const FactorCfg& c, Context& cx) {
     RUTV_TRY(hipEventRecord(cx.ev_misc[3], c.caller));
     for (auto x : cx.streams) RUTV_TRY(hipStreamWaitEvent(x, cx.ev_misc[3], 0));
   }
-  if (cx.timing) cx.timer.mark(sT);
+  if (timed) cx.timer.mark(sT);
   // ---- prologue (stream T): status, T := A with a finiteness check
   RUTV_CHECK(fill_zero_u32(sT, reinterpret_cast<unsigned*>(w.status), 2 + 3 * nsteps));
   if (T != A)
     RUTV_CHECK(copy_check(sT, m, n, A, lda, T, ldt, c.finite_check ? &w.status[0] : nullptr));
   else if (c.finite_check)
     RUTV_CHECK(check_finite(sT, m, n, T, ldt, &w.status[0]));
-  if (c.finite_check) {
+  if (c.finite_check && !c.async) {
     int flag = 0;
     RUTV_TRY(hipMemcpyAsync(&flag, &w.status[0], sizeof(int), hipMemcpyDeviceToHost, sT));
     RUTV_TRY(hipStreamSynchronize(sT));
@@ -719,18 +745,13 @@ static int factor_run(const FactorCfg& c, Context& cx) {
     RUTV_TRY(hipEventRecord(cx.ev_misc[3], sT));
     RUTV_TRY(hipStreamWaitEvent(c.caller, cx.ev_misc[3], 0));
   }
+  cx.last_status = w.status;
+  cx.last_nsteps = nsteps;
+  cx.last_finite_check = c.finite_check;
+  if (c.async) return RANDUTV_OK;  // randutv_factor_status reads the outcome later
   RUTV_TRY(hipStreamSynchronize(sT));
   if (cx.timing) cx.timer.collect();
-  std::vector<int> stat(2 + 3 * nsteps);
-  RUTV_TRY(hipMemcpy(stat.data(), w.status, sizeof(int) * stat.size(), hipMemcpyDeviceToHost));
-  cx.sweeps.assign(nsteps, 0);
-  for (i64 i = 0; i < nsteps; ++i) cx.sweeps[i] = stat[2 + 3 * i];
-  if (stat[1]) return RANDUTV_ERR_SYNC;
-  for (i64 i = 0; i < nsteps; ++i)
-    if (stat[4 + 3 * i]) return RANDUTV_ERR_SYNC;
-  for (i64 i = 0; i < nsteps; ++i)
-    if (!stat[3 + 3 * i]) return RANDUTV_ERR_NOCONV;
-  return RANDUTV_OK;
+  return read_status(cx, false);
 }
 
 // host-side allocation failures (std::vector and the like) must not cross the
@@ -822,8 +843,10 @@ static int cfg_from_args(const randutv_args* a, FactorCfg& c) {
   c.ldu = a->ldu ? a->ldu : a->m;
   c.ldt = a->ldt ? a->ldt : a->m;
   c.ldv = a->ldv ? a->ldv : a->n;
-  constexpr uint32_t kKnown = RANDUTV_FLAG_G_HOST | RANDUTV_FLAG_NO_FINITE_CHECK | RANDUTV_FLAG_STREAM;
+  constexpr uint32_t kKnown =
+      RANDUTV_FLAG_G_HOST | RANDUTV_FLAG_NO_FINITE_CHECK | RANDUTV_FLAG_STREAM | RANDUTV_FLAG_ASYNC;
   if (a->flags & ~kKnown) return -13;
+  if ((a->flags & RANDUTV_FLAG_ASYNC) && !(a->flags & RANDUTV_FLAG_STREAM)) return -13;
   if ((a->flags & RANDUTV_FLAG_G_HOST) && !a->G) return -13;
   if (prec_of_bits(a->sketch_bits, c.sketch_prec)) return -11;
   if (prec_of_bits(a->update_bits, c.update_prec)) return -12;
@@ -833,6 +856,7 @@ static int cfg_from_args(const randutv_args* a, FactorCfg& c) {
   c.G = a->G;
   c.g_host = (a->flags & RANDUTV_FLAG_G_HOST) != 0;
   c.finite_check = (a->flags & RANDUTV_FLAG_NO_FINITE_CHECK) == 0;
+  c.async = (a->flags & RANDUTV_FLAG_ASYNC) != 0;
   c.max_sweeps = a->jacobi_max_sweeps;
   c.spin_limit = a->spin_limit;
   c.max_ws = a->max_workspace_bytes > 0 ? (size_t)a->max_workspace_bytes : 0;
@@ -845,6 +869,16 @@ int randutv_factor_ex(const randutv_args* a) {
   const int rc = cfg_from_args(a, c);
   if (rc != RANDUTV_OK) return rc;
   return factor_entry(c);
+}
+
+int randutv_factor_status(void) {
+  Context& cx = ctx();
+  std::lock_guard<std::mutex> lk(g_mu);
+  return guarded([&]() -> int {
+    if (!cx.st) return RANDUTV_OK;
+    RUTV_TRY(hipDeviceSynchronize());
+    return read_status(cx, cx.last_finite_check);
+  });
 }
 
 int randutv_factor_noalloc(const randutv_args* a) {

@@ -24,7 +24,7 @@ RANDUTV_OK = 0
 ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONV, ERR_SYNC, ERR_TOO_LARGE, ERR_RANK = 1, 2, 3, 4, 5, 6, 7
 ERR_SCRATCH = 8
 NOALLOC_SCRATCH_BYTES = 128 << 20
-FLAG_G_HOST, FLAG_NO_FINITE_CHECK, FLAG_STREAM = 1, 2, 4
+FLAG_G_HOST, FLAG_NO_FINITE_CHECK, FLAG_STREAM, FLAG_ASYNC = 1, 2, 4, 8
 PRECISION_BITS = (64, 32, 16, 48)
 
 
@@ -69,6 +69,7 @@ SIGNATURES = {
     "randutv_factor": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _P, _P]),
     "randutv_factor_ex": (ctypes.c_int, [ctypes.POINTER(RandutvArgs)]),
     "randutv_factor_noalloc": (ctypes.c_int, [ctypes.POINTER(RandutvArgs)]),
+    "randutv_factor_status": (ctypes.c_int, []),
     "randutv_factor_ooc": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _I32, _U64, _P, _I64, _P, _I64,
                                           _P, _I64, _I64, _I32, ctypes.c_void_p]),
     "randutv_sketch_host": (ctypes.c_int, [_U64, _I64, _I64, _I64, _P]),
@@ -226,7 +227,8 @@ def randutv_factor(A, b: int, q: int, seed: int = 0, build_u: bool = True,
                    build_v: bool = True, in_place: bool = False, U=None, T=None, V=None,
                    sketch_bits: int = 64, update_bits: int = 64, G=None,
                    jacobi_max_sweeps: int = 0, spin_limit: int = 0,
-                   max_workspace_bytes: int = 0, finite_check: bool = True) -> Tuple:
+                   max_workspace_bytes: int = 0, finite_check: bool = True,
+                   asynchronous: bool = False, noalloc: bool = False) -> Tuple:
     """A = U T V^T.  Returns (U, T, V) column-major tensors (U/V None if not built).
 
     U, T, V may be given as preallocated column-major outputs.  sketch_bits
@@ -236,7 +238,11 @@ def randutv_factor(A, b: int, q: int, seed: int = 0, build_u: bool = True,
     three BF16 products of split operands.  G, if given, holds the caller's
     sketches in the layout of sketch_offsets: a float64 CUDA tensor, or a
     numpy float64 array / CPU tensor (host memory).  The call is ordered on
-    torch's current stream."""
+    torch's current stream.  asynchronous: return once the work is enqueued
+    (no host synchronization); randutv_factor_status() gives its outcome
+    later.  noalloc: the
+    allocation-free entry point (every temporary in the library's fixed
+    device scratch)."""
     torch = _torch()
     lib = load()
     A, lda = as_colmajor(A)
@@ -247,7 +253,7 @@ def randutv_factor(A, b: int, q: int, seed: int = 0, build_u: bool = True,
         T = _out(T, m, n, A.device, "T")
     U = _out(U, m, m, A.device, "U") if build_u else None
     V = _out(V, n, n, A.device, "V") if build_v else None
-    flags = FLAG_STREAM | (0 if finite_check else FLAG_NO_FINITE_CHECK)
+    flags = FLAG_STREAM | (0 if finite_check else FLAG_NO_FINITE_CHECK) | (FLAG_ASYNC if asynchronous else 0)
     gptr, keep = 0, None
     if G is not None:
         total = sketch_offsets(m, n, b)[-1]
@@ -269,9 +275,18 @@ def randutv_factor(A, b: int, q: int, seed: int = 0, build_u: bool = True,
                      sketch_bits=sketch_bits, update_bits=update_bits, flags=flags,
                      jacobi_max_sweeps=jacobi_max_sweeps, spin_limit=spin_limit,
                      max_workspace_bytes=max_workspace_bytes)
-    _check("randutv_factor_ex", lib.randutv_factor_ex(ctypes.byref(args)))
+    if noalloc:
+        _check("randutv_factor_noalloc", lib.randutv_factor_noalloc(ctypes.byref(args)))
+    else:
+        _check("randutv_factor_ex", lib.randutv_factor_ex(ctypes.byref(args)))
     del keep
     return U, T, V
+
+
+def randutv_factor_status() -> int:
+    """Outcome of the last factorization (e.g. an asynchronous call): waits
+    for the device, returns 0 or a RANDUTV_ERR_* code."""
+    return load().randutv_factor_status()
 
 
 def host_colmajor_empty(rows: int, cols: int, pinned: bool = True):

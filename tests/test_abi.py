@@ -143,6 +143,7 @@ def test_factor_ex_argument_checks_without_device_work():
     assert _fx(update_bits=24) == -12
     assert _fx(flags=64) == -13                                    # unknown flag
     assert _fx(flags=rb.FLAG_G_HOST) == -13                        # host G flag without G
+    assert _fx(flags=rb.FLAG_ASYNC) == -13                         # asynchronous without a stream
     assert _fx(jacobi_max_sweeps=-1) == -14
     assert _fx(jacobi_max_sweeps=1001) == -14
     assert _fx(b=300, m=600, n=600, lda=600) == rb.ERR_TOO_LARGE
