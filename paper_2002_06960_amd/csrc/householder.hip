@@ -59,6 +59,8 @@ namespace rutv {
 
 typedef unsigned long long u64;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+// two consecutive doubles of a column, 8-byte aligned (one 16-byte load)
+typedef double dbl2u __attribute__((ext_vector_type(2), aligned(8)));
 
 constexpr int kPQLeafThreads = 256;  // waves 0-3 hold the leaf rows
 constexpr int kPQRpt = 1;            // leaf rows per thread
@@ -134,7 +136,11 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
     int* __restrict__ err, unsigned spin_limit) {
   constexpr int kPQWaves = kPQThreads / WAVE;
   const int P = gridDim.x, wg = blockIdx.x;
-  const int r0 = (int)((i64)m * wg / P), r1 = (int)((i64)m * (wg + 1) / P), R = r1 - r0;
+  // slabs are whole 16-row units (the last one ends at m), so that a column
+  // segment of 16 rows is one 128-byte line when the column is line-aligned
+  const int m16 = (m + 15) / 16;
+  const int r0 = min(m, 16 * (int)((i64)m16 * wg / P)), r1 = min(m, 16 * (int)((i64)m16 * (wg + 1) / P));
+  const int R = r1 - r0;
 
   __shared__ double Wl[kPQNB * kPQLdW];        // leaf rows during a pass, then the leaf's explicit W
   __shared__ double S[kPQNB * kPanelMaxCols];  // per-wave Gram partials; X = W^T C, then Tl^T X
@@ -178,6 +184,34 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
     }
     __syncthreads();
   };
+
+  // the sum, in order, of the doubles published by workgroups [wb, we) (at
+  // most 16) at base + w * stride pairs of words: one batch of loads,
+  // repeated until every word carries the round's tag.  Sums over more
+  // workgroups are split into such parts over several threads (one round
+  // trip each instead of one per 16 workgroups), and the parts added in order.
+  auto sum16 = [&](u64* base, i64 stride, int wb, int we, unsigned tg) -> double {
+    constexpr int NB = 16;
+    u64 lo[NB], hi[NB];
+    unsigned spins = 0;
+    while (true) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        u64* p = base + (i64)min(wb + i, we - 1) * stride * 2;
+        lo[i] = xget(p);
+        hi[i] = xget(p + 1);
+      }
+      int have = 1;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) have &= (int)(wb + i >= we) | ((int)xhas(lo[i], tg) & (int)xhas(hi[i], tg));
+      if (have || give_up(spins)) break;
+    }
+    double sv = 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) sv += wb + i < we ? xval(lo[i], hi[i]) : 0.0;
+    return sv;
+  };
+  const int nparts = (P + 15) / 16;
 
   for (int c0 = 0; c0 < k; c0 += kPQNB) {
     const int nbl = min(kPQNB, k - c0);
@@ -256,52 +290,49 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
         }
       }
       arrive_and_wait(0);
-      // gather: threads 0..135 sum one Gram entry over the workgroups in
-      // order; threads 256..511 read the top block
-      if (tid < kPQGramE) {
-        constexpr int NB = 16;
-        double sv = 0.0;
-        for (int w0 = 0; w0 < P; w0 += NB) {
-          u64 lo[NB], hi[NB];
-          unsigned spins = 0;
-          while (true) {
+      // gather: items 0 .. nparts * 136 - 1 sum one part of one Gram entry
+      // (into S), the next 64 read four entries of the top block each (one
+      // batch); then the parts of each Gram entry are added in order
+      {
+        const int ng = kPQGramE * nparts;
+        for (int it = tid; it < ng + kPQNB * kPQNB / 4; it += kPQThreads) {
+          if (it < ng) {
+            const int e = it % kPQGramE, part = it / kPQGramE;
+            S[it] = sum16(xg + (i64)e * 2, kPQGramE, 16 * part, min(16 * part + 16, P), tag);
+          } else {
+            const int e = 4 * (it - ng), t = e >> 4;
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            if (t < nbl) {
+              unsigned spins = 0;
+              u64 lo[4], hi[4];
+              while (true) {
 #pragma unroll
-            for (int i = 0; i < NB; ++i) {
-              u64* p = xg + ((i64)min(w0 + i, P - 1) * kPQGramE + tid) * 2;
-              lo[i] = xget(p);
-              hi[i] = xget(p + 1);
+                for (int i = 0; i < 4; ++i) {
+                  lo[i] = xget(xt + (i64)(e + i) * 2);
+                  hi[i] = xget(xt + (i64)(e + i) * 2 + 1);
+                }
+                int have = 1;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) have &= (int)xhas(lo[i], tag) & (int)xhas(hi[i], tag);
+                if (have || give_up(spins)) break;
+              }
+#pragma unroll
+              for (int i = 0; i < 4; ++i) v[i] = xval(lo[i], hi[i]);
             }
-            int have = 1;
 #pragma unroll
-            for (int i = 0; i < NB; ++i) have &= (int)(w0 + i >= P) | ((int)xhas(lo[i], tag) & (int)xhas(hi[i], tag));
-            if (have || give_up(spins)) break;
+            for (int i = 0; i < 4; ++i) Tops[e + i] = v[i];
           }
-#pragma unroll
-          for (int i = 0; i < NB; ++i) sv += w0 + i < P ? xval(lo[i], hi[i]) : 0.0;
         }
-        int b = 0;
-        while ((b + 1) * (b + 2) / 2 <= tid) ++b;
-        const int a = tid - b * (b + 1) / 2;
-        Gs[a * kPQNB + b] = sv;
-        Gs[b * kPQNB + a] = sv;
-      }
-      // the top block: with 512 threads by threads 256..511 (beside the Gram
-      // readers), with 256 by every thread after its Gram entry
-      for (int e = tid - (kPQThreads - kPQNB * kPQNB); e < kPQNB * kPQNB; e += kPQThreads) {
-        if (e < 0) continue;
-        const int t = e >> 4;
-        double v = 0.0;
-        if (t < nbl) {
-          unsigned spins = 0;
-          u64 lo, hi;
-          while (true) {
-            lo = xget(xt + (i64)e * 2);
-            hi = xget(xt + (i64)e * 2 + 1);
-            if (((int)xhas(lo, tag) & (int)xhas(hi, tag)) || give_up(spins)) break;
-          }
-          v = xval(lo, hi);
+        __syncthreads();
+        if (tid < kPQGramE) {
+          double sv = S[tid];
+          for (int part = 1; part < nparts; ++part) sv += S[part * kPQGramE + tid];
+          int b = 0;
+          while ((b + 1) * (b + 2) / 2 <= tid) ++b;
+          const int a = tid - b * (b + 1) / 2;
+          Gs[a * kPQNB + b] = sv;
+          Gs[b * kPQNB + a] = sv;
         }
-        Tops[e] = v;
       }
       __syncthreads();
       if (tid < kPQNB) dgs[tid] = sqrt(fmax(Gs[tid * (kPQNB + 1)], 0.0));
@@ -325,15 +356,18 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
           for (int a = 0; a < kPQNB; ++a) mj[a] = a <= jj ? lane_value(Mc[a], jj) : 0.0;
 #pragma unroll
           for (int t = jj; t < kPQNB; ++t) tj[t] = lane_value(Tc[t], jj);
-          // g = G m_j (lane c: g_c), then d_c = (top and bottom) column j . column c
-          double gcv = 0.0;
+          // g = G m_j (lane c: g_c), then d_c = (top and bottom) column j .
+          // column c; four partial sums each, to shorten the dependent chains
+          double gp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int a = 0; a <= jj; ++a) gcv += Gs[c * kPQNB + a] * mj[a];
-          double dc = 0.0;
+          for (int a = 0; a <= jj; ++a) gp[a & 3] += Gs[c * kPQNB + a] * mj[a];
+          const double gcv = (gp[0] + gp[1]) + (gp[2] + gp[3]);
+          double dp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int t = jj + 1; t < kPQNB; ++t) dc += tj[t] * Tc[t];
+          for (int t = jj + 1; t < kPQNB; ++t) dp[t & 3] += tj[t] * Tc[t];
 #pragma unroll
-          for (int a = 0; a < kPQNB; ++a) dc += lane_value(gcv, a) * Mc[a];
+          for (int a = 0; a < kPQNB; ++a) dp[a & 3] += lane_value(gcv, a) * Mc[a];
+          const double dc = (dp[0] + dp[1]) + (dp[2] + dp[3]);
           const double sig2 = lane_value(dc, jj);  // squared norm below the diagonal
           double eb = 0.0;
 #pragma unroll
@@ -440,11 +474,15 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
     {
       // wave w forms X(:, 16q:16q+16) = W_slab^T C_slab(:, 16q:16q+16) for the
       // chunks q = w, w + W, ... (W waves; ncr <= 240: at most 15 chunks); the
-      // last wave also forms the Gram W^T W.  Rows are taken 4 per MFMA, in
-      // groups of kPF row steps whose C values are loaded one group ahead into
-      // alternating register sets (a single set would have to wait for every
-      // load in flight before it is refilled).
-      constexpr int kPF = 8, NQ = (kPanelMaxCols / 16 - 1 + kPQWaves - 1) / kPQWaves;
+      // last wave also forms the Gram W^T W.  The sum over rows is taken in
+      // steps of 8 rows: lane (lr, lc) loads rows 8s + 2lr and 8s + 2lr + 1 of
+      // column lc with one 16-byte load (a load instruction then touches 16
+      // cache lines for 64 bytes each, not 32) and feeds them to two MFMAs,
+      // against the same two rows of W.  Steps are taken in groups of kPF
+      // whose C values are loaded one group ahead into alternating register
+      // sets (a single set would have to wait for every load in flight before
+      // it is refilled).
+      constexpr int kPF = 4, NQ = (kPanelMaxCols / 16 - 1 + kPQWaves - 1) / kPQWaves;
       static_assert(NQ <= 4, "chunk dispatch below handles up to four chunks per wave");
       const bool gram = wave == kPQWaves - 1;
       // live chunks of this wave (uniform); loads are unconditional at clamped
@@ -459,28 +497,41 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
         Ac[qd] = Ab + (i64)(c0 + nbl + tcol) * lda + r0;
         acc[qd] = dbl4{0.0, 0.0, 0.0, 0.0};
       }
-      const int nst = (R + 3) / 4;
+      // a row pair starts at most at R - 2, so that both rows lie in the slab
+      // (R >= 17 whenever trailing columns exist); a pair moved down that way
+      // holds the wanted row R - 1 in its second element, and rows past the
+      // slab meet zero rows of Wl
+      const int nst = (R + 7) / 8;
       // one sweep over the slab for NQC live chunks (and the Gram when G)
       auto sweep = [&](auto nqc, auto gc) {
         constexpr int NQC = decltype(nqc)::value;
         constexpr bool G = decltype(gc)::value;
         constexpr int NS = NQC > 0 ? NQC : 1;
-        double ca[NS][kPF], cb[NS][kPF];
-        auto fetch = [&](double (&dst)[NS][kPF], int st0) {
-#pragma unroll
-          for (int i = 0; i < kPF; ++i)
-#pragma unroll
-            for (int qd = 0; qd < NQC; ++qd) dst[qd][i] = Ac[qd][min(4 * (st0 + i) + lr, R - 1)];
-        };
-        auto work = [&](double (&src)[NS][kPF], int st0) {
+        dbl2u ca[NS][kPF], cb[NS][kPF];
+        auto fetch = [&](dbl2u (&dst)[NS][kPF], int st0) {
 #pragma unroll
           for (int i = 0; i < kPF; ++i) {
-            const int r = 4 * (st0 + i) + lr;
-            const double wa = r < kPQMaxRows ? Wl[lc * kPQLdW + min(r, kPQMaxRows - 1)] : 0.0;  // W(r, a = lc)
+            const int p = min(8 * (st0 + i) + 2 * lr, R - 2);
 #pragma unroll
-            for (int qd = 0; qd < NQC; ++qd)
-              acc[qd] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, src[qd][i], acc[qd], 0, 0, 0);
-            if (G) accg = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, wa, accg, 0, 0, 0);
+            for (int qd = 0; qd < NQC; ++qd) dst[qd][i] = *reinterpret_cast<const dbl2u*>(Ac[qd] + p);
+          }
+        };
+        auto work = [&](dbl2u (&src)[NS][kPF], int st0) {
+#pragma unroll
+          for (int i = 0; i < kPF; ++i) {
+            const int ra = 8 * (st0 + i) + 2 * lr;
+            const bool first_in_place = ra <= R - 2;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              const int r = ra + j;
+              const double wa = r < kPQMaxRows ? Wl[lc * kPQLdW + min(r, kPQMaxRows - 1)] : 0.0;  // W(r, a = lc)
+#pragma unroll
+              for (int qd = 0; qd < NQC; ++qd) {
+                const double cv = (j == 0 && first_in_place) ? src[qd][i].x : src[qd][i].y;
+                acc[qd] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, cv, acc[qd], 0, 0, 0);
+              }
+              if (G) accg = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, wa, accg, 0, 0, 0);
+            }
           }
         };
         fetch(ca, 0);
@@ -520,30 +571,19 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
       }
     }
     arrive_and_wait(1);
-    // first exchange: workgroup wg sums entries [e0, e1) over all workgroups, in order
+    // first exchange: workgroup wg sums entries [e0, e1) over all workgroups
+    // (parts of at most 16 workgroups on separate threads, then the parts in
+    // order)
     {
-      const int e0 = (int)((i64)E * wg / P), e1 = (int)((i64)E * (wg + 1) / P);
-      constexpr int NB = 16;
+      const int e0 = (int)((i64)E * wg / P), e1 = (int)((i64)E * (wg + 1) / P), ne = e1 - e0;
+      for (int it = tid; it < ne * nparts; it += kPQThreads) {
+        const int e = e0 + it % ne, part = it / ne;
+        S[it] = sum16(xpart + (i64)e * 2, kPQTrail, 16 * part, min(16 * part + 16, P), tag1);
+      }
+      __syncthreads();
       for (int e = e0 + tid; e < e1; e += kPQThreads) {
-        double sv = 0.0;
-        for (int w0 = 0; w0 < P; w0 += NB) {
-          u64 lo[NB], hi[NB];
-          unsigned spins = 0;
-          while (true) {
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-              u64* p = xpart + ((i64)min(w0 + i, P - 1) * kPQTrail + e) * 2;
-              lo[i] = xget(p);
-              hi[i] = xget(p + 1);
-            }
-            int have = 1;
-#pragma unroll
-            for (int i = 0; i < NB; ++i) have &= (int)(w0 + i >= P) | ((int)xhas(lo[i], tag1) & (int)xhas(hi[i], tag1));
-            if (have || give_up(spins)) break;
-          }
-#pragma unroll
-          for (int i = 0; i < NB; ++i) sv += w0 + i < P ? xval(lo[i], hi[i]) : 0.0;
-        }
+        double sv = S[e - e0];
+        for (int part = 1; part < nparts; ++part) sv += S[part * ne + e - e0];
         xput(xtot + (i64)e * 2, sv, tag2);
       }
     }
@@ -589,10 +629,16 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
       for (int c = 0; c < kPQNB; ++c) trow[c] = 0.0;
 #pragma unroll
       for (int c = 0; c < kPQNB; ++c) {
+        // the Gram column is read unconditionally (a masked product per term
+        // would put an LDS round trip on the chain of every term)
+        double g[kPQNB];
+#pragma unroll
+        for (int l = 0; l < c; ++l) g[l] = Gs[l + c * kPQNB];
+        const double tauc = taul[c];
         double sdot = 0.0;
 #pragma unroll
-        for (int l = 0; l < c; ++l) sdot += l >= lane ? trow[l] * Gs[l + c * kPQNB] : 0.0;
-        const double tc = lane < c ? -taul[c] * sdot : (lane == c ? taul[c] : 0.0);
+        for (int l = 0; l < c; ++l) sdot += (l >= lane ? trow[l] : 0.0) * g[l];
+        const double tc = lane < c ? -tauc * sdot : (lane == c ? tauc : 0.0);
         trow[c] = c < nbl ? tc : 0.0;
       }
 #pragma unroll
@@ -616,59 +662,69 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
     // update on the matrix cores: 16-row x 16-column blocks of C -= W Y with
     // Y = S (16 x ncr); the MFMA forms the block transposed, so a lane holds
     // 4 columns of one row: C[rb + lc][t0 + 4q + lr] (16 rows per column per
-    // store).  Blocks are dealt to the waves and taken kG at a time; the C
-    // values of the next group are loaded into the other register set before
-    // the current group is computed and stored (the wait for a load then
-    // never includes the stores issued after it).
+    // store).  A wave keeps the W fragment of its 16-row block in registers
+    // and walks the chunks of 16 columns, kU at a time (independent MFMA
+    // chains); the C values of the next kU chunks are loaded into the other
+    // register set before the current ones are computed and stored (the wait
+    // for a load then never includes the stores issued after it).  With fewer
+    // row blocks than waves, the waves of one row block take every G-th chunk.
     {
       const int nrb = (R + 15) / 16;
-      const int nblocks = nrb * nchunk;
-      constexpr int kG = 4;
-      // unconditional loads at clamped addresses (the stores are guarded)
-      auto fetch = [&](int g, double (&dst)[kG][4]) {
+      const int G = nrb >= kPQWaves ? 1 : kPQWaves / nrb;
+      constexpr int kU = 4;
+      const int t_first = wave % G;
+      const int nmine = t_first < nchunk ? (nchunk - t_first + G - 1) / G : 0;  // chunks of this wave
+      const int nsteps = (nmine + kU - 1) / kU;
+      for (int rbi = wave / G; rbi < nrb; rbi += kPQWaves / G) {
+        const int rb = 16 * rbi;
+        const bool row_ok = rb + lc < R;
+        // row rb + lc (clamped into the slab) of the trailing columns
+        const double* const Cl = Ab + (i64)(r0 + min(rb + lc, R - 1)) + (i64)(c0 + nbl) * lda;
+        double* const Cs = Ab + (i64)(r0 + rb + lc) + (i64)(c0 + nbl) * lda;
+        double wv[4];
 #pragma unroll
-        for (int u = 0; u < kG; ++u) {
-          const int bc = min(wave + kPQWaves * (kG * g + u), nblocks - 1);
-          const int rb = 16 * (bc % nrb), t0 = 16 * (bc / nrb);
-          const int r = min(rb + lc, R - 1);
+        for (int kk = 0; kk < 4; ++kk) wv[kk] = Wl[(4 * kk + lr) * kPQLdW + rb + lc];  // W^T(4kk + lr, rb + lc)
+        // chunk index of slot u of step st
+        auto chunk = [&](int st, int u) { return t_first + G * (kU * st + u); };
+        // unconditional loads at clamped addresses (the stores are guarded)
+        auto fetch = [&](int st, double (&dst)[kU][4]) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int tc = min(t0 + 4 * q + lr, ncr - 1);
-            dst[u][q] = Ab[(i64)(r0 + r) + (i64)(c0 + nbl + tc) * lda];
+          for (int u = 0; u < kU; ++u) {
+            const int t0 = 16 * chunk(st, u);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[u][q] = Cl[(i64)min(t0 + 4 * q + lr, ncr - 1) * lda];
           }
+        };
+        auto finish = [&](int st, double (&src)[kU][4]) {
+          dbl4 d[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int t0 = 16 * min(chunk(st, u), nchunk - 1);
+            d[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+              const double yv = S[(4 * kk + lr) * kPanelMaxCols + t0 + lc];  // Y^T(t0 + lc, 4kk + lr)
+              d[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, wv[kk], d[u], 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int t0 = 16 * chunk(st, u);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int tc = t0 + 4 * q + lr;
+              if (row_ok && tc < ncr) Cs[(i64)tc * lda] = src[u][q] - d[u][q];
+            }
+          }
+        };
+        double ga[kU][4], gb[kU][4];
+        if (nsteps > 0) fetch(0, ga);
+        for (int st = 0; st < nsteps; st += 2) {
+          fetch(st + 1, gb);
+          finish(st, ga);
+          fetch(st + 2, ga);
+          finish(st + 1, gb);
         }
-      };
-      auto finish = [&](int g, double (&src)[kG][4]) {
-#pragma unroll
-        for (int u = 0; u < kG; ++u) {
-          const int bidx = wave + kPQWaves * (kG * g + u);
-          const int bc = min(bidx, nblocks - 1);
-          const int rb = 16 * (bc % nrb), t0 = 16 * (bc / nrb);
-          dbl4 d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-          for (int kk = 0; kk < kPQNB; kk += 4) {
-            const double yv = S[(kk + lr) * kPanelMaxCols + t0 + lc];  // Y^T(t0 + lc, kk + lr)
-            const double wv = Wl[(kk + lr) * kPQLdW + rb + lc];        // W^T(kk + lr, rb + lc)
-            d = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, wv, d, 0, 0, 0);
-          }
-          const int r = rb + lc;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int tc = t0 + 4 * q + lr;
-            if (bidx < nblocks && r < R && tc < ncr)
-              Ab[(i64)(r0 + r) + (i64)(c0 + nbl + tc) * lda] = src[u][q] - d[q];
-          }
-        }
-      };
-      const int nbw = (nblocks - wave + kPQWaves - 1) / kPQWaves;  // this wave's blocks
-      const int ngroups = nbw > 0 ? (nbw + kG - 1) / kG : 0;
-      double ga[kG][4], gb[kG][4];
-      if (ngroups > 0) fetch(0, ga);
-      for (int g = 0; g < ngroups; g += 2) {
-        fetch(g + 1, gb);
-        finish(g, ga);
-        fetch(g + 2, ga);
-        finish(g + 1, gb);
       }
     }
     __syncthreads();
@@ -680,7 +736,7 @@ int panel_qr(hipStream_t st, i64 m, i64 k, double* A, i64 lda, double* tau, cons
   if (k <= 0 || m <= 0) return RANDUTV_OK;
   if (k > kPanelMaxCols || m < k) return RANDUTV_ERR_TOO_LARGE;
   const int P = panel_grid(m);
-  if (P > kPQMaxWG || cdiv(m, P) > kPQMaxRows) return RANDUTV_ERR_TOO_LARGE;
+  if (P > kPQMaxWG || 16 * cdiv(cdiv(m, 16), P) > kPQMaxRows) return RANDUTV_ERR_TOO_LARGE;
   LaunchTimer* tm = launch_timer();
   RUTV_CHECK(fill_zero_u32(st, reinterpret_cast<unsigned*>(w.xch), 2 * panel_words(P)));
   if (tm) tm->begin(st, K_PANEL);
