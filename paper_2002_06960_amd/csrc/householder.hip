@@ -6,10 +6,11 @@
 // tau_j = (beta_j - alpha_j)/beta_j, sign(0) = +1, tau_j = 0 when the part
 // below the diagonal is exactly zero.
 //
-// Panel kernel layout: P workgroups of 8 waves each own a contiguous slab of
-// at most 512 rows.  The panel is processed in leaves of 16 columns whose rows
-// stay in the registers of waves 0-3 (two rows per thread); all 8 waves share
-// the matrix-core work.
+// Panel kernel layout: P workgroups (8 waves, or 4 in the variant that shares
+// its CU with a GEMM workgroup) each own a contiguous slab of at most 256 rows,
+// made of whole 16-row units.  The panel is processed in leaves of 16 columns
+// whose rows stay in the registers of waves 0-3 (one row per thread); all
+// waves share the matrix-core work.
 //
 // A leaf's reflectors need sums over all rows.  Rather than one exchange
 // between the workgroups per column, a leaf takes one exchange per pass: the
@@ -33,7 +34,9 @@
 // After a leaf, the rest of the panel receives the leaf's block reflector
 // C <- (I - W Tl W^T)^T C, with the Gram matrix of the leaf vectors and W^T C
 // summed over the workgroups in two rounds (each workgroup reduces a share of
-// the entries, then everybody reads the totals).
+// the entries, then everybody reads the totals).  Every sum over the
+// workgroups is split into parts of at most 16 workgroups, each read by one
+// thread in one batch of loads, and the parts are added in order.
 //
 // Workgroups exchange values without grid barriers or memory fences: a double
 // travels as two 64-bit words, each holding one 32-bit half of it and the
