@@ -359,18 +359,15 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
           for (int a = 0; a < kPQNB; ++a) mj[a] = a <= jj ? lane_value(Mc[a], jj) : 0.0;
 #pragma unroll
           for (int t = jj; t < kPQNB; ++t) tj[t] = lane_value(Tc[t], jj);
-          // g = G m_j (lane c: g_c), then d_c = (top and bottom) column j .
-          // column c; four partial sums each, to shorten the dependent chains
-          double gp[4] = {0.0, 0.0, 0.0, 0.0};
+          // g = G m_j (lane c: g_c), then d_c = (top and bottom) column j . column c
+          double gcv = 0.0;
 #pragma unroll
-          for (int a = 0; a <= jj; ++a) gp[a & 3] += Gs[c * kPQNB + a] * mj[a];
-          const double gcv = (gp[0] + gp[1]) + (gp[2] + gp[3]);
-          double dp[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int a = 0; a <= jj; ++a) gcv += Gs[c * kPQNB + a] * mj[a];
+          double dc = 0.0;
 #pragma unroll
-          for (int t = jj + 1; t < kPQNB; ++t) dp[t & 3] += tj[t] * Tc[t];
+          for (int t = jj + 1; t < kPQNB; ++t) dc += tj[t] * Tc[t];
 #pragma unroll
-          for (int a = 0; a < kPQNB; ++a) dp[a & 3] += lane_value(gcv, a) * Mc[a];
-          const double dc = (dp[0] + dp[1]) + (dp[2] + dp[3]);
+          for (int a = 0; a < kPQNB; ++a) dc += lane_value(gcv, a) * Mc[a];
           const double sig2 = lane_value(dc, jj);  // squared norm below the diagonal
           double eb = 0.0;
 #pragma unroll
@@ -681,9 +678,9 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
       for (int rbi = wave / G; rbi < nrb; rbi += kPQWaves / G) {
         const int rb = 16 * rbi;
         const bool row_ok = rb + lc < R;
-        // row rb + lc (clamped into the slab) of the trailing columns
-        const double* const Cl = Ab + (i64)(r0 + min(rb + lc, R - 1)) + (i64)(c0 + nbl) * lda;
-        double* const Cs = Ab + (i64)(r0 + rb + lc) + (i64)(c0 + nbl) * lda;
+        // row rb + lc (clamped into the slab; rows past it load but never store)
+        // of the trailing columns
+        double* const Cr = Ab + (i64)(r0 + min(rb + lc, R - 1)) + (i64)(c0 + nbl) * lda;
         double wv[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) wv[kk] = Wl[(4 * kk + lr) * kPQLdW + rb + lc];  // W^T(4kk + lr, rb + lc)
@@ -695,7 +692,7 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
           for (int u = 0; u < kU; ++u) {
             const int t0 = 16 * chunk(st, u);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dst[u][q] = Cl[(i64)min(t0 + 4 * q + lr, ncr - 1) * lda];
+            for (int q = 0; q < 4; ++q) dst[u][q] = Cr[(i64)min(t0 + 4 * q + lr, ncr - 1) * lda];
           }
         };
         auto finish = [&](int st, double (&src)[kU][4]) {
@@ -716,7 +713,7 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int tc = t0 + 4 * q + lr;
-              if (row_ok && tc < ncr) Cs[(i64)tc * lda] = src[u][q] - d[u][q];
+              if (row_ok && tc < ncr) Cr[(i64)tc * lda] = src[u][q] - d[u][q];
             }
           }
         };
