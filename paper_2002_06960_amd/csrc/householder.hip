@@ -645,18 +645,23 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
       for (int c = 0; c < kPQNB; ++c) Tl[lane + c * kPQNB] = trow[c];
     }
     __syncthreads();
-    // S <- Tl^T X (thread t owns column t; ncr <= 240 < threads)
-    if (tid < ncr) {
-      double xv[kPQNB];
+    // S <- Tl^T X on the matrix cores, a 16-column chunk per wave: lane l
+    // supplies Tl^T(l % 16, k) and X(k, t0 + l % 16) for k = 4s + l / 16, and
+    // register q of the result is S(4q + l / 16, t0 + l % 16).  A chunk is read
+    // and written by its wave only.  Rows a >= nbl of X and columns a >= nbl of
+    // Tl are zero (for a partial last leaf), so those rows of S come out zero.
+    for (int q = wave; q < nchunk; q += kPQWaves) {
+      const int t0 = 16 * q;
+      dbl4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int a = 0; a < kPQNB; ++a) xv[a] = a < nbl ? S[a * kPanelMaxCols + tid] : 0.0;
-#pragma unroll
-      for (int a = 0; a < kPQNB; ++a) {
-        double sv = 0.0;
-#pragma unroll
-        for (int l = 0; l <= a; ++l) sv += Tl[l + a * kPQNB] * xv[l];
-        S[a * kPanelMaxCols + tid] = a < nbl ? sv : 0.0;
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int kr = 4 * s4 + lr;
+        const double tv = Tl[kr + lc * kPQNB];                                  // Tl^T(lc, kr)
+        const double xv = kr < nbl ? S[kr * kPanelMaxCols + t0 + lc] : 0.0;  // X(kr, t0 + lc)
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(tv, xv, d, 0, 0, 0);
       }
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) S[(4 * qq + lr) * kPanelMaxCols + t0 + lc] = d[qq];
     }
     __syncthreads();
     // update on the matrix cores: 16-row x 16-column blocks of C -= W Y with
