@@ -228,7 +228,9 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
     u64* const xtop = xch + z + kXTop;
     u64* const xtot = xch + z + kXTot;
     u64* const xpart = xch + z + kXPart;
-    double row[kPQRpt][kPQNB];
+    // the leaf's rows live in LDS (X(r, c) at Wl[c * kPQLdW + r]) through its
+    // passes; loads are unconditional at clamped addresses, so all 16 are in
+    // flight together
     int gr[kPQRpt];
     bool own[kPQRpt];
 #pragma unroll
@@ -236,9 +238,12 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
       const int r = tid + kPQLeafThreads * i;
       own[i] = tid < kPQLeafThreads && r < R;
       gr[i] = r0 + r;
+      if (tid < kPQLeafThreads)
 #pragma unroll
-      for (int c = 0; c < kPQNB; ++c)
-        row[i][c] = (own[i] && c < nbl) ? Ab[(i64)gr[i] + (i64)(c0 + c) * lda] : 0.0;
+        for (int c = 0; c < kPQNB; ++c) {
+          const double v = Ab[(i64)min(gr[i], m - 1) + (i64)(c0 + min(c, nbl - 1)) * lda];
+          Wl[c * kPQLdW + r] = (own[i] && c < nbl) ? v : 0.0;
+        }
     }
 
     for (int j0 = 0; j0 < nbl;) {
@@ -246,18 +251,15 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
       const int par = (int)(tag & 1);
       u64* const xg = xgram + (i64)par * kPQMaxWG * kPQGramE * 2;
       u64* const xt = xtop + (i64)par * kPQNB * kPQNB * 2;
-      // rows to LDS (X(r, c) at Wl[c * kPQLdW + r]); the owners of top-block
-      // rows publish them
+      // the owners of top-block rows publish them
       if (tid < kPQLeafThreads) {
 #pragma unroll
         for (int i = 0; i < kPQRpt; ++i) {
           const int r = tid + kPQLeafThreads * i;
-#pragma unroll
-          for (int c = 0; c < kPQNB; ++c) Wl[c * kPQLdW + r] = row[i][c];
           const int t = gr[i] - c0;
           if (own[i] && t >= 0 && t < nbl)
 #pragma unroll
-            for (int c = 0; c < kPQNB; ++c) xput(xt + (i64)(t * kPQNB + c) * 2, row[i][c], tag);
+            for (int c = 0; c < kPQNB; ++c) xput(xt + (i64)(t * kPQNB + c) * 2, Wl[c * kPQLdW + r], tag);
         }
       }
       __syncthreads();
@@ -417,29 +419,28 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
         if (lane == 0) jstop = jf;
       }
       __syncthreads();
-      // apply the pass to this workgroup's rows: top-block rows from the
-      // recurrence, rows below through K, rows above unchanged
-      if (tid < kPQLeafThreads) {
+      // apply the pass to this workgroup's rows, in place in Wl: top-block
+      // rows from the recurrence, rows below through K (X K on the matrix
+      // cores, a 16-row block per wave at a time: lane l supplies X(rb + l % 16,
+      // k) and K(k, l % 16) for k = 4s + l / 16, and register q of the result
+      // is row rb + 4q + l / 16, column l % 16), rows above unchanged.  A block
+      // is read and written by its wave only.
+      {
+        const int lr = lane >> 4, lc = lane & 15;
+        for (int rb = 16 * wave; rb < kPQMaxRows; rb += 16 * kPQWaves) {
+          dbl4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < kPQRpt; ++i) {
-          const int r = tid + kPQLeafThreads * i, t = gr[i] - c0;
-          double x[kPQNB];
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int kr = 4 * s4 + lr;
+            d = __builtin_amdgcn_mfma_f64_16x16x4f64(Wl[kr * kPQLdW + rb + lc], Kl[kr * kPQNB + lc], d, 0, 0, 0);
+          }
 #pragma unroll
-          for (int a = 0; a < kPQNB; ++a) x[a] = Wl[a * kPQLdW + r];
-          if (t >= nbl) {
-#pragma unroll
-            for (int cc = 0; cc < kPQNB; ++cc) {
-              double sv = 0.0;
-#pragma unroll
-              for (int a = 0; a < kPQNB; ++a) sv += x[a] * Kl[a * kPQNB + cc];
-              row[i][cc] = sv;
+          for (int qq = 0; qq < 4; ++qq) {
+            const int r = rb + 4 * qq + lr, t = r0 + r - c0;
+            if (r < R) {
+              if (t >= nbl) Wl[lc * kPQLdW + r] = d[qq];
+              else if (t >= 0) Wl[lc * kPQLdW + r] = Tops[t * kPQNB + lc];
             }
-          } else if (t >= 0) {
-#pragma unroll
-            for (int cc = 0; cc < kPQNB; ++cc) row[i][cc] = Tops[t * kPQNB + cc];
-          } else {
-#pragma unroll
-            for (int cc = 0; cc < kPQNB; ++cc) row[i][cc] = x[cc];
           }
         }
       }
@@ -456,9 +457,10 @@ __global__ __launch_bounds__(kPQThreads, 2) void panel_qr_kernel(
 #pragma unroll
       for (int c = 0; c < kPQNB; ++c) {
         const bool live = own[i] && c < nbl;
-        if (live) Ab[(i64)gr[i] + (i64)(c0 + c) * lda] = row[i][c];
+        const double v = Wl[c * kPQLdW + r];
+        if (live) Ab[(i64)gr[i] + (i64)(c0 + c) * lda] = v;
         const int dr = c0 + c;
-        Wl[c * kPQLdW + r] = live ? (gr[i] > dr ? row[i][c] : (gr[i] == dr ? 1.0 : 0.0)) : 0.0;
+        Wl[c * kPQLdW + r] = live ? (gr[i] > dr ? v : (gr[i] == dr ? 1.0 : 0.0)) : 0.0;
       }
     }
     __syncthreads();
