@@ -65,6 +65,10 @@ def test_argument_validation_without_device_work():
     assert g(b"T", b"N", 4, 4, 6, 1.0, P, 5, P, 6, 0.0, P, 4) == -8   # lda < K for op T
     assert g(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 0.0, P, 3) == -13
     assert lib.randutv_geqrf(3, 4, P, 3, P) == -2              # k > m
+    # the panel kernel's limits (at most 32768 rows in 128 slabs of at most
+    # 256 rows, at most 256 columns), refused before any device work
+    assert lib.randutv_geqrf(32769, 64, P, 32769, P) == rb.ERR_TOO_LARGE
+    assert lib.randutv_geqrf(1000, 257, P, 1000, P) == rb.ERR_TOO_LARGE
     assert lib.randutv_gesvj(-1, P, 1, P, P, P, None) == -1
     assert lib.randutv_gesvj(300, P, 300, P, P, P, None) == rb.ERR_TOO_LARGE
     assert lib.randutv_sketch(0, 0, -1, 3, P, 1) == -3
