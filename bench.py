@@ -283,10 +283,20 @@ def main():
         torch.cuda.synchronize()
         ms_hq = 1e3 * (time.perf_counter() - t0)
         f_qr = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
-        hq = {"workload": f"hqrrp {m}x{n} b={b}, FP64", "ms": round(ms_hq, 3),
-              "qr_flops": f_qr, "tflops_qr_count": round(f_qr / (ms_hq * 1e-3) / 1e12, 3)}
-        log(f"# hqrrp: {ms_hq:.2f} ms")
         del Fh, tauh, jph
+        # the unpivoted blocked Householder QR of the same matrix (the same
+        # step loop without the sketch, the pivots and the exchanges)
+        pkg.randutv_geqrf_blocked(A, b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Fq, tauq = pkg.randutv_geqrf_blocked(A, b)
+        torch.cuda.synchronize()
+        ms_qr = 1e3 * (time.perf_counter() - t0)
+        del Fq, tauq
+        hq = {"workload": f"hqrrp {m}x{n} b={b}, FP64", "ms": round(ms_hq, 3),
+              "qr_flops": f_qr, "tflops_qr_count": round(f_qr / (ms_hq * 1e-3) / 1e12, 3),
+              "unpivoted_blocked_qr_ms": round(ms_qr, 3), "ratio_to_unpivoted": round(ms_hq / ms_qr, 3)}
+        log(f"# hqrrp: {ms_hq:.2f} ms; unpivoted blocked QR of the same matrix {ms_qr:.2f} ms")
 
     roofline = None
     refused = None

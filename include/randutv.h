@@ -323,6 +323,23 @@ int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b,
                   uint64_t seed, double* tau, int64_t* jpvt);
 
 /*
+ * randutv_geqrf_blocked -- unpivoted blocked Householder QR A = Q R (LAPACK
+ * dgeqrf's operation): randutv_hqrrp's step loop without the sketch, the
+ * pivots and the exchanges (panel QR of b columns, compact-WY update of the
+ * rest).  Section 2 weighs HQRRP's cost against this factorization; the
+ * entry point is its baseline.
+ *   A   : m x n (ld lda), overwritten in the LAPACK dgeqrf layout: R on and
+ *         above the diagonal, the reflector vectors (v(0) = 1 implied) below.
+ *   tau : n reflector scalars (device).
+ * m >= n, m <= 32768.  b > n is clamped to n.  Device pointers, column-major
+ * FP64, synchronous.  Errors: -1 m, -2 n, -3 A, -4 lda, -5 b, -6 tau,
+ * RANDUTV_ERR_TOO_LARGE for min(b, n) > 256 or m > 32768,
+ * RANDUTV_ERR_NONFINITE (A untouched), RANDUTV_ERR_SYNC.
+ */
+int randutv_geqrf_blocked(int64_t m, int64_t n, double* A, int64_t lda, int64_t b,
+                          double* tau);
+
+/*
  * randutv_truncate_first_block -- the first-block truncation A_k,
  * k = min(b, n), of randutv_factor(m, n, A, lda, b, q, seed, ...) computed
  * without the rest of the factorization: A_k = Q Q^T A with Q an orthonormal

@@ -22,6 +22,7 @@ from .randutv import (  # noqa: F401
     randutv_geqrf,
     randutv_gesvj,
     randutv_hqrrp,
+    randutv_geqrf_blocked,
     randutv_kernel_stats,
     randutv_kernel_bytes,
     randutv_kernel_trace,

@@ -968,20 +968,11 @@ int randutv_truncate(int64_t m, int64_t n, int64_t k, const double* U, const dou
 // b_i steps of CPQR on Y choose the pivots; the chosen columns are exchanged
 // to the front (all m rows); Householder QR of the b_i-column panel; the
 // remaining columns of rows s..m-1 get Q22^T = H^T (compact WY).
-int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint64_t seed,
-                  double* tau, int64_t* jpvt) {
-  if (m < 0) return -1;
-  if (n < 0 || n > m) return -2;
-  if (m == 0 || n == 0) return RANDUTV_OK;
-  if (!A) return -3;
-  if (lda < std::max<int64_t>(1, m)) return -4;
-  if (b < 1) return -5;
-  if (!tau) return -7;
-  if (!jpvt) return -8;
-  if (b > n) b = n;
-  if (b > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
-  if (n > 32768) return RANDUTV_ERR_TOO_LARGE;  // the exchange plan's LDS index arrays
-  if (m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
+// The same step loop without the sketch, the pivots and the exchanges
+// (pivot == false) is the unpivoted blocked Householder QR (LAPACK dgeqrf's
+// operation), the baseline HQRRP is measured against.
+static int blocked_qr(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint64_t seed,
+                      double* tau, int64_t* jpvt, bool pivot) {
   Context& cx = ctx();
   std::lock_guard<std::mutex> lk(g_mu);
   return drained(cx, [&]() -> int {
@@ -1042,15 +1033,17 @@ int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint6
     RUTV_TRY(hipStreamSynchronize(st));
     if (flag) return RANDUTV_ERR_NONFINITE;
   }
-  RUTV_CHECK(set_iota(st, n, jpvt));
+  if (pivot) RUTV_CHECK(set_iota(st, n, jpvt));
   i64 s = 0;
   for (i64 i = 0; s < n; ++i) {
     const i64 bi = std::min(b, n - s), mi = m - s, ni = n - s;
     double* As = A + s * lda;  // columns s..n-1, all rows
-    RUTV_CHECK(sketch(st, seed, (uint64_t)i, mi, bi, G, mi));
-    RUTV_CHECK(gemm(st, x, true, false, bi, ni, mi, 1.0, G, mi, As + s, lda, 0.0, Y, bi));
-    RUTV_CHECK(cpqr_pivots(st, bi, ni, Y, bi, J, cw));
-    RUTV_CHECK(exchange_columns(st, m, bi, ni, J, As, lda, jpvt + s, ew));
+    if (pivot) {
+      RUTV_CHECK(sketch(st, seed, (uint64_t)i, mi, bi, G, mi));
+      RUTV_CHECK(gemm(st, x, true, false, bi, ni, mi, 1.0, G, mi, As + s, lda, 0.0, Y, bi));
+      RUTV_CHECK(cpqr_pivots(st, bi, ni, Y, bi, J, cw));
+      RUTV_CHECK(exchange_columns(st, m, bi, ni, J, As, lda, jpvt + s, ew));
+    }
     double* Pn = As + s;  // the panel, rows s..m-1
     RUTV_CHECK(panel_qr(st, mi, bi, Pn, lda, tau + s, pw));
     if (ni > bi) {
@@ -1068,6 +1061,36 @@ int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint6
   if (flags[0] || flags[1]) return RANDUTV_ERR_SYNC;
   return RANDUTV_OK;
   });
+}
+
+int randutv_hqrrp(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, uint64_t seed,
+                  double* tau, int64_t* jpvt) {
+  if (m < 0) return -1;
+  if (n < 0 || n > m) return -2;
+  if (m == 0 || n == 0) return RANDUTV_OK;
+  if (!A) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (b < 1) return -5;
+  if (!tau) return -7;
+  if (!jpvt) return -8;
+  if (b > n) b = n;
+  if (b > kPanelMaxCols) return RANDUTV_ERR_TOO_LARGE;
+  if (n > 32768) return RANDUTV_ERR_TOO_LARGE;  // the exchange plan's LDS index arrays
+  if (m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
+  return blocked_qr(m, n, A, lda, b, seed, tau, jpvt, true);
+}
+
+int randutv_geqrf_blocked(int64_t m, int64_t n, double* A, int64_t lda, int64_t b, double* tau) {
+  if (m < 0) return -1;
+  if (n < 0 || n > m) return -2;
+  if (m == 0 || n == 0) return RANDUTV_OK;
+  if (!A) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -4;
+  if (b < 1) return -5;
+  if (!tau) return -6;
+  if (b > n) b = n;
+  if (b > kPanelMaxCols || m > kMaxRows) return RANDUTV_ERR_TOO_LARGE;
+  return blocked_qr(m, n, A, lda, b, 0, tau, nullptr, false);
 }
 
 // Truncation jobs (forward value or reverse pass of A_k, see truncation.hip):

@@ -85,6 +85,7 @@ SIGNATURES = {
     "randutv_truncate_batched": (ctypes.c_int, [_I64, _I32, _I64, _I64, _P, _I64, _I64, _I64, _I32, _U64,
                                                 _I64, _P, _I64, _I64, _P, _I64, _I64]),
     "randutv_hqrrp": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _U64, _P, _P]),
+    "randutv_geqrf_blocked": (ctypes.c_int, [_I64, _I64, _P, _I64, _I64, _P]),
     "randutv_sketch": (ctypes.c_int, [_U64, _U64, _I64, _I64, _P, _I64]),
     "randutv_dgemm": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
     "randutv_gemm_f32": (ctypes.c_int, [_C, _C, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64]),
@@ -381,6 +382,21 @@ def randutv_hqrrp(A, b: int, seed: int = 0):
     _check("randutv_hqrrp", lib.randutv_hqrrp(m, n, _ptr(F), max(1, m), b, seed & (2**64 - 1),
                                               _ptr(tau), _ptr(jpvt)))
     return F, tau, jpvt
+
+
+def randutv_geqrf_blocked(A, b: int):
+    """Unpivoted blocked Householder QR A = Q R (HQRRP's step loop without the
+    pivots).  Returns (F, tau): F (column-major copy of A) in the dgeqrf layout."""
+    torch = _torch()
+    lib = load()
+    A, _ = as_colmajor(A)
+    m, n = A.shape
+    F = colmajor_empty(m, n, A.device)
+    F.copy_(A)
+    tau = torch.empty(n, dtype=torch.float64, device=F.device)
+    _sync()
+    _check("randutv_geqrf_blocked", lib.randutv_geqrf_blocked(m, n, _ptr(F), max(1, m), b, _ptr(tau)))
+    return F, tau
 
 
 def randutv_truncate_first_block(A, b: int, q: int, seed: int = 0):

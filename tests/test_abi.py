@@ -69,6 +69,16 @@ def test_argument_validation_without_device_work():
     # 256 rows, at most 256 columns), refused before any device work
     assert lib.randutv_geqrf(32769, 64, P, 32769, P) == rb.ERR_TOO_LARGE
     assert lib.randutv_geqrf(1000, 257, P, 1000, P) == rb.ERR_TOO_LARGE
+    gb = lib.randutv_geqrf_blocked
+    assert gb(-1, 3, P, 5, 2, P) == -1
+    assert gb(4, 5, P, 4, 2, P) == -2                          # n > m
+    assert gb(5, 3, None, 5, 2, P) == -3
+    assert gb(5, 3, P, 4, 2, P) == -4
+    assert gb(5, 3, P, 5, 0, P) == -5
+    assert gb(5, 3, P, 5, 2, None) == -6
+    assert gb(0, 0, None, 1, 1, None) == 0                     # empty: no-op
+    assert gb(1000, 300, P, 1000, 300, P) == rb.ERR_TOO_LARGE  # min(b, n) > 256
+    assert gb(40000, 64, P, 40000, 64, P) == rb.ERR_TOO_LARGE  # m > 32768
     assert lib.randutv_gesvj(-1, P, 1, P, P, P, None) == -1
     assert lib.randutv_gesvj(300, P, 300, P, P, P, None) == rb.ERR_TOO_LARGE
     assert lib.randutv_sketch(0, 0, -1, 3, P, 1) == -3
