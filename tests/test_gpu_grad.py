@@ -278,3 +278,33 @@ def test_truncate_batched_equals_single_calls(k):
         r1 = (pkg.randutv_truncate_grad(Xd, b, q, 3, to_dev(G[t])) if k == b
               else pkg.randutv_truncate_grad_k(Xd, b, q, 3, k, to_dev(G[t])))
         assert torch.equal(fwd[t], f1) and torch.equal(rev[t], r1), t
+
+
+@pytest.mark.parametrize("k", [128, 64])
+def test_grad_at_the_benchmark_size(k):
+    """The batched truncation workload's matrix size: 2048 x 2048, b = 128,
+    q = 2, s_i = 0.98^i; k = b (the projector form) and k < b, against the
+    oracle with the bounds of the smaller cases above."""
+    m = n = 2048
+    b, q = 128, 2
+    A = make_matrix("exp98", m, n, seed=11)
+    Gbar = np.random.default_rng(k).standard_normal((m, n))
+    if k == b:
+        ref = tg.first_block_truncation_grad(A, b, q, 5, Gbar)
+        got = to_host(pkg.randutv_truncate_grad(to_dev(A), b, q, 5, to_dev(Gbar)))
+        M = tg.first_block_sketch(A, b, 5)
+        for _ in range(q + 1):
+            M = A @ (A.T @ M)
+        tol = max(1e-12, 100 * 2.0 ** -52 * np.linalg.cond(M))
+    else:
+        ref = tg.first_block_truncation_k_grad(A, b, q, 5, k, Gbar)
+        got = to_host(pkg.randutv_truncate_grad_k(to_dev(A), b, q, 5, k, to_dev(Gbar)))
+        Y = A.T @ tg.first_block_sketch(A, b, 5)
+        for _ in range(q):
+            Y = A.T @ (A @ Y)
+        d = np.linalg.svd(A @ np.linalg.qr(Y)[0], compute_uv=False)
+        gap = d[0] ** 2 / (d[k - 1] ** 2 - d[k] ** 2)
+        tol = max(1e-12, 100 * 2.0 ** -52 * np.linalg.cond(Y) * gap)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"truncation grad 2048^2 b={b} q={q} k={k}: max rel err {err:.2e} (bound {tol:.1e})")
+    assert err <= tol

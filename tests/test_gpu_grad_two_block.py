@@ -154,3 +154,20 @@ def test_two_block_truncation_autograd():
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
     with pytest.raises(ValueError):
         pkg.truncation(Ad, b, q, 8, 2 * b + 1)
+
+
+def test_two_block_grad_at_the_benchmark_size():
+    """2048 x 2048, b = 128, q = 2, s_i = 0.98^i (the batched truncation
+    workload's size) at k = 200, between b and 2b, against the oracle, with
+    the tolerance from the oracle's own last-bit sensitivity as above."""
+    m = n = 2048
+    b, q, k = 128, 2, 200
+    A = make_matrix("exp98", m, n, seed=13)
+    Gbar = np.random.default_rng(17).standard_normal((m, n))
+    ref = tg.two_block_truncation_grad(A, b, q, 5, k, Gbar)
+    ref_p = tg.two_block_truncation_grad(_perturbed(A), b, q, 5, k, Gbar)
+    tol, spread = _tol(ref, ref_p)
+    got = to_host(pkg.randutv_truncate_grad_k(to_dev(A), b, q, 5, k, to_dev(Gbar)))
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"two-block grad 2048^2 k={k}: rel err {err:.2e}, oracle spread {spread:.1e}")
+    assert err <= tol
